@@ -1,0 +1,116 @@
+"""Canonical Box-Muller: two 32-bit words -> one pair of unit normals (test infrastructure only).
+
+The paper asks only that each Fourier mode be a complex normal of the right variance
+(Sec. II D 1). To make the CPU and GPU noise bit-identical, the transform is fixed here as
+a sequence of IEEE-754 binary64 additions, subtractions and multiplications (each rounded
+on its own, never fused), exact scalings by powers of two, and integer/bit operations. No
+library log, sin, cos, sqrt or division is used, because those differ between platforms.
+
+Given words a, b (uint32):
+
+    u1 = (a + 1) 2^-32 in (0, 1],  u2 = b 2^-32 in [0, 1)
+    R  = sqrt(-2 ln u1),  (g_re, g_im) = (R cos 2 pi u2, R sin 2 pi u2)
+
+(Box & Muller, Ann. Math. Stat. 29 (1958) 610.) The three elementary functions are
+evaluated as follows.
+
+ln u1: write a + 1 = m 2^e with m in [1/sqrt2, sqrt2). Then ln u1 = (e - 32) ln 2 + ln m,
+with ln 2 split into a short head (exact products) and a tail. ln m = 2 artanh(s),
+s = (m - 1)/(m + 1), |s| <= 0.1716, summed as 2 s sum_{k=0..10} s^{2k}/(2k + 1) in Horner
+form (truncation < 2.5e-17 relative). 1/(m + 1) comes from five Newton steps
+y <- y (2 - d y) starting at y = 1/2.
+
+sqrt x: Newton's iteration for 1/sqrt(x), y <- y (3/2 - (x/2) y^2), four steps from the
+integer-shift seed 0x5FE6EB50C7B537A9 - (bits(x) >> 1) (relative error < 3.5 %), then
+sqrt x = x y. x = 0 (a = 2^32 - 1) gives R = 0.
+
+cos, sin of 2 pi u2: the top two bits of b give the quadrant; the remaining 30 bits are
+folded to an angle t = rho (2 pi 2^-32) in [0, pi/4], rho <= 2^29 an integer, with sin and
+cos swapped when folded. sin t = t sum_{k=0..8} (-1)^k t^{2k}/(2k+1)! and
+cos t = sum_{k=0..9} (-1)^k t^{2k}/(2k)! (truncation < 1e-16).
+"""
+import numpy as np
+
+F64 = np.float64
+
+LN2_HI = float.fromhex("0x1.62e42fefa3000p-1")   # ln 2 with the 12 low mantissa bits cleared
+LN2_LO = float.fromhex("0x1.3de6af278ece6p-42")  # ln 2 - LN2_HI, rounded
+SQRT2 = float.fromhex("0x1.6a09e667f3bcdp+0")
+TWO_PI_2M32 = float.fromhex("0x1.921fb54442d18p-30")  # 2 pi / 2^32, rounded
+RSQRT_MAGIC = np.uint64(0x5FE6EB50C7B537A9)
+
+# Series coefficients; every factorial up to 18! is exact in binary64, so each is the
+# correctly rounded quotient.
+_ATANH_C = [1.0 / (2 * k + 1) for k in range(11)]
+_SIN_C = [(-1.0) ** k / float(np.prod(np.arange(1, 2 * k + 2, dtype=np.float64))) for k in range(9)]
+_COS_C = [(-1.0) ** k / float(np.prod(np.arange(1, 2 * k + 1, dtype=np.float64))) for k in range(10)]
+
+
+def canonical_log_u1(a):
+    """ln((a + 1) 2^-32) for uint32 words ``a`` (array), by the fixed operation sequence."""
+    a = np.asarray(a, dtype=np.uint64)
+    v = a + np.uint64(1)                                # 1 .. 2^32, exact
+    vf = v.astype(F64)
+    mant, ex = np.frexp(vf)                             # vf = mant 2^ex, mant in [1/2, 1), exact
+    e0 = ex.astype(np.int64) - 1
+    m = mant * 2.0                                      # [1, 2), exact
+    big = m >= SQRT2
+    m = np.where(big, m * 0.5, m)
+    e = np.where(big, e0 + 1, e0) - 32                  # in [-32, 0]
+    d = m + 1.0
+    y = np.full_like(d, 0.5)
+    for _ in range(5):
+        y = y * (2.0 - d * y)
+    s = (m - 1.0) * y
+    s2 = s * s
+    p = np.full_like(s, _ATANH_C[10])
+    for k in range(9, -1, -1):
+        p = p * s2 + _ATANH_C[k]
+    lnm = (s + s) * p
+    ef = e.astype(F64)
+    return ef * LN2_HI + (ef * LN2_LO + lnm)
+
+
+def canonical_sqrt(x):
+    """sqrt(x) for x >= 0 (array) by the fixed Newton sequence; sqrt(0) = 0."""
+    x = np.asarray(x, dtype=F64)
+    bits = x.view(np.uint64)
+    y = (RSQRT_MAGIC - (bits >> np.uint64(1))).view(F64)
+    hx = 0.5 * x
+    for _ in range(4):
+        y = y * (1.5 - hx * (y * y))
+    r = x * y
+    return np.where(x == 0.0, 0.0, r)
+
+
+def canonical_sincos_2pi(b):
+    """(sin, cos) of 2 pi b 2^-32 for uint32 words ``b`` (array), fixed sequence."""
+    b = np.asarray(b, dtype=np.uint64)
+    q = b >> np.uint64(30)
+    r = b & np.uint64(0x3FFFFFFF)
+    swap = r >= np.uint64(1 << 29)
+    rho = np.where(swap, np.uint64(1 << 30) - r, r)
+    t = rho.astype(F64) * TWO_PI_2M32
+    t2 = t * t
+    ps = np.full_like(t, _SIN_C[8])
+    for k in range(7, -1, -1):
+        ps = ps * t2 + _SIN_C[k]
+    st = t * ps
+    pc = np.full_like(t, _COS_C[9])
+    for k in range(8, -1, -1):
+        pc = pc * t2 + _COS_C[k]
+    ct = pc
+    s_in = np.where(swap, ct, st)      # sine of the in-quadrant angle
+    c_in = np.where(swap, st, ct)
+    sin = np.select([q == 0, q == 1, q == 2], [s_in, c_in, -s_in], -c_in)
+    cos = np.select([q == 0, q == 1, q == 2], [c_in, -s_in, -c_in], s_in)
+    return sin, cos
+
+
+def box_muller(a, b):
+    """Unit normal pair (g_re, g_im) from word arrays a (radius) and b (angle)."""
+    lnu = canonical_log_u1(a)
+    x = -(lnu + lnu)
+    rad = canonical_sqrt(x)
+    sin, cos = canonical_sincos_2pi(b)
+    return rad * cos, rad * sin

@@ -1,0 +1,88 @@
+"""Pins of the canonical Box-Muller transform against library functions and statistics."""
+import numpy as np
+import pytest
+import scipy.stats
+
+from oracle import normal
+
+RNG = np.random.default_rng(12345)
+WORDS = RNG.integers(0, 2**32, size=400_000, dtype=np.uint64)
+EDGE = np.array([0, 1, 2, 3, 2**29 - 1, 2**29, 2**29 + 1, 2**30 - 1, 2**30, 2**30 + 1,
+                 2**31 - 1, 2**31, 3 * 2**30, 2**32 - 2, 2**32 - 1], dtype=np.uint64)
+
+
+def _ulp_err(x, ref):
+    return np.abs(x - ref) / np.spacing(np.abs(ref))
+
+
+def test_log_matches_library():
+    a = np.concatenate([WORDS, EDGE])
+    got = normal.canonical_log_u1(a)
+    ref = np.log((a + np.uint64(1)).astype(np.float64) * 2.0**-32)
+    nz = ref != 0
+    assert np.all(got[~nz] == 0.0)
+    assert np.max(_ulp_err(got[nz], ref[nz])) <= 4
+
+
+def test_log_exact_powers_of_two():
+    # a + 1 = 2^j gives ln u1 = (j - 32) ln 2: the head/tail split must reproduce it.
+    for j in range(0, 33):
+        a = np.array([2**j - 1], dtype=np.uint64)
+        got = float(normal.canonical_log_u1(a)[0])
+        assert abs(got - (j - 32) * np.log(2.0)) <= 2 * np.spacing(abs((j - 32) * np.log(2.0)) + 1e-300)
+
+
+def test_sqrt_matches_library():
+    x = np.concatenate([RNG.uniform(0, 45, 200_000), 10.0 ** RNG.uniform(-10, 1.7, 50_000), [1.0, 4.0, 2.0]])
+    got = normal.canonical_sqrt(x)
+    assert np.max(_ulp_err(got, np.sqrt(x))) <= 4
+    assert normal.canonical_sqrt(np.array([0.0, -0.0]))[0] == 0.0
+
+
+def test_sincos_matches_library():
+    b = np.concatenate([WORDS, EDGE])
+    s, c = normal.canonical_sincos_2pi(b)
+    th = 2.0 * np.pi * (b.astype(np.float64) * 2.0**-32)
+    # |error| limited by the rounding of the reference angle (< 8e-16) plus a few ulp.
+    assert np.max(np.abs(s - np.sin(th))) < 1.5e-15
+    assert np.max(np.abs(c - np.cos(th))) < 1.5e-15
+    assert np.max(np.abs(s * s + c * c - 1.0)) < 1e-15
+
+
+def test_sincos_exact_quadrants():
+    s, c = normal.canonical_sincos_2pi(np.array([0, 2**30, 2**31, 3 * 2**30], dtype=np.uint64))
+    assert list(s) == [0.0, 1.0, 0.0, -1.0]
+    assert list(np.abs(c)) == [1.0, 0.0, 1.0, 0.0]
+    assert c[0] == 1.0 and c[2] == -1.0
+
+
+def test_box_muller_radius_zero():
+    g_re, g_im = normal.box_muller(np.array([2**32 - 1], dtype=np.uint64), np.array([12345], dtype=np.uint64))
+    assert g_re[0] == 0.0 and g_im[0] == 0.0
+
+
+def test_normal_distribution():
+    a = WORDS
+    b = RNG.integers(0, 2**32, size=a.size, dtype=np.uint64)
+    g_re, g_im = normal.box_muller(a, b)
+    n = a.size
+    for g in (g_re, g_im):
+        assert abs(g.mean()) < 5 / np.sqrt(n)
+        assert abs(g.var() - 1) < 5 * np.sqrt(2 / n)
+        assert abs(scipy.stats.skew(g)) < 5 * np.sqrt(6 / n)
+        assert abs(scipy.stats.kurtosis(g)) < 5 * np.sqrt(24 / n)
+        assert scipy.stats.kstest(g, "norm").pvalue > 1e-4
+    assert abs(np.corrcoef(g_re, g_im)[0, 1]) < 5 / np.sqrt(n)
+
+
+def test_box_muller_against_library_form():
+    a = WORDS[:100_000]
+    b = WORDS[100_000:200_000]
+    g_re, g_im = normal.box_muller(a, b)
+    u1 = (a + np.uint64(1)).astype(np.float64) * 2.0**-32
+    u2 = b.astype(np.float64) * 2.0**-32
+    R = np.sqrt(-2.0 * np.log(u1))
+    ref_re = R * np.cos(2 * np.pi * u2)
+    ref_im = R * np.sin(2 * np.pi * u2)
+    assert np.max(np.abs(g_re - ref_re)) < 2e-14
+    assert np.max(np.abs(g_im - ref_im)) < 2e-14
