@@ -1,0 +1,151 @@
+/*
+ * cmbx -- partial-sky CMB maps from a periodic 3-D box (MI355X / gfx950).
+ *
+ * Method: Giner Mascarell & Bunn, "Simulating Partial Sky Cosmic Microwave Background
+ * Maps with 3D Fast Fourier Transforms" (arXiv:2507.15703), Sec. II D 1 (the 3-D Fourier
+ * method): fill the box's Fourier modes with complex normals of variance P_box(|k|),
+ * inverse-FFT to a real field, and interpolate the field at the sky pixels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Box: N^3 nodes, side L, node j at j L / N, periodic. N must be even, 8 <= N <= 1024,
+ *   and of the form 2^a 3^b with N/2 also of that form.
+ * - Observer at the box centre c = (L/2, L/2, L/2); pixel with unit direction n sits at
+ *   c + r n. In grid units p = (r n + L/2) (N / L), evaluated in FP64; the stencil is
+ *   chosen by floor(p) and node indices wrap modulo N.
+ * - Spectrum normalisation: the caller gives P_inf(k), the infinite-space spectrum with
+ *   xi(r) = int d^3k P_inf e^{i k.r} (Sec. II A, eq. xiinfpinf); the box uses
+ *   P_box = P_inf (2 pi / L)^3 (Sec. II C, eq. finalpbox with M = N) and drops k = 0.
+ * - Noise: mode (ix, iy, iz) of the half grid (iz = 0 .. N/2) is driven by Philox4x32-10
+ *   with key = (seed & 0xffffffff, seed >> 32) and counter (iz >> 1, iy, ix, 0), words
+ *   (x0, x1) for even iz and (x2, x3) for odd iz, through a fixed-operation FP64
+ *   Box-Muller transform; generic modes get sqrt(P_box/2) (g_re + i g_im), the planes
+ *   iz = 0, N/2 are made Hermitian, and the 8 self-conjugate modes are sqrt(P_box) g_re.
+ *   Realisation b of a batch uses seed + b.
+ * - Inverse DFT: unnormalised, + sign: T(j) = sum_f T(f) exp(+2 pi i f.j / N).
+ * - All device pointers are HIP device memory owned by the caller unless stated. Calls
+ *   that launch work are asynchronous on the plan's stream; the caller synchronises.
+ * - Every function returns CMBX_OK (0) or a negative error code and never throws;
+ *   cmbx_last_error() gives the message of the calling thread's last failure.
+ */
+#ifndef CMBX_H
+#define CMBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CMBX_OK            0
+#define CMBX_EINVAL       -1  /* an argument is out of range or NULL */
+#define CMBX_EUNSUPPORTED -2  /* a valid request this build does not implement (e.g. N = 2^a 3^b 5^c) */
+#define CMBX_ENOMEM       -3  /* a device or host allocation failed */
+#define CMBX_EHIP         -4  /* a HIP runtime call failed (no device, launch error) */
+#define CMBX_ESTATE       -5  /* call out of order (e.g. simulate before a spectrum is set) */
+
+/* working precision of a plan */
+#define CMBX_F32 1
+#define CMBX_F64 2
+
+/* interpolants (option CMBX_OPT_INTERP) */
+#define CMBX_TRILINEAR 1 /* 2 nodes per axis, K(x) = 1 - |x| */
+#define CMBX_TRICUBIC  2 /* 4 nodes per axis, Keys cubic convolution with a = -1/2 */
+
+/* plan options for cmbx_plan_set */
+#define CMBX_OPT_INTERP   1 /* CMBX_TRILINEAR (default) or CMBX_TRICUBIC */
+#define CMBX_OPT_STREAM   2 /* hipStream_t cast to int64_t (0 = the null stream); -1 = the plan's own stream (default) */
+#define CMBX_OPT_TILE_XY  3 /* columns per workgroup of the x/y passes; 0 = tuned default */
+#define CMBX_OPT_LINES_Z  4 /* lines per workgroup of the z pass; 0 = tuned default */
+
+typedef struct cmbx_plan cmbx_plan;
+typedef struct cmbx_ensemble cmbx_ensemble;
+
+/*
+ * Create a plan for a batch of `batch` realisations of an N^3 box of side L in precision
+ * `dtype`. The plan owns its device workspace (batch x N^3 reals: the field, computed in
+ * place), the twiddle table and the weight table, on the device current at the call.
+ * Errors: CMBX_EINVAL (out == NULL, N odd or < 8 or > 1024, L <= 0 or not finite,
+ * batch < 1, unknown dtype), CMBX_EUNSUPPORTED (N not 2^a 3^b), CMBX_EHIP (no device),
+ * CMBX_ENOMEM. On error *out is set to NULL.
+ */
+int cmbx_plan_box(int N, double L, int dtype, int batch, cmbx_plan** out);
+
+/* Release a plan and its device memory (waits for its stream). NULL is accepted. */
+int cmbx_plan_destroy(cmbx_plan* plan);
+
+/* Set a plan option (CMBX_OPT_*). CMBX_EINVAL for an unknown key or a bad value. */
+int cmbx_plan_set(cmbx_plan* plan, int key, int64_t value);
+
+/* Read back a plan's geometry: any output pointer may be NULL. */
+int cmbx_plan_info(const cmbx_plan* plan, int* N, double* L, int* dtype, int* batch,
+                   void** field);
+
+/*
+ * Set the plan's spectrum from a host table of P_inf(k) (Sec. II B-C). k (strictly
+ * increasing, >= 0) and P_inf (>= 0, finite) are host FP64 arrays of length n >= 2,
+ * copied; P_inf is linear in k between nodes and zero outside [k[0], k[n-1]] (the
+ * cut-off beyond which the spectrum is taken to vanish, Sec. II B). The per-|k|^2 weight
+ * table sqrt(P_box/2) is formed in FP64 on the host, rounded once to the plan's
+ * precision and uploaded. Errors: CMBX_EINVAL, CMBX_ENOMEM, CMBX_EHIP.
+ */
+int cmbx_spectrum_table(cmbx_plan* plan, const double* k, const double* P_inf, int64_t n);
+
+/*
+ * Simulate the plan's batch and sample it on a sky patch (Sec. II D 1).
+ *   seed   realisation b uses seed + b
+ *   r      shell radius, 0 < r < L/2
+ *   dirs   device FP64 [n_pix][3] unit vectors (caller-owned)
+ *   out    device array [batch][n_pix] of the plan's precision (caller-owned)
+ * The field of realisation b is left in the plan's workspace (cmbx_plan_info).
+ * Errors: CMBX_ESTATE (no spectrum yet), CMBX_EINVAL (r out of range, n_pix < 1, NULL
+ * pointer), CMBX_EHIP (launch failure).
+ */
+int cmbx_simulate_patch(cmbx_plan* plan, uint64_t seed, double r, const double* dirs,
+                        int64_t n_pix, void* out);
+
+/* ---- ensembles: many jobs of mixed box sizes per launch sequence ---- */
+
+typedef struct cmbx_job {
+  cmbx_plan* plan;     /* plan of this job (its batch is simulated; its workspace is used) */
+  uint64_t seed;       /* as cmbx_simulate_patch */
+  double r;
+  const double* dirs;  /* device [n_pix][3] */
+  int64_t n_pix;
+  void* out;           /* device [batch][n_pix] */
+} cmbx_job;
+
+/*
+ * Capture the jobs' kernel chains into one HIP graph. Jobs that share a plan run one after
+ * another; jobs of different plans are independent branches. Buffers stay caller-owned
+ * and must outlive the ensemble. Errors: as cmbx_simulate_patch for each job, CMBX_EINVAL
+ * for n_jobs < 1.
+ */
+int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, cmbx_ensemble** out);
+/* Launch the captured graph on `stream` (a hipStream_t; NULL = the default stream). */
+int cmbx_ensemble_launch(cmbx_ensemble* ens, void* stream);
+int cmbx_ensemble_destroy(cmbx_ensemble* ens);
+
+/* ---- stage-by-stage entry points (tests and profiling) ---- */
+
+/* Write the unpacked weighted half grid of realisation `seed`: device complex array
+ * [N][N][N/2+1] of the plan's precision (re, im interleaved). */
+int cmbx_debug_noise(cmbx_plan* plan, uint64_t seed, void* halfgrid);
+/* Run noise + inverse FFT for one realisation into `field`: device real [N][N][N]. */
+int cmbx_debug_field(cmbx_plan* plan, uint64_t seed, void* field);
+/* Interpolate a caller-given device field [N][N][N] (plan precision) at the pixels. */
+int cmbx_debug_gather(cmbx_plan* plan, const void* field, double r, const double* dirs,
+                      int64_t n_pix, void* out);
+
+/* Message of the calling thread's last failed call ("" if none). Valid until its next call. */
+const char* cmbx_last_error(void);
+/* Library version string. */
+const char* cmbx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMBX_H */

@@ -1,0 +1,302 @@
+"""Python binding of the C ABI in ``include/cmbx.h`` (ctypes; argument marshalling only).
+
+Every call goes to ``_lib/libcmbx.so``; all computation happens in its HIP kernels. Device
+buffers are passed as torch CUDA tensors (or raw integer addresses); torch supplies device
+memory and streams only. If the library is missing, loading raises: there is no fallback.
+
+The function names follow the C ABI without the ``cmbx_`` prefix; ``Plan`` and
+``Ensemble`` are small owners that release their handles.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libcmbx.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
+F32, F64 = 1, 2
+TRILINEAR, TRICUBIC = 1, 2
+OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z = 1, 2, 3, 4
+
+_DTYPES = {"f32": F32, "float32": F32, F32: F32, "f64": F64, "float64": F64, F64: F64}
+_INTERPS = {"trilinear": TRILINEAR, "tricubic": TRICUBIC, TRILINEAR: TRILINEAR, TRICUBIC: TRICUBIC}
+
+_lib = None
+
+
+class CmbxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cmbx error {code}: {msg}")
+        self.code = code
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("r", ctypes.c_double),
+                ("dirs", ctypes.c_void_p), ("n_pix", ctypes.c_int64), ("out", ctypes.c_void_p)]
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_2507_15703_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D, U64, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64
+        sig = {
+            "cmbx_plan_box": (I, [I, D, I, I, ctypes.POINTER(P)]),
+            "cmbx_plan_destroy": (I, [P]),
+            "cmbx_plan_set": (I, [P, I, I64]),
+            "cmbx_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(I),
+                                   ctypes.POINTER(P)]),
+            "cmbx_spectrum_table": (I, [P, P, P, I64]),
+            "cmbx_simulate_patch": (I, [P, U64, D, P, I64, P]),
+            "cmbx_ensemble_create": (I, [ctypes.POINTER(_Job), I, ctypes.POINTER(P)]),
+            "cmbx_ensemble_launch": (I, [P, P]),
+            "cmbx_ensemble_destroy": (I, [P]),
+            "cmbx_debug_noise": (I, [P, U64, P]),
+            "cmbx_debug_field": (I, [P, U64, P]),
+            "cmbx_debug_gather": (I, [P, P, D, P, I64, P]),
+            "cmbx_last_error": (ctypes.c_char_p, []),
+            "cmbx_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise CmbxError(rc, lib().cmbx_last_error().decode())
+    return rc
+
+
+def last_error():
+    return lib().cmbx_last_error().decode()
+
+
+def version():
+    return lib().cmbx_version().decode()
+
+
+def _ptr(x, nbytes=None, dtype=None, what="buffer"):
+    """Device address of a torch CUDA tensor (checked) or a raw integer address."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if not x.is_cuda:
+        raise ValueError(f"{what} must be a CUDA tensor")
+    if not x.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and x.dtype != dtype:
+        raise ValueError(f"{what} must have dtype {dtype}, got {x.dtype}")
+    if nbytes is not None and x.numel() * x.element_size() < nbytes:
+        raise ValueError(f"{what} holds {x.numel() * x.element_size()} bytes, needs {nbytes}")
+    return x.data_ptr()
+
+
+# ------------------------------------------------------------------ raw ABI mirrors
+def plan_box(N, L, dtype, batch):
+    h = ctypes.c_void_p()
+    _check(lib().cmbx_plan_box(int(N), float(L), _DTYPES[dtype], int(batch), ctypes.byref(h)))
+    return h.value
+
+
+def plan_destroy(h):
+    return _check(lib().cmbx_plan_destroy(h))
+
+
+def plan_set(h, key, value):
+    return _check(lib().cmbx_plan_set(h, int(key), int(value)))
+
+
+def spectrum_table(h, k, p_inf):
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    p = np.ascontiguousarray(p_inf, dtype=np.float64)
+    if k.shape != p.shape or k.ndim != 1:
+        raise ValueError("k and P_inf must be 1-D arrays of equal length")
+    return _check(lib().cmbx_spectrum_table(h, k.ctypes.data, p.ctypes.data, k.size))
+
+
+def simulate_patch(h, seed, r, dirs, n_pix, out):
+    return _check(lib().cmbx_simulate_patch(h, int(seed), float(r), dirs, int(n_pix), out))
+
+
+def debug_noise(h, seed, halfgrid):
+    return _check(lib().cmbx_debug_noise(h, int(seed), halfgrid))
+
+
+def debug_field(h, seed, field):
+    return _check(lib().cmbx_debug_field(h, int(seed), field))
+
+
+def debug_gather(h, field, r, dirs, n_pix, out):
+    return _check(lib().cmbx_debug_gather(h, field, float(r), dirs, int(n_pix), out))
+
+
+# ------------------------------------------------------------------ owners
+class Plan:
+    """A box plan (N^3, side L, precision, batch) bound to a stream.
+
+    ``stream``: a torch.cuda.Stream, a raw hipStream_t integer, or None for torch's
+    current stream (so the plan's work is ordered with torch's allocations).
+    """
+
+    def __init__(self, N, L=1.0, dtype="f32", batch=1, interp="trilinear", stream=None):
+        import torch
+        self.N, self.L, self.batch = int(N), float(L), int(batch)
+        self.dtype = _DTYPES[dtype]
+        self.torch_dtype = torch.float32 if self.dtype == F32 else torch.float64
+        self.handle = plan_box(N, L, self.dtype, batch)
+        try:
+            self.set_interp(interp)
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            self.stream = stream
+            plan_set(self.handle, OPT_STREAM, stream if isinstance(stream, int) else stream.cuda_stream)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "handle", None):
+            plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_interp(self, interp):
+        self.interp = _INTERPS[interp]
+        plan_set(self.handle, OPT_INTERP, self.interp)
+
+    def set_tiles(self, tile_xy=0, lines_z=0):
+        plan_set(self.handle, OPT_TILE_XY, tile_xy)
+        plan_set(self.handle, OPT_LINES_Z, lines_z)
+
+    def spectrum_table(self, k, p_inf):
+        spectrum_table(self.handle, k, p_inf)
+
+    @property
+    def real_size(self):
+        return 4 if self.dtype == F32 else 8
+
+    def field_ptr(self, b=0):
+        f = ctypes.c_void_p()
+        _check(lib().cmbx_plan_info(self.handle, None, None, None, None, ctypes.byref(f)))
+        return f.value + b * self.N**3 * self.real_size
+
+    def field(self, b=0):
+        """A copy of realisation b's field from the plan's workspace, [N][N][N] tensor."""
+        import torch
+        out = torch.empty((self.N, self.N, self.N), dtype=self.torch_dtype, device="cuda")
+        _memcpy_d2d(out.data_ptr(), self.field_ptr(b), self.N**3 * self.real_size, self.stream)
+        return out
+
+    def _check_dirs_out(self, dirs, out, n_pix=None):
+        import torch
+        if n_pix is None:
+            n_pix = dirs.shape[0] if not isinstance(dirs, int) else None
+        if n_pix is None:
+            raise ValueError("n_pix is required with raw pointers")
+        if not isinstance(dirs, int) and (dirs.dim() != 2 or dirs.shape[1] != 3 or dirs.shape[0] < n_pix):
+            raise ValueError("dirs must be a [n_pix, 3] float64 CUDA tensor")
+        d = _ptr(dirs, n_pix * 24, torch.float64, "dirs")
+        o = _ptr(out, self.batch * n_pix * self.real_size, self.torch_dtype, "out")
+        return d, o, n_pix
+
+    def simulate_patch(self, seed, r, dirs, out=None, n_pix=None):
+        """Maps [batch, n_pix] of realisations seed .. seed + batch - 1."""
+        import torch
+        if out is None:
+            n = dirs.shape[0]
+            out = torch.empty((self.batch, n), dtype=self.torch_dtype, device="cuda")
+        d, o, n_pix = self._check_dirs_out(dirs, out, n_pix)
+        simulate_patch(self.handle, seed, r, d, n_pix, o)
+        return out
+
+    def debug_noise(self, seed):
+        import torch
+        ctype = torch.complex64 if self.dtype == F32 else torch.complex128
+        h = torch.empty((self.N, self.N, self.N // 2 + 1), dtype=ctype, device="cuda")
+        debug_noise(self.handle, seed, h.data_ptr())
+        return h
+
+    def debug_field(self, seed):
+        import torch
+        f = torch.empty((self.N, self.N, self.N), dtype=self.torch_dtype, device="cuda")
+        debug_field(self.handle, seed, f.data_ptr())
+        return f
+
+    def debug_gather(self, field, r, dirs, out=None):
+        import torch
+        n = dirs.shape[0]
+        if out is None:
+            out = torch.empty((n,), dtype=self.torch_dtype, device="cuda")
+        fp = _ptr(field, self.N**3 * self.real_size, self.torch_dtype, "field")
+        d = _ptr(dirs, n * 24, torch.float64, "dirs")
+        o = _ptr(out, n * self.real_size, self.torch_dtype, "out")
+        debug_gather(self.handle, fp, r, d, n, o)
+        return out
+
+
+def _memcpy_d2d(dst, src, nbytes, stream):
+    hip = _hip()
+    s = stream if isinstance(stream, int) else stream.cuda_stream
+    rc = hip.hipMemcpyAsync(ctypes.c_void_p(dst), ctypes.c_void_p(src), ctypes.c_size_t(nbytes), 3, ctypes.c_void_p(s))
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
+
+_hip_rt = None
+
+
+def _hip():
+    global _hip_rt
+    if _hip_rt is None:
+        _hip_rt = ctypes.CDLL("libamdhip64.so")
+        _hip_rt.hipMemcpyAsync.restype = ctypes.c_int
+    return _hip_rt
+
+
+class Ensemble:
+    """Jobs captured into one HIP graph (cmbx_ensemble_create)."""
+
+    def __init__(self, jobs):
+        """jobs: list of dict(plan=Plan, seed, r, dirs=tensor, out=tensor)."""
+        arr = (_Job * len(jobs))()
+        self._keep = []
+        for i, j in enumerate(jobs):
+            p = j["plan"]
+            d, o, n_pix = p._check_dirs_out(j["dirs"], j["out"])
+            arr[i] = _Job(p.handle, int(j["seed"]), float(j["r"]), d, n_pix, o)
+            self._keep.append(j)
+        h = ctypes.c_void_p()
+        _check(lib().cmbx_ensemble_create(arr, len(jobs), ctypes.byref(h)))
+        self.handle = h.value
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream if isinstance(stream, int) else stream.cuda_stream
+        _check(lib().cmbx_ensemble_launch(self.handle, s))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().cmbx_ensemble_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,463 @@
+// C ABI of the box simulator: argument checking, plans, host FP64 tables, and the launch
+// sequences of the hot path (see include/cmbx.h for the contract of every entry point).
+#include "../../include/cmbx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+struct cmbx_plan {
+  int N = 0;
+  double L = 0;
+  int dtype = 0;
+  int batch = 0;
+  int device = 0;
+  int interp = CMBX_TRILINEAR;
+  int tile_xy = 0;  // 0 = compiled default
+  int lines_z = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  void* field = nullptr;   // batch x N^3 reals
+  void* tw = nullptr;      // N complex roots of unity
+  void* wtab = nullptr;    // 3 (N/2)^2 + 1 half weights, then 4 full weights
+  bool has_spectrum = false;
+  size_t real_size() const { return dtype == CMBX_F32 ? 4 : 8; }
+  size_t field_bytes() const { return (size_t)N * N * N * real_size(); }
+  int64_t wtab_len() const { return 3ll * (N / 2) * (N / 2) + 1 + 4; }
+};
+
+struct cmbx_ensemble {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return CMBX_OK;
+}
+
+#define HIP_TRY(call)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail(CMBX_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_2a3b(int n) {
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+// exp(2 pi i m / N) in extended precision, rounded to double, for m = 0 .. N-1
+void roots_of_unity(int N, std::vector<double>& re, std::vector<double>& im) {
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  re.resize(N);
+  im.resize(N);
+  for (int m = 0; m < N; ++m) {
+    // reduce to the first octant for accuracy, exact at multiples of N/8
+    const long double ang = two_pi * (long double)m / (long double)N;
+    re[m] = (double)cosl(ang);
+    im[m] = (double)sinl(ang);
+    if (4 * m % N == 0) {
+      const int q = 4 * m / N;
+      re[m] = q == 0 ? 1.0 : q == 2 ? -1.0 : 0.0;
+      im[m] = q == 1 ? 1.0 : q == 3 ? -1.0 : 0.0;
+    }
+  }
+}
+
+// P_inf at k: linear between nodes, zero outside [k[0], k[n-1]] (same operations and
+// order as the specification: i = last node with k_i <= k, clamped to n-2).
+double interp_p(const double* kt, const double* pt, int64_t n, double k) {
+  if (!(k >= kt[0] && k <= kt[n - 1])) return 0.0;
+  int64_t i = (int64_t)(std::upper_bound(kt, kt + n, k) - kt) - 1;
+  i = std::min<int64_t>(std::max<int64_t>(i, 0), n - 2);
+  const double d = k - kt[i];
+  const double h = kt[i + 1] - kt[i];
+  const double t = d / h;
+  const double dp = pt[i + 1] - pt[i];
+  const double prod = dp * t;
+  return pt[i] + prod;
+}
+
+template <typename T>
+void fill_weights(const cmbx_plan* p, const double* kt, const double* pt, int64_t n, std::vector<T>& out) {
+  // P_box = P_inf (2 pi / L)^3 (eq. finalpbox, cubic box); half = sqrt(P_box / 2),
+  // full = sqrt(P_box) at |f|^2 = c (N/2)^2, c = 0..3; P_box(0) = 0.
+  const int M = p->N / 2;
+  const int64_t mmax = 3ll * M * M;
+  const double c = 6.283185307179586 / p->L;
+  const double c3 = c * c * c;
+  out.assign(mmax + 1 + 4, T(0));
+  std::vector<double> pbox(mmax + 1);
+  for (int64_t m = 0; m <= mmax; ++m) {
+    const double k = c * std::sqrt((double)m);
+    const double pi = interp_p(kt, pt, n, k);
+    pbox[m] = m == 0 ? 0.0 : pi * c3;
+    out[m] = (T)std::sqrt(pbox[m] * 0.5);
+  }
+  for (int cc = 0; cc < 4; ++cc) out[mmax + 1 + cc] = (T)std::sqrt(pbox[(int64_t)cc * M * M]);
+}
+
+int check_plan(const cmbx_plan* p) {
+  if (!p) return fail(CMBX_EINVAL, "plan is NULL");
+  return CMBX_OK;
+}
+
+cmbx::FieldArgs field_args(const cmbx_plan* p, uint64_t seed, void* buf) {
+  cmbx::FieldArgs a;
+  a.dtype = p->dtype;
+  a.N = p->N;
+  a.buf = buf;
+  a.wtab = p->wtab;
+  a.tw = p->tw;
+  a.k0 = (uint32_t)(seed & 0xffffffffu);
+  a.k1 = (uint32_t)(seed >> 32);
+  a.tile_xy = p->tile_xy;
+  a.lines_z = p->lines_z;
+  return a;
+}
+
+int enqueue_field(const cmbx_plan* p, uint64_t seed, void* buf, hipStream_t s) {
+  const cmbx::FieldArgs a = field_args(p, seed, buf);
+  HIP_TRY(cmbx::launch_pass_x(a, s));
+  HIP_TRY(cmbx::launch_pass_y(a, s));
+  HIP_TRY(cmbx::launch_pass_z(a, s));
+  return CMBX_OK;
+}
+
+int enqueue_gather(const cmbx_plan* p, const void* field, double r, const double* dirs, int64_t n_pix, void* out,
+                   hipStream_t s) {
+  cmbx::GatherArgs g;
+  g.dtype = p->dtype;
+  g.interp = p->interp;
+  g.N = p->N;
+  g.field = field;
+  g.scale = (double)p->N / p->L;
+  g.half = 0.5 * p->L;
+  g.r = r;
+  g.dirs = dirs;
+  g.n_pix = n_pix;
+  g.out = out;
+  HIP_TRY(cmbx::launch_gather(g, s));
+  return CMBX_OK;
+}
+
+int check_patch_args(const cmbx_plan* p, double r, const double* dirs, int64_t n_pix, const void* out) {
+  if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set: call cmbx_spectrum_table first");
+  if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2 = %g", r, 0.5 * p->L);
+  if (n_pix < 1) return fail(CMBX_EINVAL, "n_pix = %lld must be >= 1", (long long)n_pix);
+  if (n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "n_pix = %lld exceeds 2^31", (long long)n_pix);
+  if (!dirs || !out) return fail(CMBX_EINVAL, "dirs and out must be non-NULL device pointers");
+  return CMBX_OK;
+}
+
+// Launch the whole hot path for every realisation of the plan on stream s.
+int enqueue_patch(cmbx_plan* p, uint64_t seed, double r, const double* dirs, int64_t n_pix, void* out,
+                  hipStream_t s) {
+  for (int b = 0; b < p->batch; ++b) {
+    char* buf = (char*)p->field + (size_t)b * p->field_bytes();
+    int rc = enqueue_field(p, seed + (uint64_t)b, buf, s);
+    if (rc) return rc;
+    rc = enqueue_gather(p, buf, r, dirs, n_pix, (char*)out + (size_t)b * n_pix * p->real_size(), s);
+    if (rc) return rc;
+  }
+  return CMBX_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int cmbx_plan_box(int N, double L, int dtype, int batch, cmbx_plan** out) {
+  if (!out) return fail(CMBX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (N < 8 || N > 1024 || N % 2) return fail(CMBX_EINVAL, "N = %d must be even and in [8, 1024]", N);
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(CMBX_EINVAL, "L = %g must be positive and finite", L);
+  if (dtype != CMBX_F32 && dtype != CMBX_F64) return fail(CMBX_EINVAL, "unknown dtype %d", dtype);
+  if (batch < 1) return fail(CMBX_EINVAL, "batch = %d must be >= 1", batch);
+  if (!is_2a3b(N) || !cmbx::size_compiled(N))
+    return fail(CMBX_EUNSUPPORTED, "N = %d: compiled sizes are 2^a and 3 x 2^a in [8, 1024]", N);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(CMBX_EHIP, "no HIP device available");
+  cmbx_plan* p = new cmbx_plan;
+  p->N = N;
+  p->L = L;
+  p->dtype = dtype;
+  p->batch = batch;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking);
+  p->stream = p->own_stream;
+  if (e == hipSuccess) e = hipMalloc(&p->field, p->field_bytes() * batch);
+  if (e == hipSuccess) e = hipMalloc(&p->tw, (size_t)N * 2 * p->real_size());
+  if (e == hipSuccess) e = hipMalloc(&p->wtab, (size_t)p->wtab_len() * p->real_size());
+  if (e != hipSuccess) {
+    const int code = (e == hipErrorOutOfMemory) ? CMBX_ENOMEM : CMBX_EHIP;
+    const std::string msg = hipGetErrorString(e);
+    cmbx_plan_destroy(p);
+    return fail(code, "plan allocation (N = %d, batch = %d): %s", N, batch, msg.c_str());
+  }
+  std::vector<double> re, im;
+  roots_of_unity(N, re, im);
+  if (dtype == CMBX_F32) {
+    std::vector<float> t(2 * N);
+    for (int m = 0; m < N; ++m) t[2 * m] = (float)re[m], t[2 * m + 1] = (float)im[m];
+    e = hipMemcpy(p->tw, t.data(), t.size() * 4, hipMemcpyHostToDevice);
+  } else {
+    std::vector<double> t(2 * N);
+    for (int m = 0; m < N; ++m) t[2 * m] = re[m], t[2 * m + 1] = im[m];
+    e = hipMemcpy(p->tw, t.data(), t.size() * 8, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    cmbx_plan_destroy(p);
+    return fail(CMBX_EHIP, "twiddle upload: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return ok();
+}
+
+int cmbx_plan_destroy(cmbx_plan* p) {
+  if (!p) return ok();
+  DeviceGuard g(p->device);
+  if (p->own_stream) (void)hipStreamSynchronize(p->own_stream);
+  if (p->stream && p->stream != p->own_stream) (void)hipStreamSynchronize(p->stream);
+  if (p->field) (void)hipFree(p->field);
+  if (p->tw) (void)hipFree(p->tw);
+  if (p->wtab) (void)hipFree(p->wtab);
+  if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
+  delete p;
+  return ok();
+}
+
+int cmbx_plan_set(cmbx_plan* p, int key, int64_t value) {
+  if (int rc = check_plan(p)) return rc;
+  int opts[4];
+  switch (key) {
+    case CMBX_OPT_INTERP:
+      if (value != CMBX_TRILINEAR && value != CMBX_TRICUBIC) return fail(CMBX_EINVAL, "unknown interpolant %lld", (long long)value);
+      p->interp = (int)value;
+      return ok();
+    case CMBX_OPT_STREAM:
+      p->stream = value == -1 ? p->own_stream : (hipStream_t)(intptr_t)value;
+      return ok();
+    case CMBX_OPT_TILE_XY: {
+      const int n = cmbx::tile_xy_choices(p->dtype, p->N, opts);
+      if (value != 0 && std::find(opts, opts + n, (int)value) == opts + n)
+        return fail(CMBX_EINVAL, "tile %lld not compiled for N = %d", (long long)value, p->N);
+      p->tile_xy = (int)value;
+      return ok();
+    }
+    case CMBX_OPT_LINES_Z: {
+      const int n = cmbx::lines_z_choices(p->dtype, p->N, opts);
+      if (value != 0 && std::find(opts, opts + n, (int)value) == opts + n)
+        return fail(CMBX_EINVAL, "z lines %lld not compiled for N = %d", (long long)value, p->N);
+      p->lines_z = (int)value;
+      return ok();
+    }
+    default:
+      return fail(CMBX_EINVAL, "unknown option key %d", key);
+  }
+}
+
+int cmbx_plan_info(const cmbx_plan* p, int* N, double* L, int* dtype, int* batch, void** field) {
+  if (int rc = check_plan(p)) return rc;
+  if (N) *N = p->N;
+  if (L) *L = p->L;
+  if (dtype) *dtype = p->dtype;
+  if (batch) *batch = p->batch;
+  if (field) *field = p->field;
+  return ok();
+}
+
+int cmbx_spectrum_table(cmbx_plan* p, const double* k, const double* P, int64_t n) {
+  if (int rc = check_plan(p)) return rc;
+  if (!k || !P) return fail(CMBX_EINVAL, "k and P_inf must be non-NULL host arrays");
+  if (n < 2) return fail(CMBX_EINVAL, "n = %lld must be >= 2", (long long)n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(k[i]) || k[i] < 0) return fail(CMBX_EINVAL, "k[%lld] = %g must be finite and >= 0", (long long)i, k[i]);
+    if (!std::isfinite(P[i]) || P[i] < 0) return fail(CMBX_EINVAL, "P_inf[%lld] = %g must be finite and >= 0", (long long)i, P[i]);
+    if (i > 0 && !(k[i] > k[i - 1])) return fail(CMBX_EINVAL, "k must be strictly increasing (index %lld)", (long long)i);
+  }
+  DeviceGuard g(p->device);
+  hipError_t e;
+  // the table is uploaded synchronously with respect to the plan's stream
+  e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return fail(CMBX_EHIP, "stream sync: %s", hipGetErrorString(e));
+  if (p->dtype == CMBX_F32) {
+    std::vector<float> w;
+    fill_weights(p, k, P, n, w);
+    e = hipMemcpy(p->wtab, w.data(), w.size() * 4, hipMemcpyHostToDevice);
+  } else {
+    std::vector<double> w;
+    fill_weights(p, k, P, n, w);
+    e = hipMemcpy(p->wtab, w.data(), w.size() * 8, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return fail(CMBX_EHIP, "weight table upload: %s", hipGetErrorString(e));
+  p->has_spectrum = true;
+  return ok();
+}
+
+int cmbx_simulate_patch(cmbx_plan* p, uint64_t seed, double r, const double* dirs, int64_t n_pix, void* out) {
+  if (int rc = check_plan(p)) return rc;
+  if (int rc = check_patch_args(p, r, dirs, n_pix, out)) return rc;
+  DeviceGuard g(p->device);
+  if (int rc = enqueue_patch(p, seed, r, dirs, n_pix, out, p->stream)) return rc;
+  return ok();
+}
+
+int cmbx_debug_noise(cmbx_plan* p, uint64_t seed, void* halfgrid) {
+  if (int rc = check_plan(p)) return rc;
+  if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set");
+  if (!halfgrid) return fail(CMBX_EINVAL, "halfgrid is NULL");
+  DeviceGuard g(p->device);
+  HIP_TRY(cmbx::launch_noise_debug(p->dtype, p->N, halfgrid, p->wtab, (uint32_t)(seed & 0xffffffffu),
+                                   (uint32_t)(seed >> 32), p->stream));
+  return ok();
+}
+
+int cmbx_debug_field(cmbx_plan* p, uint64_t seed, void* field) {
+  if (int rc = check_plan(p)) return rc;
+  if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set");
+  if (!field) return fail(CMBX_EINVAL, "field is NULL");
+  DeviceGuard g(p->device);
+  if (int rc = enqueue_field(p, seed, field, p->stream)) return rc;
+  return ok();
+}
+
+int cmbx_debug_gather(cmbx_plan* p, const void* field, double r, const double* dirs, int64_t n_pix, void* out) {
+  if (int rc = check_plan(p)) return rc;
+  if (!field) return fail(CMBX_EINVAL, "field is NULL");
+  if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2", r);
+  if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "bad n_pix %lld", (long long)n_pix);
+  if (!dirs || !out) return fail(CMBX_EINVAL, "dirs and out must be non-NULL");
+  DeviceGuard g(p->device);
+  if (int rc = enqueue_gather(p, field, r, dirs, n_pix, out, p->stream)) return rc;
+  return ok();
+}
+
+int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, cmbx_ensemble** out) {
+  if (!out) return fail(CMBX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!jobs || n_jobs < 1) return fail(CMBX_EINVAL, "need at least one job");
+  for (int j = 0; j < n_jobs; ++j) {
+    if (!jobs[j].plan) return fail(CMBX_EINVAL, "job %d has no plan", j);
+    if (int rc = check_patch_args(jobs[j].plan, jobs[j].r, jobs[j].dirs, jobs[j].n_pix, jobs[j].out)) {
+      g_err = "job " + std::to_string(j) + ": " + g_err;
+      return rc;
+    }
+    if (jobs[j].plan->device != jobs[0].plan->device) return fail(CMBX_EINVAL, "all jobs must be on one device");
+  }
+  DeviceGuard g(jobs[0].plan->device);
+  // Jobs of one plan share its workspace and form one chain; chains of different plans
+  // are independent branches of the graph.
+  std::vector<cmbx_plan*> plans;
+  std::map<cmbx_plan*, std::vector<int>> chains;
+  for (int j = 0; j < n_jobs; ++j) {
+    if (!chains.count(jobs[j].plan)) plans.push_back(jobs[j].plan);
+    chains[jobs[j].plan].push_back(j);
+  }
+  hipStream_t origin = nullptr;
+  std::vector<hipStream_t> branch(plans.size(), nullptr);
+  std::vector<hipEvent_t> ev(plans.size() + 1, nullptr);
+  hipGraph_t graph = nullptr;
+  int rc = CMBX_OK;
+  auto cleanup = [&]() {
+    for (auto s : branch)
+      if (s) (void)hipStreamDestroy(s);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (origin) (void)hipStreamDestroy(origin);
+  };
+  hipError_t e = hipStreamCreateWithFlags(&origin, hipStreamNonBlocking);
+  for (size_t i = 0; e == hipSuccess && i < plans.size(); ++i) e = hipStreamCreateWithFlags(&branch[i], hipStreamNonBlocking);
+  for (size_t i = 0; e == hipSuccess && i < ev.size(); ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(CMBX_EHIP, "ensemble setup: %s", hipGetErrorString(e));
+  }
+  e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], origin);
+  for (size_t i = 0; e == hipSuccess && rc == CMBX_OK && i < plans.size(); ++i) {
+    e = hipStreamWaitEvent(branch[i], ev[0], 0);
+    for (int j : chains[plans[i]]) {
+      if (e != hipSuccess || rc != CMBX_OK) break;
+      rc = enqueue_patch(plans[i], jobs[j].seed, jobs[j].r, jobs[j].dirs, jobs[j].n_pix, jobs[j].out, branch[i]);
+    }
+    if (e == hipSuccess && rc == CMBX_OK) e = hipEventRecord(ev[i + 1], branch[i]);
+    if (e == hipSuccess && rc == CMBX_OK) e = hipStreamWaitEvent(origin, ev[i + 1], 0);
+  }
+  const hipError_t e_end = hipStreamEndCapture(origin, &graph);
+  if (e == hipSuccess) e = e_end;
+  if (rc != CMBX_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    cleanup();
+    if (rc != CMBX_OK) return rc;
+    return fail(CMBX_EHIP, "ensemble capture: %s", hipGetErrorString(e));
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  cleanup();
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(CMBX_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  cmbx_ensemble* en = new cmbx_ensemble;
+  en->graph = graph;
+  en->exec = exec;
+  *out = en;
+  return ok();
+}
+
+int cmbx_ensemble_launch(cmbx_ensemble* en, void* stream) {
+  if (!en) return fail(CMBX_EINVAL, "ensemble is NULL");
+  HIP_TRY(hipGraphLaunch(en->exec, (hipStream_t)stream));
+  return ok();
+}
+
+int cmbx_ensemble_destroy(cmbx_ensemble* en) {
+  if (!en) return ok();
+  if (en->exec) (void)hipGraphExecDestroy(en->exec);
+  if (en->graph) (void)hipGraphDestroy(en->graph);
+  delete en;
+  return ok();
+}
+
+const char* cmbx_last_error(void) { return g_err.c_str(); }
+
+const char* cmbx_version(void) { return "cmbx 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Complex arithmetic, radix-R inverse DFT butterflies and an LDS Stockham stage driver
+// for gfx950 (wave64). Used by the three passes of the inverse 3-D FFT.
+//
+// Sign convention: every transform here is the unnormalised inverse DFT
+//   y_k = sum_r v_r exp(+2 pi i r k / R),
+// which composed over the stages gives T(j) = sum_f T(f) exp(+2 pi i f j / L).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace cmbx {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_i(cpx<T> a) { return {-a.y, a.x}; }  // i a
+template <typename T>
+__device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------------- butterflies
+template <typename T, int R>
+struct Dft;
+
+template <typename T>
+struct Dft<T, 2> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  }
+};
+
+template <typename T>
+struct Dft<T, 3> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T h = T(0.8660254037844386467637231707529362);  // sqrt(3)/2
+    cpx<T> s = v[1] + v[2], d = v[1] - v[2];
+    cpx<T> m = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+    cpx<T> j = {-h * d.y, h * d.x};  // i (sqrt3/2) d
+    v[0] = v[0] + s;
+    v[1] = m + j;
+    v[2] = m - j;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void dft4(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2, cpx<T>& a3) {
+  cpx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = mul_i(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <typename T>
+struct Dft<T, 4> {
+  static __device__ __forceinline__ void run(cpx<T>* v) { dft4(v[0], v[1], v[2], v[3]); }
+};
+
+template <typename T>
+struct Dft<T, 8> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T c = T(0.7071067811865475244008443621048490);
+    cpx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cpx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    o1 = {c * (o1.x - o1.y), c * (o1.x + o1.y)};    // x e^{i pi/4}
+    o2 = mul_i(o2);                                  // x e^{i pi/2}
+    o3 = {-c * (o3.x + o3.y), c * (o3.x - o3.y)};   // x e^{3 i pi/4}
+    v[0] = e0 + o0; v[4] = e0 - o0;
+    v[1] = e1 + o1; v[5] = e1 - o1;
+    v[2] = e2 + o2; v[6] = e2 - o2;
+    v[3] = e3 + o3; v[7] = e3 - o3;
+  }
+};
+
+template <typename T>
+struct Dft<T, 16> {
+  // r = 4a + b, k = k1 + 4 k2: length-4 transforms over a, twiddles e^{2 pi i b k1 / 16},
+  // then length-4 transforms over b.
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T c1 = T(0.9238795325112867561281831893967883);  // cos(pi/8)
+    const T s1 = T(0.3826834323650897717284599840303989);  // sin(pi/8)
+    const T c2 = T(0.7071067811865475244008443621048490);
+    cpx<T> a[4][4];  // a[b][k1]
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      a[b][0] = v[b]; a[b][1] = v[4 + b]; a[b][2] = v[8 + b]; a[b][3] = v[12 + b];
+      dft4(a[b][0], a[b][1], a[b][2], a[b][3]);
+    }
+    // b = 1: w^{k1}, k1 = 1,2,3 -> m = 1, 2, 3
+    a[1][1] = cmul(a[1][1], cpx<T>{c1, s1});
+    a[1][2] = cmul(a[1][2], cpx<T>{c2, c2});
+    a[1][3] = cmul(a[1][3], cpx<T>{s1, c1});
+    // b = 2: m = 2, 4, 6
+    a[2][1] = cmul(a[2][1], cpx<T>{c2, c2});
+    a[2][2] = mul_i(a[2][2]);
+    a[2][3] = cmul(a[2][3], cpx<T>{-c2, c2});
+    // b = 3: m = 3, 6, 9
+    a[3][1] = cmul(a[3][1], cpx<T>{s1, c1});
+    a[3][2] = cmul(a[3][2], cpx<T>{-c2, c2});
+    a[3][3] = cmul(a[3][3], cpx<T>{-c1, -s1});
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cpx<T> b0 = a[0][k1], b1 = a[1][k1], b2 = a[2][k1], b3 = a[3][k1];
+      dft4(b0, b1, b2, b3);
+      v[k1] = b0; v[k1 + 4] = b1; v[k1 + 8] = b2; v[k1 + 12] = b3;
+    }
+  }
+};
+
+// ---------------------------------------------------------------- stage plans
+// Factorisation of a transform length L = 2^a 3^b into radix stages: radix-3 stages
+// first, then the power of two as radix-8 stages with one radix-16, -4 or -2 stage to
+// make up the remainder (a = 8 uses two radix-16 stages).
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+constexpr int pow3_count(int L) { return (L % 3 == 0) ? 1 + pow3_count(L / 3) : 0; }
+constexpr int pow2_part(int L) { return (L % 3 == 0) ? pow2_part(L / 3) : L; }
+
+constexpr int pow2_stage_count(int a) {
+  return a == 0 ? 0 : a <= 4 ? 1 : a == 5 ? 2 : a == 6 ? 2 : a == 7 ? 2 : a == 8 ? 2 : a == 9 ? 3 : a == 10 ? 3 : 3;
+}
+constexpr int pow2_radix(int a, int i) {
+  // a: exponent of the power of two; i: stage index within the power-of-two stages
+  return a <= 4 ? (1 << a)
+       : a == 5 ? (i == 0 ? 8 : 4)
+       : a == 6 ? 8
+       : a == 7 ? (i == 0 ? 16 : 8)
+       : a == 8 ? 16
+       : a == 9 ? 8
+       : a == 10 ? (i == 0 ? 16 : 8)
+       : (i < 2 ? 16 : 8);  // a == 11
+}
+constexpr int stage_count(int L) { return pow3_count(L) + pow2_stage_count(ilog2(pow2_part(L))); }
+constexpr int stage_radix(int L, int i) {
+  return i < pow3_count(L) ? 3 : pow2_radix(ilog2(pow2_part(L)), i - pow3_count(L));
+}
+constexpr int stage_stride(int L, int i) { return i == 0 ? 1 : stage_stride(L, i - 1) * stage_radix(L, i - 1); }
+constexpr bool plan_ok(int L, int i = 0, int prod = 1) {
+  return i == stage_count(L) ? prod == L : plan_ok(L, i + 1, prod * stage_radix(L, i));
+}
+
+// ---------------------------------------------------------------- stage driver
+// One Stockham stage (radix R, stride NS = product of the earlier radices) over NSEQ
+// independent sequences of length L. Each of the (L/R) NSEQ butterflies reads R inputs
+// spaced L/R apart, multiplies input r by w^{r k} (k = j mod NS, w = e^{2 pi i/(NS R)}),
+// transforms them and writes output r to position (j / NS) NS R + k + r NS. After the
+// last stage the sequence is in natural order.
+//
+// Slot s -> (sequence, j): with SEQFAST consecutive lanes take consecutive sequences
+// (column tiles, where the sequences are the contiguous dimension); otherwise consecutive
+// j within one sequence (line tiles). src(seq, n) / dst(seq, n, v) access element n of a
+// sequence. tw is the table of NTW-th roots exp(2 pi i m / NTW), NTW = L * TWMUL.
+template <typename T, int L, int NSEQ, int NT, int R, int NS, bool SEQFAST, int TWMUL, class Src, class Dst>
+__device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ tw, Src& src, Dst& dst) {
+  constexpr int J = L / R;
+  constexpr int SLOTS = J * NSEQ;
+  constexpr int PER = (SLOTS + NT - 1) / NT;
+  constexpr bool FULL = (SLOTS % NT) == 0;
+  const int tid = threadIdx.x;
+  cpx<T> v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int s = tid + q * NT;
+    if (FULL || s < SLOTS) {
+      const int seq = SEQFAST ? s % NSEQ : s / J;
+      const int j = SEQFAST ? s / NSEQ : s % J;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src(seq, j + r * J);
+    }
+  }
+  src.done();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int s = tid + q * NT;
+    if (FULL || s < SLOTS) {
+      const int seq = SEQFAST ? s % NSEQ : s / J;
+      const int j = SEQFAST ? s / NSEQ : s % J;
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * (L / (NS * R)) * TWMUL]);
+      }
+      Dft<T, R>::run(v[q]);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst(seq, base + r * NS, v[q][r]);
+    }
+  }
+  dst.done();
+}
+
+// LDS-resident sequences. SEQFAST layout: element n of sequence q at n * NSEQ + q;
+// otherwise at q * L + n.
+template <typename T, int L, int NSEQ, bool SEQFAST>
+struct LdsIO {
+  cpx<T>* p;
+  __device__ __forceinline__ cpx<T> operator()(int q, int n) const {
+    return p[SEQFAST ? n * NSEQ + q : q * L + n];
+  }
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const {
+    p[SEQFAST ? n * NSEQ + q : q * L + n] = v;
+  }
+  __device__ __forceinline__ void done() const { __syncthreads(); }
+};
+
+// Run all stages of a length-L transform: stage 0 reads from `first`, the last stage
+// writes to `last`, stages in between go through the LDS sequences `lds`.
+template <typename T, int L, int NSEQ, int NT, bool SEQFAST, int TWMUL, int S, class First, class Last>
+__device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* lds, First& first, Last& last) {
+  constexpr int NST = stage_count(L);
+  static_assert(plan_ok(L), "unsupported transform length");
+  if constexpr (S < NST) {
+    constexpr int R = stage_radix(L, S);
+    constexpr int NS = stage_stride(L, S);
+    LdsIO<T, L, NSEQ, SEQFAST> mid{lds};
+    if constexpr (S == 0 && NST == 1) {
+      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, last);
+    } else if constexpr (S == 0) {
+      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, mid);
+    } else if constexpr (S == NST - 1) {
+      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, last);
+    } else {
+      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, mid);
+    }
+    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1>(tw, lds, first, last);
+  }
+}
+
+}  // namespace cmbx

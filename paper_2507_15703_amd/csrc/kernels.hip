@@ -1,0 +1,407 @@
+// HIP kernels of the hot path for gfx950: the three passes of the inverse 3-D FFT (the
+// first fused with noise generation) and the sphere gather.
+//
+// Data layout (one realisation, plan precision T):
+//   during the passes: complex [N][N][N/2] -- the half grid with its iz = 0 and iz = N/2
+//     planes packed into column 0 as Z_0 + i Z_{N/2}. Both planes are Hermitian within
+//     the plane, so after the x and y transforms they are real and column 0 holds their
+//     two real 2-D transforms side by side. This keeps every line at N/2 columns.
+//   after pass 3: real [N][N][N], z fastest -- the same bytes, in place.
+#include <hip/hip_runtime.h>
+
+#include "fft_device.hpp"
+#include "kernels.hpp"
+#include "noise_device.hpp"
+
+namespace cmbx {
+
+// ------------------------------------------------------------------ global accessors
+// Column tile of a strided axis: element n of column q at p[n * stride + q].
+template <typename T>
+struct GlobalColIO {
+  cpx<T>* p;
+  size_t stride;
+  __device__ __forceinline__ cpx<T> operator()(int q, int n) const { return p[(size_t)n * stride + q]; }
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const { p[(size_t)n * stride + q] = v; }
+  // the tile is read and written in place, so all reads must finish before any write
+  __device__ __forceinline__ void done() const { __syncthreads(); }
+};
+
+// Contiguous lines of length L: element n of line q at p[q * L + n].
+template <typename T, int L>
+struct GlobalLineIO {
+  cpx<T>* p;
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const { p[(size_t)q * L + n] = v; }
+  __device__ __forceinline__ void done() const {}
+};
+
+// First stage of the z pass: the packed half line X_0 .. X_{M-1} (LDS, line-major) is
+// turned into the M-point complex sequence
+//   Z_k = (X_k + conj X_{M-k}) + i w^k (X_k - conj X_{M-k}),  w = exp(2 pi i / N),
+//   Z_0 = (a + b) + i (a - b)   with X_0 = a, X_{N/2} = b (column 0 holds a + i b),
+// whose inverse M-point DFT z_n gives the real outputs x_{2n} = Re z_n, x_{2n+1} = Im z_n.
+template <typename T, int M>
+struct HalfToComplex {
+  const cpx<T>* x;
+  const cpx<T>* tw;  // N = 2M roots
+  __device__ __forceinline__ cpx<T> operator()(int q, int k) const {
+    const cpx<T> xk = x[q * M + k];
+    if (k == 0) return {xk.x + xk.y, xk.x - xk.y};
+    const cpx<T> xc = conj(x[q * M + (M - k)]);
+    return (xk + xc) + mul_i(cmul(tw[k], xk - xc));
+  }
+  __device__ __forceinline__ void done() const { __syncthreads(); }
+};
+
+// ------------------------------------------------------------------ launch shapes
+constexpr int clamp_nt(int work) { return work >= 2048 ? 256 : work >= 1024 ? 128 : 64; }
+
+template <typename T, int N, int TZ>
+struct XYShape {
+  static constexpr int M = N / 2;
+  static constexpr int NT = clamp_nt(N * TZ);
+  static_assert(M % TZ == 0 && TZ % 2 == 0, "tile must divide N/2 and be even");
+};
+
+template <typename T, int N, int LINES>
+struct ZShape {
+  static constexpr int M = N / 2;
+  static constexpr int NT = clamp_nt(LINES * M);
+};
+
+// ------------------------------------------------------------------ pass 1: noise + x
+// Workgroup = (z tile of TZ packed columns, one iy). Generates the N x TZ tile of weighted
+// modes in LDS (one Philox call per pair of neighbouring iz), then runs the length-N
+// inverse transform along x and writes the tile's N rows of TZ columns (128 B for FP32
+// TZ = 16) to the strided x axis.
+template <typename T, int N, int TZ>
+__global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __restrict__ buf,
+                                                                 const T* __restrict__ wtab,
+                                                                 const cpx<T>* __restrict__ twg,
+                                                                 uint32_t k0, uint32_t k1) {
+  constexpr int M = N / 2;
+  constexpr int NT = XYShape<T, N, TZ>::NT;
+  constexpr int PAIRS = TZ / 2;
+  __shared__ cpx<T> tile[N * TZ];
+  __shared__ cpx<T> tw[N];
+  const int tid = threadIdx.x;
+  const int zc0 = blockIdx.x * TZ;
+  const int iy = blockIdx.y;
+  const T* wself = wtab + 3 * M * M + 1;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  const int fy2 = freq2(iy, N);
+  for (int s = tid; s < N * PAIRS; s += NT) {
+    const int pr = s % PAIRS;
+    const int ix = s / PAIRS;
+    const int zc = zc0 + 2 * pr;
+    cpx<T> v0, v1;
+    if (zc == 0) {
+      const cpx<T> a = mode_value<T>(N, ix, iy, 0, k0, k1, wtab, wself);
+      const cpx<T> b = mode_value<T>(N, ix, iy, M, k0, k1, wtab, wself);
+      v0 = {a.x - b.y, a.y + b.x};  // Z_0 + i Z_{N/2}
+      v1 = mode_value<T>(N, ix, iy, 1, k0, k1, wtab, wself);
+    } else {
+      const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
+      const int m0 = freq2(ix, N) + fy2 + zc * zc;
+      const int m1 = m0 + 2 * zc + 1;
+      v0 = weighted<T>(wtab[m0], w.x, w.y);
+      v1 = weighted<T>(wtab[m1], w.z, w.w);
+    }
+    tile[ix * TZ + 2 * pr] = v0;
+    tile[ix * TZ + 2 * pr + 1] = v1;
+  }
+  __syncthreads();
+  LdsIO<T, N, TZ, true> first{tile};
+  GlobalColIO<T> last{buf + (size_t)iy * M + zc0, (size_t)N * M};
+  fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, first, last);
+}
+
+// ------------------------------------------------------------------ pass 2: y
+template <typename T, int N, int TZ>
+__global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __restrict__ buf,
+                                                                 const cpx<T>* __restrict__ twg) {
+  constexpr int M = N / 2;
+  constexpr int NT = XYShape<T, N, TZ>::NT;
+  __shared__ cpx<T> tile[N * TZ];
+  __shared__ cpx<T> tw[N];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  __syncthreads();
+  GlobalColIO<T> io{buf + (size_t)blockIdx.y * N * M + blockIdx.x * TZ, (size_t)M};
+  fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, io, io);
+}
+
+// ------------------------------------------------------------------ pass 3: z (c2r)
+// Workgroup = LINES consecutive (ix, iy) lines of N/2 complex; they are contiguous, so
+// the whole block is loaded and stored with unit stride.
+template <typename T, int N, int LINES>
+__global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __restrict__ buf,
+                                                                   const cpx<T>* __restrict__ twg) {
+  constexpr int M = N / 2;
+  constexpr int NT = ZShape<T, N, LINES>::NT;
+  __shared__ cpx<T> tile[LINES * M];
+  __shared__ cpx<T> tw[N];
+  const int tid = threadIdx.x;
+  cpx<T>* g = buf + (size_t)blockIdx.x * LINES * M;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  for (int i = tid; i < LINES * M; i += NT) tile[i] = g[i];
+  __syncthreads();
+  HalfToComplex<T, M> first{tile, tw};
+  GlobalLineIO<T, M> last{g};
+  fft_run<T, M, LINES, NT, false, 2, 0>(tw, tile, first, last);
+}
+
+// ------------------------------------------------------------------ debug noise
+template <typename T>
+__global__ void k_noise_debug(cpx<T>* __restrict__ out, int N, const T* __restrict__ wtab, uint32_t k0,
+                              uint32_t k1) {
+  const int M = N / 2;
+  const int64_t total = (int64_t)N * N * (M + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int iz = (int)(i % (M + 1));
+  const int64_t t = i / (M + 1);
+  const int iy = (int)(t % N);
+  const int ix = (int)(t / N);
+  out[i] = mode_value<T>(N, ix, iy, iz, k0, k1, wtab, wtab + 3 * M * M + 1);
+}
+
+// ------------------------------------------------------------------ gather
+// One thread per pixel. The position p = (r n + L/2) N/L and its floor are formed in FP64
+// (no contraction, so CPU and GPU take the same integer decision); the fraction is then
+// rounded to T, and weights and accumulation are in T. The 2 or 4 nodes per axis wrap
+// modulo N. Blocks are assigned so that each XCD's L2 serves a contiguous pixel range.
+template <typename T>
+__device__ __forceinline__ void weights1d(T f, T* w, int interp) {
+  if (interp == kTricubic) {
+    w[0] = f * (T(-0.5) + f * (T(1.0) - T(0.5) * f));
+    w[1] = T(1.0) + f * f * (T(-2.5) + T(1.5) * f);
+    w[2] = f * (T(0.5) + f * (T(2.0) - T(1.5) * f));
+    w[3] = f * f * (T(-0.5) + T(0.5) * f);
+  } else {
+    w[0] = T(1.0) - f;
+    w[1] = f;
+  }
+}
+
+__device__ __forceinline__ int wrap(int i, int N) { return i < 0 ? i + N : (i >= N ? i - N : i); }
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int N, double scale, double half,
+                                                double r, const double* __restrict__ dirs, int64_t npix,
+                                                T* __restrict__ out) {
+  const int nb = gridDim.x;
+  const int per = nb / 8;
+  const int b = blockIdx.x;
+  const int logical = (nb % 8 == 0) ? (b % 8) * per + b / 8 : b;
+  const int64_t i = (int64_t)logical * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  int i0[3];
+  T w[3][4];
+  {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double p = (r * dirs[3 * i + d] + half) * scale;
+      // any finite position is reduced modulo N; non-finite input samples node 0
+      if (!(p > -1.0e9 && p < 1.0e9)) p = 0.0;
+      const double fl = floor(p);
+      int base = (int)fl % N;
+      base = base < 0 ? base + N : base;
+      i0[d] = base - (K == 4 ? 1 : 0);
+      weights1d<T>((T)(p - fl), w[d], K == 4 ? kTricubic : kTrilinear);
+    }
+  }
+  int iz[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) iz[c] = wrap(i0[2] + c, N);
+  T acc = 0;
+#pragma unroll
+  for (int a = 0; a < K; ++a) {
+    const int ix = wrap(i0[0] + a, N);
+    T accb = 0;
+#pragma unroll
+    for (int bb = 0; bb < K; ++bb) {
+      const int iy = wrap(i0[1] + bb, N);
+      const T* line = field + ((size_t)ix * N + iy) * N;
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < K; ++c) s += w[2][c] * line[iz[c]];
+      accb += w[1][bb] * s;
+    }
+    acc += w[0][a] * accb;
+  }
+  out[i] = acc;
+}
+
+// ------------------------------------------------------------------ dispatch tables
+namespace {
+
+template <typename T>
+constexpr int max_tz() { return sizeof(T) == 4 ? 16 : 8; }
+constexpr int lds_budget() { return 72 * 1024; }
+
+// default column tile: the largest even divisor of N/2 up to the type's maximum whose
+// tile (plus twiddles) stays within the LDS budget
+template <typename T>
+constexpr int default_tz(int N) {
+  for (int tz = max_tz<T>(); tz >= 2; tz -= 2)
+    if ((N / 2) % tz == 0 && (N * tz + N) * 2 * (int)sizeof(T) <= lds_budget()) return tz;
+  return 2;
+}
+template <typename T>
+constexpr int alt_tz(int N) {
+  const int d = default_tz<T>(N);
+  return (d / 2 >= 2 && (d / 2) % 2 == 0 && (N / 2) % (d / 2) == 0) ? d / 2 : d;
+}
+// lines per z workgroup: about 4096 (FP32) / 2048 (FP64) complex, dividing N^2
+template <typename T>
+constexpr int default_lines(int N) {
+  const int target = (sizeof(T) == 4 ? 4096 : 2048) / (N / 2);
+  int l = 1;
+  while (l * 2 <= target && (N * N) % (l * 2) == 0) l *= 2;
+  return l;
+}
+template <typename T>
+constexpr int alt_lines(int N) {
+  const int d = default_lines<T>(N);
+  return d >= 2 ? d / 2 : d;
+}
+
+using PassFn = hipError_t (*)(const FieldArgs&, hipStream_t);
+
+template <typename T, int N, int TZ>
+hipError_t run_x(const FieldArgs& a, hipStream_t s) {
+  dim3 grid(N / 2 / TZ, N);
+  hipLaunchKernelGGL((k_pass_x<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
+                     (const T*)a.wtab, (const cpx<T>*)a.tw, a.k0, a.k1);
+  return hipGetLastError();
+}
+template <typename T, int N, int TZ>
+hipError_t run_y(const FieldArgs& a, hipStream_t s) {
+  dim3 grid(N / 2 / TZ, N);
+  hipLaunchKernelGGL((k_pass_y<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
+                     (const cpx<T>*)a.tw);
+  return hipGetLastError();
+}
+template <typename T, int N, int LINES>
+hipError_t run_z(const FieldArgs& a, hipStream_t s) {
+  dim3 grid(N * N / LINES);
+  hipLaunchKernelGGL((k_pass_z<T, N, LINES>), grid, dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf,
+                     (const cpx<T>*)a.tw);
+  return hipGetLastError();
+}
+
+struct Entry {
+  int dtype, N;
+  int tz[2];
+  PassFn x[2], y[2];
+  int lines[2];
+  PassFn z[2];
+};
+
+template <typename T, int N>
+constexpr Entry make_entry() {
+  constexpr int t0 = default_tz<T>(N), t1 = alt_tz<T>(N);
+  constexpr int l0 = default_lines<T>(N), l1 = alt_lines<T>(N);
+  return Entry{sizeof(T) == 4 ? kF32 : kF64,
+               N,
+               {t0, t1},
+               {&run_x<T, N, t0>, &run_x<T, N, t1>},
+               {&run_y<T, N, t0>, &run_y<T, N, t1>},
+               {l0, l1},
+               {&run_z<T, N, l0>, &run_z<T, N, l1>}};
+}
+
+#define CMBX_SIZES(T)                                                                                     \
+  make_entry<T, 8>(), make_entry<T, 12>(), make_entry<T, 16>(), make_entry<T, 24>(), make_entry<T, 32>(), \
+      make_entry<T, 48>(), make_entry<T, 64>(), make_entry<T, 96>(), make_entry<T, 128>(),                \
+      make_entry<T, 192>(), make_entry<T, 256>(), make_entry<T, 384>(), make_entry<T, 512>(),             \
+      make_entry<T, 768>(), make_entry<T, 1024>()
+
+const Entry kTable[] = {CMBX_SIZES(float), CMBX_SIZES(double)};
+
+const Entry* find(int dtype, int N) {
+  for (const Entry& e : kTable)
+    if (e.dtype == dtype && e.N == N) return &e;
+  return nullptr;
+}
+
+int pick(const int* opts, int want) {
+  if (want <= 0) return 0;
+  for (int i = 0; i < 2; ++i)
+    if (opts[i] == want) return i;
+  return -1;
+}
+
+}  // namespace
+
+bool size_compiled(int N) { return find(kF32, N) != nullptr; }
+
+int tile_xy_choices(int dtype, int N, int* out) {
+  const Entry* e = find(dtype, N);
+  if (!e) return 0;
+  out[0] = e->tz[0];
+  if (e->tz[1] == e->tz[0]) return 1;
+  out[1] = e->tz[1];
+  return 2;
+}
+
+int lines_z_choices(int dtype, int N, int* out) {
+  const Entry* e = find(dtype, N);
+  if (!e) return 0;
+  out[0] = e->lines[0];
+  if (e->lines[1] == e->lines[0]) return 1;
+  out[1] = e->lines[1];
+  return 2;
+}
+
+hipError_t launch_pass_x(const FieldArgs& a, hipStream_t s) {
+  const Entry* e = find(a.dtype, a.N);
+  const int i = e ? pick(e->tz, a.tile_xy) : -1;
+  if (i < 0) return hipErrorInvalidValue;
+  return e->x[i](a, s);
+}
+hipError_t launch_pass_y(const FieldArgs& a, hipStream_t s) {
+  const Entry* e = find(a.dtype, a.N);
+  const int i = e ? pick(e->tz, a.tile_xy) : -1;
+  if (i < 0) return hipErrorInvalidValue;
+  return e->y[i](a, s);
+}
+hipError_t launch_pass_z(const FieldArgs& a, hipStream_t s) {
+  const Entry* e = find(a.dtype, a.N);
+  const int i = e ? pick(e->lines, a.lines_z) : -1;
+  if (i < 0) return hipErrorInvalidValue;
+  return e->z[i](a, s);
+}
+
+hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uint32_t k0, uint32_t k1,
+                              hipStream_t s) {
+  const int64_t total = (int64_t)N * N * (N / 2 + 1);
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (dtype == kF32)
+    hipLaunchKernelGGL(k_noise_debug<float>, grid, dim3(256), 0, s, (cpx<float>*)out, N, (const float*)wtab, k0, k1);
+  else
+    hipLaunchKernelGGL(k_noise_debug<double>, grid, dim3(256), 0, s, (cpx<double>*)out, N, (const double*)wtab, k0,
+                       k1);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
+  int64_t nb = (a.n_pix + 255) / 256;
+  nb = (nb + 7) / 8 * 8;
+  const dim3 grid((unsigned)nb);
+  const bool cubic = a.interp == kTricubic;
+  if (a.dtype == kF32) {
+    auto k = cubic ? k_gather<float, 4> : k_gather<float, 2>;
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const float*)a.field, a.N, a.scale, a.half, a.r, a.dirs, a.n_pix,
+                       (float*)a.out);
+  } else {
+    auto k = cubic ? k_gather<double, 4> : k_gather<double, 2>;
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const double*)a.field, a.N, a.scale, a.half, a.r, a.dirs,
+                       a.n_pix, (double*)a.out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cmbx

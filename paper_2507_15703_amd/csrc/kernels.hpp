@@ -1,0 +1,49 @@
+// Internal interface between the C ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmbx {
+
+enum { kF32 = 1, kF64 = 2 };
+enum { kTrilinear = 1, kTricubic = 2 };
+
+// Box sizes with compiled kernels: N = 2^a 3^b, 8 <= N <= 1024, N/2 also 2^a 3^b.
+bool size_compiled(int N);
+
+// Tile choices compiled for (dtype, N). Returns the count written (<= 4); [0] is the default.
+int tile_xy_choices(int dtype, int N, int* out);
+int lines_z_choices(int dtype, int N, int* out);
+
+struct FieldArgs {
+  int dtype, N;
+  void* buf;           // N^3 reals, in place (complex N x N x N/2 during the passes)
+  const void* wtab;    // sqrt(P_box/2) for |f|^2 = 0 .. 3 (N/2)^2, then sqrt(P_box) x 4
+  const void* tw;      // N roots exp(2 pi i m / N), complex, plan precision
+  uint32_t k0, k1;     // Philox key (seed words)
+  int tile_xy, lines_z;
+};
+
+// Pass 1: noise + weights + Hermitian planes + inverse FFT along x.
+hipError_t launch_pass_x(const FieldArgs& a, hipStream_t s);
+// Pass 2: inverse FFT along y.
+hipError_t launch_pass_y(const FieldArgs& a, hipStream_t s);
+// Pass 3: complex-to-real inverse FFT along z (unpacks the iz = 0 / N/2 column).
+hipError_t launch_pass_z(const FieldArgs& a, hipStream_t s);
+
+// Unpacked weighted half grid [N][N][N/2+1] (tests).
+hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uint32_t k0, uint32_t k1,
+                              hipStream_t s);
+
+struct GatherArgs {
+  int dtype, interp, N;
+  const void* field;   // [N][N][N] reals
+  double scale, half;  // N / L and L / 2
+  double r;
+  const double* dirs;  // [n_pix][3]
+  int64_t n_pix;
+  void* out;           // [n_pix]
+};
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
+
+}  // namespace cmbx

@@ -1,0 +1,84 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared symbol, and
+rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_15703_amd import cmbx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(cmbx.LIB_PATH):
+        from paper_2507_15703_amd import build
+        build.build()
+    return cmbx.lib()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "cmbx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmbx_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "cmbx_plan_box" in names and "cmbx_simulate_patch" in names and "cmbx_spectrum_table" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version(L):
+    assert "gfx950" in cmbx.version()
+
+
+def _plan(N, Lbox, dt, batch):
+    h = ctypes.c_void_p()
+    rc = cmbx.lib().cmbx_plan_box(N, Lbox, dt, batch, ctypes.byref(h))
+    return rc, h.value
+
+
+@pytest.mark.parametrize("args,code", [
+    ((7, 1.0, cmbx.F32, 1), cmbx.EINVAL),      # odd
+    ((4, 1.0, cmbx.F32, 1), cmbx.EINVAL),      # too small
+    ((2048, 1.0, cmbx.F32, 1), cmbx.EINVAL),   # too large
+    ((64, 0.0, cmbx.F32, 1), cmbx.EINVAL),
+    ((64, -1.0, cmbx.F32, 1), cmbx.EINVAL),
+    ((64, float("nan"), cmbx.F32, 1), cmbx.EINVAL),
+    ((64, float("inf"), cmbx.F32, 1), cmbx.EINVAL),
+    ((64, 1.0, 3, 1), cmbx.EINVAL),
+    ((64, 1.0, cmbx.F32, 0), cmbx.EINVAL),
+    ((80, 1.0, cmbx.F32, 1), cmbx.EUNSUPPORTED),  # 2^4 * 5
+    ((36, 1.0, cmbx.F32, 1), cmbx.EUNSUPPORTED),  # 2^2 * 3^2: not compiled
+])
+def test_plan_box_rejects(L, args, code):
+    rc, h = _plan(*args)
+    assert rc == code and h is None
+    assert cmbx.last_error() != ""
+
+
+def test_null_arguments(L):
+    assert L.cmbx_plan_box(64, 1.0, cmbx.F32, 1, None) == cmbx.EINVAL
+    assert L.cmbx_spectrum_table(None, None, None, 2) == cmbx.EINVAL
+    assert L.cmbx_simulate_patch(None, 0, 0.4, None, 1, None) == cmbx.EINVAL
+    assert L.cmbx_debug_noise(None, 0, None) == cmbx.EINVAL
+    assert L.cmbx_debug_field(None, 0, None) == cmbx.EINVAL
+    assert L.cmbx_debug_gather(None, None, 0.1, None, 1, None) == cmbx.EINVAL
+    assert L.cmbx_plan_set(None, cmbx.OPT_INTERP, 1) == cmbx.EINVAL
+    assert L.cmbx_ensemble_create(None, 0, None) == cmbx.EINVAL
+    assert L.cmbx_ensemble_launch(None, None) == cmbx.EINVAL
+    assert L.cmbx_plan_destroy(None) == cmbx.OK
+    assert L.cmbx_ensemble_destroy(None) == cmbx.OK
+
+
+def test_valid_plan_without_device_reports_ehip(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    rc, h = _plan(64, 1.0, cmbx.F32, 1)
+    assert rc == cmbx.EHIP and h is None
+    assert "device" in cmbx.last_error()

@@ -1,0 +1,223 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar: the weighted half grid is bit-identical (FP64 path: to the oracle's FP64 modes; FP32
+path: to the oracle's modes rounded to FP32 factor by factor); fields and maps agree with
+the FP64 oracle to max|gpu - oracle| / rms(oracle) <= 1e-5 (FP32) and <= 1e-12 (FP64).
+"""
+import numpy as np
+import pytest
+
+from oracle import field as ofield
+from oracle import gather as ogather
+from oracle import noise as onoise
+from paper_2507_15703_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-12}
+NPDT = {"f32": np.float32, "f64": np.float64}
+
+
+@pytest.fixture(scope="module")
+def cmbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_15703_amd import cmbx as c
+    c.lib()
+    return c
+
+
+def _plan(cmbx, N, L, dt, batch=1, interp="trilinear", table=None):
+    p = cmbx.Plan(N, L, dt, batch=batch, interp=interp)
+    k, pk = table if table is not None else workloads.powerlaw_cutoff_table(N, L, kc_modes=max(2, N // 4))
+    p.spectrum_table(k, pk)
+    return p, (k, pk)
+
+
+def _rel(gpu, ref):
+    ref = np.asarray(ref, dtype=np.float64)
+    return np.max(np.abs(np.asarray(gpu, dtype=np.float64) - ref)) / np.sqrt(np.mean(ref**2))
+
+
+def _bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint32 if a.dtype in (np.float32, np.complex64) else np.uint64)
+
+
+# ------------------------------------------------------------------ noise (bit-exact)
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N", [8, 12, 16, 24, 48, 64])
+def test_noise_bit_exact(cmbx, N, dt):
+    L = 1.0 + N / 100.0
+    p, (k, pk) = _plan(cmbx, N, L, dt)
+    for seed in (0, 1, (5 << 32) | 77, 2**64 - 1):
+        gpu = p.debug_noise(seed).cpu().numpy()
+        ref = onoise.halfgrid(N, L, seed, k, pk, dtype=NPDT[dt])
+        assert np.array_equal(_bits(gpu), _bits(ref)), (N, dt, seed)
+    p.close()
+
+
+def test_noise_bit_exact_256(cmbx):
+    N, L = 256, 1.0
+    p, (k, pk) = _plan(cmbx, N, L, "f32")
+    gpu = p.debug_noise(1).cpu().numpy()
+    ref = onoise.halfgrid(N, L, 1, k, pk, dtype=np.float32)
+    assert np.array_equal(_bits(gpu), _bits(ref))
+    p.close()
+
+
+# ------------------------------------------------------------------ field
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N", [8, 12, 16, 24, 32, 48, 64, 96, 128])
+def test_field_matches_oracle(cmbx, N, dt):
+    L = 1.0
+    p, (k, pk) = _plan(cmbx, N, L, dt)
+    gpu = p.debug_field(7).cpu().numpy()
+    ref = ofield.field(onoise.halfgrid(N, L, 7, k, pk, dtype=np.float64))
+    assert _rel(gpu, ref) <= TOL[dt], (N, dt)
+    p.close()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N", [64, 384])
+def test_field_alt_tiles_agree(cmbx, N, dt):
+    """Every compiled tile shape gives the same field up to rounding (the compiler may
+    contract multiply-adds differently per instantiation)."""
+    p, (k, pk) = _plan(cmbx, N, 1.0, dt)
+    base = p.debug_field(3).cpu().numpy()
+    if N <= 64:
+        ref = ofield.field(onoise.halfgrid(N, 1.0, 3, k, pk))
+        assert _rel(base, ref) <= TOL[dt]
+    tried = 0
+    for txy, lz in [(16, 0), (8, 0), (4, 0), (2, 0), (0, 32), (0, 16), (0, 8), (0, 4), (0, 2)]:
+        try:
+            p.set_tiles(txy, lz)
+        except cmbx.CmbxError:
+            continue
+        tried += 1
+        err = _rel(p.debug_field(3).cpu().numpy(), base)
+        assert err <= (1e-6 if dt == "f32" else 1e-14), (txy, lz, err)
+    assert tried >= 2
+    p.close()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_field_256(cmbx, dt):
+    N, L = 256, 1.0
+    p, (k, pk) = _plan(cmbx, N, L, dt)
+    gpu = p.debug_field(1).cpu().numpy()
+    ref = ofield.field(onoise.halfgrid(N, L, 1, k, pk, dtype=np.float64), workers=-1)
+    assert _rel(gpu, ref) <= TOL[dt]
+    p.close()
+
+
+# ------------------------------------------------------------------ gather
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("interp", ["trilinear", "tricubic"])
+def test_gather_matches_oracle(cmbx, dt, interp):
+    N, L = 32, 2.0
+    p, _ = _plan(cmbx, N, L, dt, interp=interp)
+    rng = np.random.default_rng(9)
+    fld = rng.standard_normal((N, N, N))
+    ft = torch.tensor(fld.astype(NPDT[dt]), device="cuda")
+    cases = [
+        (0.7, workloads.random_directions(1000, 1)),
+        (0.9999, workloads.random_directions(257, 2)),          # stencils wrap at the edge
+        (0.25, np.array([[0, 0, 1.0], [1, 0, 0], [0, -1, 0]])),  # exactly on nodes: 0.25 * 32 / 2 = 4
+        (0.5, workloads.random_directions(1, 3)),                 # a single pixel
+    ]
+    for r, dirs in cases:
+        d = torch.tensor(dirs, device="cuda")
+        gpu = p.debug_gather(ft, r, d).cpu().numpy()
+        ref = ogather.gather(fld.astype(NPDT[dt]).astype(np.float64), L, r, dirs, interp)
+        assert _rel(gpu, ref) <= (2e-6 if dt == "f32" else 1e-13), (r, interp, dt)
+    p.close()
+
+
+# ------------------------------------------------------------------ end to end
+def test_simulate_config_small_fp64(cmbx):
+    """64^3 FP64, r = 0.4 L, cap 20 deg (128 x 512 pixels), trilinear, seed 0."""
+    N, L, r = 64, 1.0, 0.4
+    table = workloads.powerlaw_cutoff_table(N, L, kc_modes=16)
+    p, (k, pk) = _plan(cmbx, N, L, "f64", interp="trilinear", table=table)
+    dirs = workloads.cap_directions(20.0, 128, 512)
+    out = p.simulate_patch(0, r, torch.tensor(dirs, device="cuda")).cpu().numpy()
+    h = onoise.halfgrid(N, L, 0, k, pk)
+    ref = ogather.gather(ofield.field(h), L, r, dirs, "trilinear")
+    assert _rel(out[0], ref) <= 1e-12
+    p.close()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_simulate_batch_seeds(cmbx, dt):
+    """Realisation b of a batch uses seed + b; every realisation matches the oracle."""
+    N, L, r = 48, 1.0, 0.45
+    p, (k, pk) = _plan(cmbx, N, L, dt, batch=3, interp="tricubic")
+    dirs = workloads.cap_directions(35.0, 40, 77)
+    out = p.simulate_patch(100, r, torch.tensor(dirs, device="cuda")).cpu().numpy()
+    for b in range(3):
+        ref = ogather.gather(ofield.field(onoise.halfgrid(N, L, 100 + b, k, pk)), L, r, dirs, "tricubic")
+        assert _rel(out[b], ref) <= TOL[dt], b
+    p.close()
+
+
+def test_simulate_256_tricubic_fp32(cmbx):
+    """256^3 FP32, r = 0.45 L, cap 30 deg as 1024 x 1024 pixels, tricubic, seed 1."""
+    N, L, r = 256, 1.0, 0.45
+    p, (k, pk) = _plan(cmbx, N, L, "f32", interp="tricubic")
+    dirs = workloads.cap_directions(30.0, 1024, 1024)
+    out = p.simulate_patch(1, r, torch.tensor(dirs, device="cuda")).cpu().numpy()
+    fld = ofield.field(onoise.halfgrid(N, L, 1, k, pk), workers=-1)
+    ref = ogather.gather(fld, L, r, dirs, "tricubic")
+    assert _rel(out[0], ref) <= 1e-5
+    p.close()
+
+
+def test_errors_on_device(cmbx):
+    p = cmbx.Plan(16, 1.0, "f32")
+    d = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    d[:, 2] = 1
+    with pytest.raises(cmbx.CmbxError) as e:
+        p.simulate_patch(0, 0.3, d)
+    assert e.value.code == cmbx.ESTATE
+    k, pk = workloads.powerlaw_cutoff_table(16, 1.0)
+    p.spectrum_table(k, pk)
+    for bad_r in (0.0, -0.1, 0.5, 0.7):
+        with pytest.raises(cmbx.CmbxError) as e:
+            p.simulate_patch(0, bad_r, d)
+        assert e.value.code == cmbx.EINVAL
+    with pytest.raises(cmbx.CmbxError) as e:
+        p.spectrum_table(k[::-1].copy(), pk)
+    assert e.value.code == cmbx.EINVAL
+    with pytest.raises(cmbx.CmbxError):
+        p.set_tiles(5, 0)
+    p.close()
+
+
+# ------------------------------------------------------------------ ensemble (graph)
+def test_ensemble_graph_matches_plain(cmbx):
+    """The hipGraph ensemble of mixed sizes reproduces the plain path bit for bit."""
+    jobs = []
+    specs = [(32, 3, 12.0), (48, 2, 25.0), (32, 1, 33.0), (64, 2, 18.0)]
+    plans = {}
+    for i, (N, batch, th) in enumerate(specs):
+        key = (N, batch)
+        if key not in plans:
+            plans[key] = _plan(cmbx, N, 1.0, "f32", batch=batch, interp="tricubic")[0]
+        dirs = torch.tensor(workloads.cap_directions(th, 20, 64), device="cuda")
+        out = torch.empty((batch, dirs.shape[0]), dtype=torch.float32, device="cuda")
+        jobs.append(dict(plan=plans[key], seed=50 + 10 * i, r=0.45, dirs=dirs, out=out))
+    ens = cmbx.Ensemble(jobs)
+    for _ in range(3):
+        for j in jobs:
+            j["out"].fill_(float("nan"))
+        ens.launch()
+        torch.cuda.synchronize()
+        for j in jobs:
+            ref = j["plan"].simulate_patch(j["seed"], j["r"], j["dirs"])
+            torch.cuda.synchronize()
+            assert torch.equal(j["out"], ref)
+    ens.close()
+    for p in plans.values():
+        p.close()
