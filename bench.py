@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the partial-sky box simulator on one MI355X.
+
+Workload: the 512^3 part of the mixed-size ensemble -- four FP32 boxes of side L = 1,
+each with its own seed, shell radius r = 0.45 L, a polar cap of half-angle drawn
+uniformly in [10, 40] deg (n_ring = round(25.6 theta) rings x 1024 or 2048 pixels) and
+tricubic sampling. One step = one pass of the whole hot path (noise + inverse 3-D FFT +
+sphere gather) over the four boxes, i.e. four maps. The batched path replays the four
+independent kernel chains as one HIP graph; the plain path runs the same jobs one after
+another through cmbx_simulate_patch on one stream. Inputs (directions, spectrum tables)
+are resident in device memory before timing starts.
+
+Prints one JSON line (see the keys below). ``--gpus`` above 1 is refused: this build
+measures one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "maps/s batched FP32 vs plain at 512³ box+cap sample, px err≤1e-5; HBM %peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def build_jobs(torch, cmbx, workloads, n_boxes):
+    jobs = [j for j in workloads.ensemble_jobs() if j["N"] == 512][:n_boxes]
+    out = []
+    for j in jobs:
+        N, L = j["N"], 1.0
+        plan = cmbx.Plan(N, L, "f32", batch=1, interp="tricubic")
+        k, p = workloads.powerlaw_cutoff_table(N, L, kc_modes=N / 4)
+        plan.spectrum_table(k, p * j["amp"])
+        dirs = torch.tensor(workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"]), device="cuda")
+        res = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
+        out.append(dict(plan=plan, seed=j["seed"], r=j["r_over_L"] * L, dirs=dirs, out=res,
+                        theta=j["theta_deg"], n_pix=int(dirs.shape[0])))
+    return out
+
+
+def cpu_baseline(jobs_meta, frac_planes=16):
+    """The FP64 oracle on a bounded sample of the same workload, scaled to maps/s.
+
+    Sample: the noise of N / frac_planes x-planes of one 512^3 box and the gather of
+    1 / frac_planes of its pixels (both scale linearly), plus the full-size inverse FFT.
+    """
+    import numpy as np
+    import scipy.fft
+
+    from oracle import gather as ogather
+    from oracle import noise as onoise
+    from oracle import spectrum as ospec
+    from paper_2507_15703_amd import workloads
+
+    j = jobs_meta[0]
+    N, L = 512, 1.0
+    k, p = workloads.powerlaw_cutoff_table(N, L, kc_modes=N / 4)
+    workers = len(os.sched_getaffinity(0))
+    nplanes = N // frac_planes
+    t0 = time.perf_counter()
+    half, _ = ospec.weight_tables(N, L, k, p)
+    g_re, g_im = onoise.unit_normals(N, j["seed"], np.arange(nplanes))
+    m = ospec.mode_m(N)[:nplanes]
+    sample = half[m] * (g_re + 1j * g_im)
+    t_noise = (time.perf_counter() - t0) * frac_planes
+    h = np.zeros((N, N, N // 2 + 1), dtype=np.complex128)
+    h[:nplanes] = sample
+    del sample, g_re, g_im, m
+    t0 = time.perf_counter()
+    fld = scipy.fft.irfftn(h, s=(N, N, N), axes=(0, 1, 2), norm="forward", workers=workers)
+    t_fft = time.perf_counter() - t0
+    del h
+    dirs = workloads.cap_directions(j["theta"], int(round(25.6 * j["theta"])), 1024 if j["theta"] <= 20 else 2048)
+    sub = dirs[:: frac_planes]
+    t0 = time.perf_counter()
+    ogather.gather(fld, L, j["r"], sub, "tricubic")
+    t_gather = (time.perf_counter() - t0) * (len(dirs) / len(sub))
+    sec = t_noise + t_fft + t_gather
+    return {"value": 1.0 / sec, "unit": "maps/s", "cores": workers, "kind": "oracle",
+            "sample": (f"one 512^3 FP64 map of the workload: noise of {nplanes}/{N} x-planes x{frac_planes}, "
+                       f"full inverse FFT (scipy, {workers} workers), tricubic gather of 1/{frac_planes} of "
+                       f"{len(dirs)} pixels x{frac_planes}; est. {sec:.1f} s/map "
+                       f"(noise {t_noise:.1f}, fft {t_fft:.1f}, gather {t_gather:.1f})")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--boxes", type=int, default=4, help="512^3 boxes per step (<= 4)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): independent realisations "
+              "shard across GPUs with no communication; run one process per GPU instead.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2507_15703_amd import cmbx, workloads
+
+    torch.cuda.set_device(0)
+    jobs = build_jobs(torch, cmbx, workloads, args.boxes)
+    nmaps = len(jobs)
+    ens = cmbx.Ensemble([dict(plan=j["plan"], seed=j["seed"], r=j["r"], dirs=j["dirs"], out=j["out"]) for j in jobs])
+
+    def step_batched():
+        ens.launch()
+
+    def step_plain():
+        for j in jobs:
+            j["plan"].simulate_patch(j["seed"], j["r"], j["dirs"], j["out"])
+
+    def timed(step, K, W):
+        for _ in range(W):
+            step()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(s)
+        for _ in range(K):
+            step()
+        e1.record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / 1e3, wall
+
+    print(f"[bench] {nmaps} x 512^3 FP32 boxes, pixels {[j['n_pix'] for j in jobs]}", file=sys.stderr, flush=True)
+    ev_b, wall_b = timed(step_batched, args.steps, args.warmup)
+    print(f"[bench] batched: {ev_b * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    ev_p, wall_p = timed(step_plain, args.steps, args.warmup)
+    print(f"[bench] plain:   {ev_p * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    sec_b = max(ev_b, 1e-12)
+    value = nmaps * args.steps / sec_b
+    plain = nmaps * args.steps / max(ev_p, 1e-12)
+
+    # per-kernel durations (HIP events on the plan's stream, the stream they run on)
+    j0 = jobs[0]
+    ms = j0["plan"].time_passes(j0["seed"], j0["r"], j0["dirs"], j0["out"], reps=args.kernel_reps)
+    N = 512
+    field_bytes = 4 * N**3
+    kbytes = [field_bytes, 2 * field_bytes, 2 * field_bytes, 28 * j0["n_pix"]]
+    names = ["pass_x_noise", "pass_y", "pass_z_c2r", "gather_tricubic"]
+    kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
+               for n, t, b in zip(names, ms, kbytes)}
+    # dominant HBM-bound kernel among the FFT passes
+    dom = max(range(3), key=lambda i: ms[i])
+    ach = kbytes[dom] / (ms[dom] * 1e-3) / 1e9
+    roofline = {"kernel": names[dom], "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    map_bytes = 20 * N**3 + sum(28 * j["n_pix"] for j in jobs) / nmaps
+    path_gbs = map_bytes * value / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec_b * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{nmaps}x512^3 FP32 batched (one hipGraph), r=0.45L, caps U[10,40] deg, tricubic",
+                   "boxes": nmaps, "N": N, "pixels": [j["n_pix"] for j in jobs], "maps_per_step": nmaps},
+        "plain_maps_per_s": round(plain, 2),
+        "batched_over_plain": round(value / plain, 3),
+        "wall_s": {"batched": round(wall_b, 4), "plain": round(wall_p, 4)},
+        "path_GBps_alg": round(path_gbs, 1),
+        "path_hbm_frac_alg": round(path_gbs / HBM_PEAK_GBS, 4),
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(jobs)
+    for j in jobs:
+        j["plan"].close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

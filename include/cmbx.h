@@ -135,9 +135,26 @@ int cmbx_ensemble_destroy(cmbx_ensemble* ens);
 int cmbx_debug_noise(cmbx_plan* plan, uint64_t seed, void* halfgrid);
 /* Run noise + inverse FFT for one realisation into `field`: device real [N][N][N]. */
 int cmbx_debug_field(cmbx_plan* plan, uint64_t seed, void* field);
+/* Run the first `npasses` (1..3) kernels of the field computation for realisation `seed`
+ * into `buf` (device, N^3 reals of the plan's precision). After pass 1 (x) and pass 2 (y)
+ * buf holds complex [N][N][N/2]: the half grid transformed along x (and y), with column
+ * iz = 0 carrying Z(iz=0) + i Z(iz=N/2); after pass 3 it is the real field. */
+int cmbx_debug_passes(cmbx_plan* plan, uint64_t seed, int npasses, void* buf);
 /* Interpolate a caller-given device field [N][N][N] (plan precision) at the pixels. */
 int cmbx_debug_gather(cmbx_plan* plan, const void* field, double r, const double* dirs,
                       int64_t n_pix, void* out);
+
+/*
+ * Time each kernel of the hot path for realisation `seed` of the plan (its first batch
+ * slot): every kernel is launched `reps` times in a row on the plan's stream between two
+ * HIP events, and ms[i] receives the average duration in milliseconds of kernel i:
+ * ms[0] pass x (noise + x transform), ms[1] pass y, ms[2] pass z (complex-to-real),
+ * ms[3] gather into out[0 .. n_pix). Synchronises the plan's stream; the workspace and
+ * out hold one realisation afterwards. Errors: as cmbx_simulate_patch, CMBX_EINVAL for
+ * reps < 1 or ms == NULL.
+ */
+int cmbx_time_passes(cmbx_plan* plan, uint64_t seed, double r, const double* dirs, int64_t n_pix,
+                     void* out, int reps, double* ms);
 
 /* Message of the calling thread's last failed call ("" if none). Valid until its next call. */
 const char* cmbx_last_error(void);

@@ -59,6 +59,8 @@ def lib():
             "cmbx_debug_noise": (I, [P, U64, P]),
             "cmbx_debug_field": (I, [P, U64, P]),
             "cmbx_debug_gather": (I, [P, P, D, P, I64, P]),
+            "cmbx_debug_passes": (I, [P, U64, I, P]),
+            "cmbx_time_passes": (I, [P, U64, D, P, I64, P, I, ctypes.POINTER(D)]),
             "cmbx_last_error": (ctypes.c_char_p, []),
             "cmbx_version": (ctypes.c_char_p, []),
         }
@@ -223,6 +225,13 @@ class Plan:
         simulate_patch(self.handle, seed, r, d, n_pix, o)
         return out
 
+    def time_passes(self, seed, r, dirs, out, reps=10):
+        """Average ms of (pass x, pass y, pass z, gather) over ``reps`` launches each."""
+        d, o, n_pix = self._check_dirs_out(dirs, out)
+        ms = (ctypes.c_double * 4)()
+        _check(lib().cmbx_time_passes(self.handle, int(seed), float(r), d, n_pix, o, int(reps), ms))
+        return list(ms)
+
     def debug_noise(self, seed):
         import torch
         ctype = torch.complex64 if self.dtype == F32 else torch.complex128
@@ -235,6 +244,18 @@ class Plan:
         f = torch.empty((self.N, self.N, self.N), dtype=self.torch_dtype, device="cuda")
         debug_field(self.handle, seed, f.data_ptr())
         return f
+
+    def debug_passes(self, seed, npasses):
+        """Workspace after the first ``npasses`` kernels: complex [N][N][N/2] for 1-2 passes,
+        real [N][N][N] after 3."""
+        import torch
+        ctype = torch.complex64 if self.dtype == F32 else torch.complex128
+        if npasses < 3:
+            b = torch.empty((self.N, self.N, self.N // 2), dtype=ctype, device="cuda")
+        else:
+            b = torch.empty((self.N, self.N, self.N), dtype=self.torch_dtype, device="cuda")
+        _check(lib().cmbx_debug_passes(self.handle, int(seed), int(npasses), b.data_ptr()))
+        return b
 
     def debug_gather(self, field, r, dirs, out=None):
         import torch

@@ -358,6 +358,19 @@ int cmbx_debug_field(cmbx_plan* p, uint64_t seed, void* field) {
   return ok();
 }
 
+int cmbx_debug_passes(cmbx_plan* p, uint64_t seed, int npasses, void* buf) {
+  if (int rc = check_plan(p)) return rc;
+  if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set");
+  if (!buf) return fail(CMBX_EINVAL, "buf is NULL");
+  if (npasses < 1 || npasses > 3) return fail(CMBX_EINVAL, "npasses = %d must be 1, 2 or 3", npasses);
+  DeviceGuard g(p->device);
+  const cmbx::FieldArgs a = field_args(p, seed, buf);
+  HIP_TRY(cmbx::launch_pass_x(a, p->stream));
+  if (npasses >= 2) HIP_TRY(cmbx::launch_pass_y(a, p->stream));
+  if (npasses >= 3) HIP_TRY(cmbx::launch_pass_z(a, p->stream));
+  return ok();
+}
+
 int cmbx_debug_gather(cmbx_plan* p, const void* field, double r, const double* dirs, int64_t n_pix, void* out) {
   if (int rc = check_plan(p)) return rc;
   if (!field) return fail(CMBX_EINVAL, "field is NULL");
@@ -453,6 +466,38 @@ int cmbx_ensemble_destroy(cmbx_ensemble* en) {
   if (en->exec) (void)hipGraphExecDestroy(en->exec);
   if (en->graph) (void)hipGraphDestroy(en->graph);
   delete en;
+  return ok();
+}
+
+int cmbx_time_passes(cmbx_plan* p, uint64_t seed, double r, const double* dirs, int64_t n_pix, void* out, int reps,
+                     double* ms) {
+  if (int rc = check_plan(p)) return rc;
+  if (int rc = check_patch_args(p, r, dirs, n_pix, out)) return rc;
+  if (reps < 1 || !ms) return fail(CMBX_EINVAL, "reps must be >= 1 and ms non-NULL");
+  DeviceGuard g(p->device);
+  hipEvent_t ev[5] = {};
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  const cmbx::FieldArgs a = field_args(p, seed, p->field);
+  int rc = CMBX_OK;
+  hipError_t e = hipEventRecord(ev[0], p->stream);
+  for (int i = 0; e == hipSuccess && i < reps; ++i) e = cmbx::launch_pass_x(a, p->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
+  for (int i = 0; e == hipSuccess && i < reps; ++i) e = cmbx::launch_pass_y(a, p->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], p->stream);
+  for (int i = 0; e == hipSuccess && i < reps; ++i) e = cmbx::launch_pass_z(a, p->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], p->stream);
+  for (int i = 0; e == hipSuccess && rc == CMBX_OK && i < reps; ++i)
+    rc = enqueue_gather(p, p->field, r, dirs, n_pix, out, p->stream);
+  if (e == hipSuccess && rc == CMBX_OK) e = hipEventRecord(ev[4], p->stream);
+  if (e == hipSuccess && rc == CMBX_OK) e = hipEventSynchronize(ev[4]);
+  for (int i = 0; e == hipSuccess && rc == CMBX_OK && i < 4; ++i) {
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+    ms[i] = (double)t / reps;
+  }
+  for (auto& ee : ev) (void)hipEventDestroy(ee);
+  if (rc != CMBX_OK) return rc;
+  if (e != hipSuccess) return fail(CMBX_EHIP, "pass timing: %s", hipGetErrorString(e));
   return ok();
 }
 

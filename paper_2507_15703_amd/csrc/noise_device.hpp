@@ -48,6 +48,15 @@ constexpr uint64_t kRsqrtMagic = 0x5FE6EB50C7B537A9ull;
 
 constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }  // exact up to 18!
 constexpr double sgn(int k) { return (k & 1) ? -1.0 : 1.0; }
+// Series coefficients, evaluated at compile time (each the correctly rounded quotient).
+// kSin[k] = (-1)^k / (2k+1)!, kCos[k] = (-1)^k / (2k)!, kAtanh[k] = 1 / (2k+1).
+constexpr double kSin[9] = {1.0, sgn(1) / fact(3), sgn(2) / fact(5), sgn(3) / fact(7), sgn(4) / fact(9),
+                            sgn(5) / fact(11), sgn(6) / fact(13), sgn(7) / fact(15), sgn(8) / fact(17)};
+constexpr double kCos[10] = {1.0, sgn(1) / fact(2), sgn(2) / fact(4), sgn(3) / fact(6), sgn(4) / fact(8),
+                             sgn(5) / fact(10), sgn(6) / fact(12), sgn(7) / fact(14), sgn(8) / fact(16),
+                             sgn(9) / fact(18)};
+constexpr double kAtanh[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0 / 9.0, 1.0 / 11.0,
+                               1.0 / 13.0, 1.0 / 15.0, 1.0 / 17.0, 1.0 / 19.0, 1.0 / 21.0};
 }  // namespace bm
 
 // (g_re, g_im) = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) by the fixed sequence above.
@@ -69,17 +78,9 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& g_re,
   for (int i = 0; i < 5; ++i) y = y * (2.0 - d * y);
   const double s = (m - 1.0) * y;
   const double s2 = s * s;
-  double p = 1.0 / 21.0;
-  p = p * s2 + 1.0 / 19.0;
-  p = p * s2 + 1.0 / 17.0;
-  p = p * s2 + 1.0 / 15.0;
-  p = p * s2 + 1.0 / 13.0;
-  p = p * s2 + 1.0 / 11.0;
-  p = p * s2 + 1.0 / 9.0;
-  p = p * s2 + 1.0 / 7.0;
-  p = p * s2 + 1.0 / 5.0;
-  p = p * s2 + 1.0 / 3.0;
-  p = p * s2 + 1.0;
+  double p = kAtanh[10];
+#pragma unroll
+  for (int k = 9; k >= 0; --k) p = p * s2 + kAtanh[k];
   const double lnm = (s + s) * p;
   const double ef = (double)e;
   const double lnu = ef * kLn2Head + (ef * kLn2Tail + lnm);
@@ -97,34 +98,23 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& g_re,
   const uint32_t rho = swap ? (1u << 30) - rr : rr;
   const double t = (double)rho * kTwoPi2m32;
   const double t2 = t * t;
-  double ps = sgn(8) / fact(17);
-  ps = ps * t2 + sgn(7) / fact(15);
-  ps = ps * t2 + sgn(6) / fact(13);
-  ps = ps * t2 + sgn(5) / fact(11);
-  ps = ps * t2 + sgn(4) / fact(9);
-  ps = ps * t2 + sgn(3) / fact(7);
-  ps = ps * t2 + sgn(2) / fact(5);
-  ps = ps * t2 + sgn(1) / fact(3);
-  ps = ps * t2 + 1.0;
+  double ps = kSin[8];
+#pragma unroll
+  for (int k = 7; k >= 0; --k) ps = ps * t2 + kSin[k];
   const double st = t * ps;
-  double pc = sgn(9) / fact(18);
-  pc = pc * t2 + sgn(8) / fact(16);
-  pc = pc * t2 + sgn(7) / fact(14);
-  pc = pc * t2 + sgn(6) / fact(12);
-  pc = pc * t2 + sgn(5) / fact(10);
-  pc = pc * t2 + sgn(4) / fact(8);
-  pc = pc * t2 + sgn(3) / fact(6);
-  pc = pc * t2 + sgn(2) / fact(4);
-  pc = pc * t2 + sgn(1) / fact(2);
-  pc = pc * t2 + 1.0;
+  double pc = kCos[9];
+#pragma unroll
+  for (int k = 8; k >= 0; --k) pc = pc * t2 + kCos[k];
   const double ct = pc;
   const double si = swap ? ct : st;  // in-quadrant sine and cosine
   const double ci = swap ? st : ct;
-  double sn, cs;
-  if (q == 0) { sn = si; cs = ci; }
-  else if (q == 1) { sn = ci; cs = -si; }
-  else if (q == 2) { sn = -si; cs = -ci; }
-  else { sn = -ci; cs = si; }
+  // quadrant q: (sin, cos) = (si, ci), (ci, -si), (-si, -ci), (-ci, si) for q = 0..3,
+  // formed with selects and sign flips only (no divergent branches)
+  const bool odd = (q & 1u) != 0u;
+  double sn = odd ? ci : si;
+  double cs = odd ? si : ci;
+  sn = (q & 2u) ? -sn : sn;
+  cs = ((q + 1u) & 2u) ? -cs : cs;
   g_re = rad * cs;
   g_im = rad * sn;
 }
@@ -158,26 +148,30 @@ __device__ __forceinline__ cpx<T> mode_value(int N, int ix, int iy, int iz, uint
                                              const T* __restrict__ wh, const T* __restrict__ wself) {
   const int M = N / 2;
   const int m = freq2(ix, N) + freq2(iy, N) + iz * iz;
-  if (iz != 0 && iz != M) {
-    const uint2 w = mode_words(k0, k1, ix, iy, iz);
-    return weighted<T>(wh[m], w.x, w.y);
+  int sx = ix, sy = iy;  // mode whose words are drawn
+  bool cj = false, self = false;
+  if (iz == 0 || iz == M) {
+    const int px = ix == 0 ? 0 : N - ix;
+    const int py = iy == 0 ? 0 : N - iy;
+    const int own = ix * N + iy, par = px * N + py;
+    if (own == par) {
+      self = true;
+    } else if (own > par) {
+      sx = px;
+      sy = py;
+      cj = true;
+    }
   }
-  const int px = ix == 0 ? 0 : N - ix;
-  const int py = iy == 0 ? 0 : N - iy;
-  const int own = ix * N + iy, par = px * N + py;
-  if (own == par) {
-    const uint2 w = mode_words(k0, k1, ix, iy, iz);
-    double gr, gi;
-    box_muller(w.x, w.y, gr, gi);
+  const uint2 w = mode_words(k0, k1, sx, sy, iz);
+  double gr, gi;
+  box_muller(w.x, w.y, gr, gi);
+  if (self) {
     const int c = (ix == M) + (iy == M) + (iz == M);
     return {wself[c] * (T)gr, T(0)};
   }
-  if (own < par) {
-    const uint2 w = mode_words(k0, k1, ix, iy, iz);
-    return weighted<T>(wh[m], w.x, w.y);
-  }
-  const uint2 w = mode_words(k0, k1, px, py, iz);
-  return conj(weighted<T>(wh[m], w.x, w.y));
+  const T wv = wh[m];
+  const cpx<T> v = {wv * (T)gr, wv * (T)gi};
+  return cj ? conj(v) : v;
 }
 
 }  // namespace cmbx
