@@ -35,10 +35,11 @@ def build_jobs(torch, cmbx, workloads, n_boxes):
         plan = cmbx.Plan(N, L, "f32", batch=1, interp="tricubic")
         k, p = workloads.powerlaw_cutoff_table(N, L, kc_modes=N / 4)
         plan.spectrum_table(k, p * j["amp"])
+        tuned = plan.autotune(reps=5)
         dirs = torch.tensor(workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"]), device="cuda")
         res = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
         out.append(dict(plan=plan, seed=j["seed"], r=j["r_over_L"] * L, dirs=dirs, out=res,
-                        theta=j["theta_deg"], n_pix=int(dirs.shape[0])))
+                        theta=j["theta_deg"], n_pix=int(dirs.shape[0]), tuned=tuned))
     return out
 
 
@@ -179,6 +180,7 @@ def main():
         "path_GBps_alg": round(path_gbs, 1),
         "path_hbm_frac_alg": round(path_gbs / HBM_PEAK_GBS, 4),
         "kernels": kernels,
+        "tiles": {k: jobs[0]["tuned"][k] for k in ("tile_x", "tile_y", "lines_z")},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -57,8 +57,10 @@ extern "C" {
 /* plan options for cmbx_plan_set */
 #define CMBX_OPT_INTERP   1 /* CMBX_TRILINEAR (default) or CMBX_TRICUBIC */
 #define CMBX_OPT_STREAM   2 /* hipStream_t cast to int64_t (0 = the null stream); -1 = the plan's own stream (default) */
-#define CMBX_OPT_TILE_XY  3 /* columns per workgroup of the x/y passes; 0 = tuned default */
-#define CMBX_OPT_LINES_Z  4 /* lines per workgroup of the z pass; 0 = tuned default */
+#define CMBX_OPT_TILE_XY  3 /* columns per workgroup of both the x and y passes; 0 = default */
+#define CMBX_OPT_LINES_Z  4 /* lines per workgroup of the z pass; 0 = default */
+#define CMBX_OPT_TILE_X   5 /* columns per workgroup of the x pass (noise + x transform) */
+#define CMBX_OPT_TILE_Y   6 /* columns per workgroup of the y pass */
 
 typedef struct cmbx_plan cmbx_plan;
 typedef struct cmbx_ensemble cmbx_ensemble;
@@ -155,6 +157,19 @@ int cmbx_debug_gather(cmbx_plan* plan, const void* field, double r, const double
  */
 int cmbx_time_passes(cmbx_plan* plan, uint64_t seed, double r, const double* dirs, int64_t n_pix,
                      void* out, int reps, double* ms);
+
+/*
+ * Autotune the plan's workgroup shapes: for each of the three field kernels, every
+ * compiled tile choice (cmbx_tile_choices) is launched `reps` times on the plan's stream
+ * and timed with HIP events; the fastest is kept as the plan's option. best[0..2]
+ * receives (tile_x, tile_y, lines_z) and ms[0..2] their average milliseconds (either may
+ * be NULL). Needs a spectrum (CMBX_ESTATE otherwise); overwrites the first workspace slot;
+ * synchronises the plan's stream.
+ */
+int cmbx_plan_autotune(cmbx_plan* plan, int reps, int* best, double* ms);
+/* Compiled tile choices for (dtype, N): which = 0 for the x/y column tiles, 1 for the z
+ * lines. Writes up to 4 values to out and returns their count (0 if none). */
+int cmbx_tile_choices(int dtype, int N, int which, int* out);
 
 /* Message of the calling thread's last failed call ("" if none). Valid until its next call. */
 const char* cmbx_last_error(void);

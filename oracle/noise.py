@@ -16,20 +16,26 @@ canonical stream (``philox.mode_words`` then ``normal.box_muller``):
                            above and the other is its complex conjugate;
 * self-conjugate modes     (ix, iy in {0, N/2} on those planes): T = full[m] g_re, real.
 
-In single precision each factor is rounded to FP32 first and the product is an FP32
-multiply, so the result is reproducible bit for bit.
+In single precision the normal pair comes from the binary32 transform
+(``normal.box_muller_f32``), the weight is rounded to FP32 and the product is an FP32
+multiply; in double precision everything is binary64. Either way the result is
+reproducible bit for bit.
 """
 import numpy as np
 
 from . import normal, philox, spectrum
 
 
-def unit_normals(N, seed, ix):
+def _pair(a, b, rdt):
+    return normal.box_muller_f32(a, b) if rdt == np.float32 else normal.box_muller(a, b)
+
+
+def unit_normals(N, seed, ix, dtype=np.float64):
     """(g_re, g_im) for x-index array ``ix`` (1-D) and all iy, iz; shape (len(ix), N, N/2 + 1)."""
     ix = np.asarray(ix)
     gx, gy, gz = np.meshgrid(ix, np.arange(N), np.arange(N // 2 + 1), indexing="ij")
     a, b = philox.mode_words(seed, gx, gy, gz)
-    return normal.box_muller(a, b)
+    return _pair(a, b, np.dtype(dtype))
 
 
 def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32):
@@ -45,10 +51,10 @@ def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32):
     out = np.empty((N, N, N // 2 + 1), dtype=cdt)
     for x0 in range(0, N, chunk):
         x1 = min(N, x0 + chunk)
-        g_re, g_im = unit_normals(N, seed, np.arange(x0, x1))
+        g_re, g_im = unit_normals(N, seed, np.arange(x0, x1), rdt)
         w = half[m_all[x0:x1]]
-        out[x0:x1].real = w * g_re.astype(rdt)
-        out[x0:x1].imag = w * g_im.astype(rdt)
+        out[x0:x1].real = w * g_re
+        out[x0:x1].imag = w * g_im
     _hermitian_planes(out, N, seed, full, rdt)
     return out
 
@@ -66,9 +72,9 @@ def _hermitian_planes(out, N, seed, full, rdt):
         selfc = own == partner
         sx, sy = ix[selfc], iy[selfc]
         a, b = philox.mode_words(seed, sx, sy, np.full(sx.shape, iz))
-        g_re, _ = normal.box_muller(a, b)
+        g_re, _ = _pair(a, b, rdt)
         m = (np.minimum(sx, N - sx) ** 2 + np.minimum(sy, N - sy) ** 2 + iz * iz).astype(np.int64)
-        new[selfc] = (full[m] * g_re.astype(rdt)).astype(rdt)
+        new[selfc] = full[m] * g_re
         out[:, :, iz] = new
 
 

@@ -114,3 +114,95 @@ def box_muller(a, b):
     rad = canonical_sqrt(x)
     sin, cos = canonical_sincos_2pi(b)
     return rad * cos, rad * sin
+
+
+# ---------------------------------------------------------------------------------------
+# Single-precision variant (the FP32 path's noise). Same structure, every operation an
+# IEEE-754 binary32 add, subtract or multiply, shorter series sized to binary32:
+#   ln u1: a + 1 = v (up to 2^32) is cut to its leading 24 bits, v = mi 2^(e - 23) with
+#     mi in [2^23, 2^24), so m = mi 2^-23 in [1, 2) is exact in binary32 (relative change
+#     of u1 below 2^-23); then as above with four Newton steps for 1/(m + 1) and the
+#     artanh series to s^8; ln 2 split into a 16-bit head and a tail.
+#   sqrt x: three Newton steps from 0x5F3759DF - (bits(x) >> 1).
+#   sin t: series to t^9; cos t: series to t^10; t = rho (2 pi / 2^32), rho <= 2^29
+#     rounded to binary32.
+# Coefficients are the binary64 quotients rounded to binary32.
+F32 = np.float32
+LN2_HI_F = F32(float.fromhex("0x1.62e4p-1"))
+LN2_LO_F = F32(float.fromhex("0x1.7f7d1cp-20"))
+SQRT2_F = F32(float.fromhex("0x1.6a09e6p+0"))
+TWO_PI_2M32_F = F32(float.fromhex("0x1.921fb6p-30"))
+RSQRT_MAGIC_F = np.uint32(0x5F3759DF)
+_ATANH_CF = [F32(1.0 / (2 * k + 1)) for k in range(5)]
+_SIN_CF = [F32(c) for c in _SIN_C[:5]]
+_COS_CF = [F32(c) for c in _COS_C[:6]]
+
+
+def canonical_log_u1_f32(a):
+    """ln((a + 1) 2^-32) in binary32 by the fixed operation sequence."""
+    a = np.asarray(a, dtype=np.uint64)
+    v = a + np.uint64(1)                                 # 1 .. 2^32
+    _, ex = np.frexp(v.astype(np.float64))               # exact exponent: v in [2^(ex-1), 2^ex)
+    e0 = ex.astype(np.int64) - 1
+    sh = e0 - 23
+    mi = np.where(sh >= 0, v >> np.maximum(sh, 0).astype(np.uint64),
+                  v << np.maximum(-sh, 0).astype(np.uint64))       # [2^23, 2^24)
+    m = mi.astype(F32) * F32(2.0**-23)                   # [1, 2), exact
+    big = m >= SQRT2_F
+    m = np.where(big, m * F32(0.5), m)
+    e = np.where(big, e0 + 1, e0) - 32
+    d = m + F32(1.0)
+    y = np.full_like(d, F32(0.5))
+    for _ in range(4):
+        y = y * (F32(2.0) - d * y)
+    s = (m - F32(1.0)) * y
+    s2 = s * s
+    p = np.full_like(s, _ATANH_CF[4])
+    for k in range(3, -1, -1):
+        p = p * s2 + _ATANH_CF[k]
+    lnm = (s + s) * p
+    ef = e.astype(F32)
+    return ef * LN2_HI_F + (ef * LN2_LO_F + lnm)
+
+
+def canonical_sqrt_f32(x):
+    x = np.asarray(x, dtype=F32)
+    bits = x.view(np.uint32)
+    y = (RSQRT_MAGIC_F - (bits >> np.uint32(1))).view(F32)
+    hx = F32(0.5) * x
+    for _ in range(3):
+        y = y * (F32(1.5) - hx * (y * y))
+    r = x * y
+    return np.where(x == F32(0.0), F32(0.0), r).astype(F32)
+
+
+def canonical_sincos_2pi_f32(b):
+    b = np.asarray(b, dtype=np.uint64)
+    q = b >> np.uint64(30)
+    r = b & np.uint64(0x3FFFFFFF)
+    swap = r >= np.uint64(1 << 29)
+    rho = np.where(swap, np.uint64(1 << 30) - r, r)
+    t = rho.astype(F32) * TWO_PI_2M32_F
+    t2 = t * t
+    ps = np.full_like(t, _SIN_CF[4])
+    for k in range(3, -1, -1):
+        ps = ps * t2 + _SIN_CF[k]
+    st = t * ps
+    pc = np.full_like(t, _COS_CF[5])
+    for k in range(4, -1, -1):
+        pc = pc * t2 + _COS_CF[k]
+    ct = pc
+    s_in = np.where(swap, ct, st)
+    c_in = np.where(swap, st, ct)
+    sin = np.select([q == 0, q == 1, q == 2], [s_in, c_in, -s_in], -c_in).astype(F32)
+    cos = np.select([q == 0, q == 1, q == 2], [c_in, -s_in, -c_in], s_in).astype(F32)
+    return sin, cos
+
+
+def box_muller_f32(a, b):
+    """Unit normal pair (g_re, g_im), binary32, from word arrays a and b."""
+    lnu = canonical_log_u1_f32(a)
+    x = -(lnu + lnu)
+    rad = canonical_sqrt_f32(x)
+    sin, cos = canonical_sincos_2pi_f32(b)
+    return rad * cos, rad * sin

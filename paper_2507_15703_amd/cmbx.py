@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libcmbx.so")
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 F32, F64 = 1, 2
 TRILINEAR, TRICUBIC = 1, 2
-OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z = 1, 2, 3, 4
+OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y = 1, 2, 3, 4, 5, 6
 
 _DTYPES = {"f32": F32, "float32": F32, F32: F32, "f64": F64, "float64": F64, F64: F64}
 _INTERPS = {"trilinear": TRILINEAR, "tricubic": TRICUBIC, TRILINEAR: TRILINEAR, TRICUBIC: TRICUBIC}
@@ -61,6 +61,8 @@ def lib():
             "cmbx_debug_gather": (I, [P, P, D, P, I64, P]),
             "cmbx_debug_passes": (I, [P, U64, I, P]),
             "cmbx_time_passes": (I, [P, U64, D, P, I64, P, I, ctypes.POINTER(D)]),
+            "cmbx_plan_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
+            "cmbx_tile_choices": (I, [I, I, I, ctypes.POINTER(I)]),
             "cmbx_last_error": (ctypes.c_char_p, []),
             "cmbx_version": (ctypes.c_char_p, []),
         }
@@ -180,12 +182,49 @@ class Plan:
         self.interp = _INTERPS[interp]
         plan_set(self.handle, OPT_INTERP, self.interp)
 
-    def set_tiles(self, tile_xy=0, lines_z=0):
+    def set_tiles(self, tile_xy=0, lines_z=0, tile_x=None, tile_y=None):
+        """Workgroup tile shapes (0 = compiled default); tile_x / tile_y override tile_xy."""
         plan_set(self.handle, OPT_TILE_XY, tile_xy)
+        if tile_x is not None:
+            plan_set(self.handle, OPT_TILE_X, tile_x)
+        if tile_y is not None:
+            plan_set(self.handle, OPT_TILE_Y, tile_y)
         plan_set(self.handle, OPT_LINES_Z, lines_z)
 
     def spectrum_table(self, k, p_inf):
         spectrum_table(self.handle, k, p_inf)
+
+    def autotune(self, reps=5, cache_path=None, use_cache=True):
+        """Choose the fastest compiled tile shapes of the three field kernels (timed on the
+        device by cmbx_plan_autotune) and remember them in a JSON cache keyed by
+        (arch, N, precision). A cached entry is reused if every value is still a compiled
+        choice; otherwise the plan is re-tuned. Returns dict(tile_x, tile_y, lines_z, ms)."""
+        import json
+        path = cache_path or TUNE_CACHE
+        key = f"gfx950:N{self.N}:{'f32' if self.dtype == F32 else 'f64'}"
+        cache = _load_cache(path) if use_cache else {}
+        ent = cache.get(key)
+        txy = tile_choices(self.dtype, self.N, 0)
+        tz = tile_choices(self.dtype, self.N, 1)
+        if (isinstance(ent, dict) and ent.get("tile_x") in txy and ent.get("tile_y") in txy
+                and ent.get("lines_z") in tz):
+            self.set_tiles(0, ent["lines_z"], tile_x=ent["tile_x"], tile_y=ent["tile_y"])
+            return dict(ent, cached=True)
+        best = (ctypes.c_int * 3)()
+        ms = (ctypes.c_double * 3)()
+        _check(lib().cmbx_plan_autotune(self.handle, int(reps), best, ms))
+        ent = {"tile_x": best[0], "tile_y": best[1], "lines_z": best[2], "ms": list(ms)}
+        if use_cache:
+            cache[key] = ent
+            try:
+                os.makedirs(os.path.dirname(path), exist_ok=True)
+                tmp = path + ".tmp"
+                with open(tmp, "w") as f:
+                    json.dump(cache, f, indent=1)
+                os.replace(tmp, path)
+            except OSError:
+                pass
+        return dict(ent, cached=False)
 
     @property
     def real_size(self):
@@ -267,6 +306,26 @@ class Plan:
         o = _ptr(out, n * self.real_size, self.torch_dtype, "out")
         debug_gather(self.handle, fp, r, d, n, o)
         return out
+
+
+def tile_choices(dtype, N, which):
+    """Compiled tile choices: which = 0 (x/y column tiles) or 1 (z lines)."""
+    out = (ctypes.c_int * 4)()
+    n = lib().cmbx_tile_choices(_DTYPES[dtype], int(N), int(which), out)
+    return list(out[:n])
+
+
+TUNE_CACHE = os.environ.get("CMBX_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "cmbx", "tune.json"))
+
+
+def _load_cache(path):
+    import json
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}  # missing or corrupt cache: start afresh
 
 
 def _memcpy_d2d(dst, src, nbytes, stream):

@@ -22,7 +22,8 @@ struct cmbx_plan {
   int batch = 0;
   int device = 0;
   int interp = CMBX_TRILINEAR;
-  int tile_xy = 0;  // 0 = compiled default
+  int tile_x = 0;  // 0 = compiled default
+  int tile_y = 0;
   int lines_z = 0;
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
@@ -136,7 +137,8 @@ cmbx::FieldArgs field_args(const cmbx_plan* p, uint64_t seed, void* buf) {
   a.tw = p->tw;
   a.k0 = (uint32_t)(seed & 0xffffffffu);
   a.k1 = (uint32_t)(seed >> 32);
-  a.tile_xy = p->tile_xy;
+  a.tile_x = p->tile_x;
+  a.tile_y = p->tile_y;
   a.lines_z = p->lines_z;
   return a;
 }
@@ -274,11 +276,14 @@ int cmbx_plan_set(cmbx_plan* p, int key, int64_t value) {
     case CMBX_OPT_STREAM:
       p->stream = value == -1 ? p->own_stream : (hipStream_t)(intptr_t)value;
       return ok();
-    case CMBX_OPT_TILE_XY: {
+    case CMBX_OPT_TILE_XY:
+    case CMBX_OPT_TILE_X:
+    case CMBX_OPT_TILE_Y: {
       const int n = cmbx::tile_xy_choices(p->dtype, p->N, opts);
       if (value != 0 && std::find(opts, opts + n, (int)value) == opts + n)
         return fail(CMBX_EINVAL, "tile %lld not compiled for N = %d", (long long)value, p->N);
-      p->tile_xy = (int)value;
+      if (key != CMBX_OPT_TILE_Y) p->tile_x = (int)value;
+      if (key != CMBX_OPT_TILE_X) p->tile_y = (int)value;
       return ok();
     }
     case CMBX_OPT_LINES_Z: {
@@ -498,6 +503,69 @@ int cmbx_time_passes(cmbx_plan* p, uint64_t seed, double r, const double* dirs, 
   for (auto& ee : ev) (void)hipEventDestroy(ee);
   if (rc != CMBX_OK) return rc;
   if (e != hipSuccess) return fail(CMBX_EHIP, "pass timing: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int cmbx_tile_choices(int dtype, int N, int which, int* out) {
+  if (!out || (which != 0 && which != 1)) return 0;
+  int tmp[4];
+  const int n = which == 0 ? cmbx::tile_xy_choices(dtype, N, tmp) : cmbx::lines_z_choices(dtype, N, tmp);
+  for (int i = 0; i < n; ++i) out[i] = tmp[i];
+  return n;
+}
+
+int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
+  if (int rc = check_plan(p)) return rc;
+  if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set");
+  if (reps < 1) return fail(CMBX_EINVAL, "reps = %d must be >= 1", reps);
+  DeviceGuard g(p->device);
+  int tz[4], ln[4];
+  const int ntz = cmbx::tile_xy_choices(p->dtype, p->N, tz);
+  const int nln = cmbx::lines_z_choices(p->dtype, p->N, ln);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  cmbx::FieldArgs a = field_args(p, 0x5eedull, p->field);
+  // time one pass with the current args; returns ms or a negative value on error
+  auto time_pass = [&](int which) -> double {
+    hipError_t e = which == 0 ? cmbx::launch_pass_x(a, p->stream)  // warm-up
+                   : which == 1 ? cmbx::launch_pass_y(a, p->stream)
+                                : cmbx::launch_pass_z(a, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
+    for (int i = 0; e == hipSuccess && i < reps; ++i)
+      e = which == 0 ? cmbx::launch_pass_x(a, p->stream)
+          : which == 1 ? cmbx::launch_pass_y(a, p->stream)
+                       : cmbx::launch_pass_z(a, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    return e == hipSuccess ? (double)t / reps : -1.0;
+  };
+  int pick[3] = {0, 0, 0};
+  double tbest[3] = {1e300, 1e300, 1e300};
+  bool bad = false;
+  for (int which = 0; which < 3 && !bad; ++which) {
+    const int n = which == 2 ? nln : ntz;
+    for (int i = 0; i < n && !bad; ++i) {
+      a.tile_x = which == 0 ? tz[i] : p->tile_x;
+      a.tile_y = which == 1 ? tz[i] : p->tile_y;
+      a.lines_z = which == 2 ? ln[i] : p->lines_z;
+      const double t = time_pass(which);
+      if (t < 0) bad = true;
+      else if (t < tbest[which]) tbest[which] = t, pick[which] = which == 2 ? ln[i] : tz[i];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (bad) return fail(CMBX_EHIP, "autotune launch failed: %s", hipGetErrorString(hipGetLastError()));
+  p->tile_x = pick[0];
+  p->tile_y = pick[1];
+  p->lines_z = pick[2];
+  for (int i = 0; i < 3; ++i) {
+    if (best) best[i] = pick[i];
+    if (ms) ms[i] = tbest[i];
+  }
   return ok();
 }
 

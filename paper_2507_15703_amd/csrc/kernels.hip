@@ -90,25 +90,27 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __re
   const T* wself = wtab + 3 * M * M + 1;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   const int fy2 = freq2(iy, N);
+  if (zc0 == 0) {
+    // column 0 packs the Hermitian planes iz = 0 and N/2; column 1 is iz = 1
+    for (int ix = tid; ix < N; ix += NT) {
+      const cpx<T> a = mode_value<T>(N, ix, iy, 0, k0, k1, wtab, wself);
+      const cpx<T> b = mode_value<T>(N, ix, iy, M, k0, k1, wtab, wself);
+      tile[ix * TZ] = {a.x - b.y, a.y + b.x};  // Z_0 + i Z_{N/2}
+      tile[ix * TZ + 1] = mode_value<T>(N, ix, iy, 1, k0, k1, wtab, wself);
+    }
+  }
+  // every other pair of columns (2p, 2p + 1) holds two generic modes drawn from one
+  // Philox call
   for (int s = tid; s < N * PAIRS; s += NT) {
     const int pr = s % PAIRS;
     const int ix = s / PAIRS;
     const int zc = zc0 + 2 * pr;
-    cpx<T> v0, v1;
-    if (zc == 0) {
-      const cpx<T> a = mode_value<T>(N, ix, iy, 0, k0, k1, wtab, wself);
-      const cpx<T> b = mode_value<T>(N, ix, iy, M, k0, k1, wtab, wself);
-      v0 = {a.x - b.y, a.y + b.x};  // Z_0 + i Z_{N/2}
-      v1 = mode_value<T>(N, ix, iy, 1, k0, k1, wtab, wself);
-    } else {
-      const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
-      const int m0 = freq2(ix, N) + fy2 + zc * zc;
-      const int m1 = m0 + 2 * zc + 1;
-      v0 = weighted<T>(wtab[m0], w.x, w.y);
-      v1 = weighted<T>(wtab[m1], w.z, w.w);
-    }
-    tile[ix * TZ + 2 * pr] = v0;
-    tile[ix * TZ + 2 * pr + 1] = v1;
+    if (zc == 0) continue;
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
+    const int m0 = freq2(ix, N) + fy2 + zc * zc;
+    const int m1 = m0 + 2 * zc + 1;
+    tile[ix * TZ + 2 * pr] = weighted<T>(wtab[m0], w.x, w.y);
+    tile[ix * TZ + 2 * pr + 1] = weighted<T>(wtab[m1], w.z, w.w);
   }
   __syncthreads();
   LdsIO<T, N, TZ, true> first{tile};
@@ -249,10 +251,10 @@ constexpr int default_tz(int N) {
     if ((N / 2) % tz == 0 && (N * tz + N) * 2 * (int)sizeof(T) <= lds_budget()) return tz;
   return 2;
 }
-template <typename T>
-constexpr int alt_tz(int N) {
-  const int d = default_tz<T>(N);
-  return (d / 2 >= 2 && (d / 2) % 2 == 0 && (N / 2) % (d / 2) == 0) ? d / 2 : d;
+// alternative tiles: half and a quarter of the default (kept even and dividing N/2)
+constexpr int tz_choice(int d, int N, int k) {
+  const int t = d >> k;
+  return (t >= 2 && t % 2 == 0 && (N / 2) % t == 0) ? t : d;
 }
 // lines per z workgroup: about 4096 (FP32) / 2048 (FP64) complex, dividing N^2
 template <typename T>
@@ -262,10 +264,13 @@ constexpr int default_lines(int N) {
   while (l * 2 <= target && (N * N) % (l * 2) == 0) l *= 2;
   return l;
 }
+// alternatives: twice (if the block stays within 8192 complex) and half the default
 template <typename T>
-constexpr int alt_lines(int N) {
+constexpr int lines_choice(int N, int k) {
   const int d = default_lines<T>(N);
-  return d >= 2 ? d / 2 : d;
+  if (k == 1) return (d * 2 * (N / 2) <= 8192 && (N * N) % (d * 2) == 0) ? d * 2 : d;
+  if (k == 2) return d >= 2 ? d / 2 : d;
+  return d;
 }
 
 using PassFn = hipError_t (*)(const FieldArgs&, hipStream_t);
@@ -292,25 +297,28 @@ hipError_t run_z(const FieldArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+constexpr int kChoices = 3;
+
 struct Entry {
   int dtype, N;
-  int tz[2];
-  PassFn x[2], y[2];
-  int lines[2];
-  PassFn z[2];
+  int tz[kChoices];
+  PassFn x[kChoices], y[kChoices];
+  int lines[kChoices];
+  PassFn z[kChoices];
 };
 
 template <typename T, int N>
 constexpr Entry make_entry() {
-  constexpr int t0 = default_tz<T>(N), t1 = alt_tz<T>(N);
-  constexpr int l0 = default_lines<T>(N), l1 = alt_lines<T>(N);
+  constexpr int d = default_tz<T>(N);
+  constexpr int t0 = d, t1 = tz_choice(d, N, 1), t2 = tz_choice(d, N, 2);
+  constexpr int l0 = lines_choice<T>(N, 0), l1 = lines_choice<T>(N, 1), l2 = lines_choice<T>(N, 2);
   return Entry{sizeof(T) == 4 ? kF32 : kF64,
                N,
-               {t0, t1},
-               {&run_x<T, N, t0>, &run_x<T, N, t1>},
-               {&run_y<T, N, t0>, &run_y<T, N, t1>},
-               {l0, l1},
-               {&run_z<T, N, l0>, &run_z<T, N, l1>}};
+               {t0, t1, t2},
+               {&run_x<T, N, t0>, &run_x<T, N, t1>, &run_x<T, N, t2>},
+               {&run_y<T, N, t0>, &run_y<T, N, t1>, &run_y<T, N, t2>},
+               {l0, l1, l2},
+               {&run_z<T, N, l0>, &run_z<T, N, l1>, &run_z<T, N, l2>}};
 }
 
 #define CMBX_SIZES(T)                                                                                     \
@@ -329,9 +337,19 @@ const Entry* find(int dtype, int N) {
 
 int pick(const int* opts, int want) {
   if (want <= 0) return 0;
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < kChoices; ++i)
     if (opts[i] == want) return i;
   return -1;
+}
+
+int distinct(const int* opts, int* out) {
+  int n = 0;
+  for (int i = 0; i < kChoices; ++i) {
+    bool seen = false;
+    for (int j = 0; j < n; ++j) seen = seen || out[j] == opts[i];
+    if (!seen) out[n++] = opts[i];
+  }
+  return n;
 }
 
 }  // namespace
@@ -340,31 +358,23 @@ bool size_compiled(int N) { return find(kF32, N) != nullptr; }
 
 int tile_xy_choices(int dtype, int N, int* out) {
   const Entry* e = find(dtype, N);
-  if (!e) return 0;
-  out[0] = e->tz[0];
-  if (e->tz[1] == e->tz[0]) return 1;
-  out[1] = e->tz[1];
-  return 2;
+  return e ? distinct(e->tz, out) : 0;
 }
 
 int lines_z_choices(int dtype, int N, int* out) {
   const Entry* e = find(dtype, N);
-  if (!e) return 0;
-  out[0] = e->lines[0];
-  if (e->lines[1] == e->lines[0]) return 1;
-  out[1] = e->lines[1];
-  return 2;
+  return e ? distinct(e->lines, out) : 0;
 }
 
 hipError_t launch_pass_x(const FieldArgs& a, hipStream_t s) {
   const Entry* e = find(a.dtype, a.N);
-  const int i = e ? pick(e->tz, a.tile_xy) : -1;
+  const int i = e ? pick(e->tz, a.tile_x) : -1;
   if (i < 0) return hipErrorInvalidValue;
   return e->x[i](a, s);
 }
 hipError_t launch_pass_y(const FieldArgs& a, hipStream_t s) {
   const Entry* e = find(a.dtype, a.N);
-  const int i = e ? pick(e->tz, a.tile_xy) : -1;
+  const int i = e ? pick(e->tz, a.tile_y) : -1;
   if (i < 0) return hipErrorInvalidValue;
   return e->y[i](a, s);
 }

@@ -21,7 +21,7 @@ struct FieldArgs {
   const void* wtab;    // sqrt(P_box/2) for |f|^2 = 0 .. 3 (N/2)^2, then sqrt(P_box) x 4
   const void* tw;      // N roots exp(2 pi i m / N), complex, plan precision
   uint32_t k0, k1;     // Philox key (seed words)
-  int tile_xy, lines_z;
+  int tile_x, tile_y, lines_z;  // 0 = compiled default
 };
 
 // Pass 1: noise + weights + Hermitian planes + inverse FFT along x.

@@ -16,6 +16,8 @@
 //   sqrt x: four Newton steps for 1/sqrt(x) from the integer-shift seed, times x;
 //   cos, sin of 2 pi b 2^-32: quadrant from the top two bits, the rest folded to
 //     t in [0, pi/4] with sin/cos swapped when folded, Taylor series to t^17 / t^18.
+// Single-precision plans use a binary32 variant of the same steps (below); double
+// precision plans use the binary64 one.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,9 +31,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
   constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
-    const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    const uint64_t p0 = (uint64_t)M0 * c.x;
+    const uint64_t p1 = (uint64_t)M1 * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
     k0 += W0;
     k1 += W1;
   }
@@ -119,19 +121,92 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& g_re,
   g_im = rad * sn;
 }
 
+namespace bmf {
+// binary32 constants
+constexpr float kLn2Head = 0x1.62e4p-1f;     // ln 2 with a 16-bit significand
+constexpr float kLn2Tail = 0x1.7f7d1cp-20f;  // ln 2 - head, rounded to binary32
+constexpr float kSqrt2 = 0x1.6a09e6p+0f;
+constexpr float kTwoPi2m32 = 0x1.921fb6p-30f;
+constexpr uint32_t kRsqrtMagic = 0x5F3759DFu;
+// the binary64 quotients rounded to binary32
+constexpr float kSin[5] = {(float)bm::kSin[0], (float)bm::kSin[1], (float)bm::kSin[2], (float)bm::kSin[3],
+                           (float)bm::kSin[4]};
+constexpr float kCos[6] = {(float)bm::kCos[0], (float)bm::kCos[1], (float)bm::kCos[2],
+                           (float)bm::kCos[3], (float)bm::kCos[4], (float)bm::kCos[5]};
+constexpr float kAtanh[5] = {(float)bm::kAtanh[0], (float)bm::kAtanh[1], (float)bm::kAtanh[2],
+                             (float)bm::kAtanh[3], (float)bm::kAtanh[4]};
+}  // namespace bmf
+
+// binary32 variant for single-precision plans: the same steps in binary32 with series
+// sized to it. a + 1 is cut to its leading 24 bits (m = mi 2^-23, mi in [2^23, 2^24)),
+// four Newton steps for 1/(m + 1), artanh series to s^8, three Newton steps for
+// 1/sqrt(x), sine series to t^9 and cosine series to t^10.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& g_re, float& g_im) {
+#pragma clang fp contract(off)
+  using namespace bmf;
+  const uint64_t v = (uint64_t)a + 1ull;
+  const int e0 = 63 - __clzll((long long)v);
+  const uint32_t mi = e0 >= 23 ? (uint32_t)(v >> (e0 - 23)) : (uint32_t)(v << (23 - e0));
+  float m = (float)mi * 0x1p-23f;  // [1, 2), exact
+  const bool big = m >= kSqrt2;
+  m = big ? m * 0.5f : m;
+  const int e = (big ? e0 + 1 : e0) - 32;
+  const float d = m + 1.0f;
+  float y = 0.5f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) y = y * (2.0f - d * y);
+  const float s = (m - 1.0f) * y;
+  const float s2 = s * s;
+  float p = kAtanh[4];
+#pragma unroll
+  for (int k = 3; k >= 0; --k) p = p * s2 + kAtanh[k];
+  const float lnm = (s + s) * p;
+  const float ef = (float)e;
+  const float lnu = ef * kLn2Head + (ef * kLn2Tail + lnm);
+  const float x = -(lnu + lnu);
+  float r = __uint_as_float(kRsqrtMagic - (__float_as_uint(x) >> 1));
+  const float hx = 0.5f * x;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r = r * (1.5f - hx * (r * r));
+  const float rad = (x == 0.0f) ? 0.0f : x * r;
+  const uint32_t q = b >> 30;
+  const uint32_t rr = b & 0x3FFFFFFFu;
+  const bool swap = rr >= (1u << 29);
+  const uint32_t rho = swap ? (1u << 30) - rr : rr;
+  const float t = (float)rho * kTwoPi2m32;
+  const float t2 = t * t;
+  float ps = kSin[4];
+#pragma unroll
+  for (int k = 3; k >= 0; --k) ps = ps * t2 + kSin[k];
+  const float st = t * ps;
+  float pc = kCos[5];
+#pragma unroll
+  for (int k = 4; k >= 0; --k) pc = pc * t2 + kCos[k];
+  const float ct = pc;
+  const float si = swap ? ct : st;
+  const float ci = swap ? st : ct;
+  const bool odd = (q & 1u) != 0u;
+  float sn = odd ? ci : si;
+  float cs = odd ? si : ci;
+  sn = (q & 2u) ? -sn : sn;
+  cs = ((q + 1u) & 2u) ? -cs : cs;
+  g_re = rad * cs;
+  g_im = rad * sn;
+}
+
 // Words (a, b) of mode (ix, iy, iz).
 __device__ __forceinline__ uint2 mode_words(uint32_t k0, uint32_t k1, int ix, int iy, int iz) {
   const uint4 w = philox4x32_10(make_uint4((uint32_t)iz >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
   return (iz & 1) ? make_uint2(w.z, w.w) : make_uint2(w.x, w.y);
 }
 
-// A generic mode from its words: weight x (g_re, g_im), each factor rounded to T and the
-// product formed in T.
+// A generic mode from its words: weight x (g_re, g_im), the pair from the transform of
+// the working precision T and the product formed in T.
 template <typename T>
 __device__ __forceinline__ cpx<T> weighted(T w, uint32_t a, uint32_t b) {
-  double gr, gi;
+  T gr, gi;
   box_muller(a, b, gr, gi);
-  return {w * (T)gr, w * (T)gi};
+  return {w * gr, w * gi};
 }
 
 __device__ __forceinline__ int freq2(int i, int N) {
@@ -163,14 +238,14 @@ __device__ __forceinline__ cpx<T> mode_value(int N, int ix, int iy, int iz, uint
     }
   }
   const uint2 w = mode_words(k0, k1, sx, sy, iz);
-  double gr, gi;
+  T gr, gi;
   box_muller(w.x, w.y, gr, gi);
   if (self) {
     const int c = (ix == M) + (iy == M) + (iz == M);
-    return {wself[c] * (T)gr, T(0)};
+    return {wself[c] * gr, T(0)};
   }
   const T wv = wh[m];
-  const cpx<T> v = {wv * (T)gr, wv * (T)gi};
+  const cpx<T> v = {wv * gr, wv * gi};
   return cj ? conj(v) : v;
 }
 

@@ -86,3 +86,44 @@ def test_box_muller_against_library_form():
     ref_im = R * np.sin(2 * np.pi * u2)
     assert np.max(np.abs(g_re - ref_re)) < 2e-14
     assert np.max(np.abs(g_im - ref_im)) < 2e-14
+
+
+# ---------------------------------------------------------------- binary32 variant
+def test_f32_log_matches_library():
+    a = np.concatenate([WORDS, EDGE])
+    got = normal.canonical_log_u1_f32(a)
+    assert got.dtype == np.float32
+    ref = np.log((a + np.uint64(1)).astype(np.float64) * 2.0**-32)
+    # a + 1 keeps its leading 24 bits: u1 changes by a relative 2^-23 at most, i.e. ln u1 by
+    # an absolute 2^-23, on top of a few binary32 roundings of the result
+    err = np.abs(got.astype(np.float64) - ref)
+    assert np.all(err <= 4 * 2.0**-24 * np.abs(ref) + 2.0**-23)
+
+
+def test_f32_sqrt_matches_library():
+    x = np.concatenate([RNG.uniform(0, 45, 200_000), 10.0 ** RNG.uniform(-9, 1.6, 50_000)]).astype(np.float32)
+    got = normal.canonical_sqrt_f32(x)
+    assert got.dtype == np.float32
+    ref = np.sqrt(x.astype(np.float64))
+    assert np.max(np.abs(got - ref) / ref) < 3 * 2.0**-24
+
+
+def test_f32_sincos_matches_library():
+    b = np.concatenate([WORDS, EDGE])
+    s, c = normal.canonical_sincos_2pi_f32(b)
+    assert s.dtype == np.float32 and c.dtype == np.float32
+    th = 2.0 * np.pi * (b.astype(np.float64) * 2.0**-32)
+    assert np.max(np.abs(s - np.sin(th))) < 4e-7
+    assert np.max(np.abs(c - np.cos(th))) < 4e-7
+
+
+def test_f32_pair_close_to_f64_pair_and_normal():
+    a, b = WORDS[:200_000], WORDS[200_000:]
+    g32 = normal.box_muller_f32(a, b)
+    g64 = normal.box_muller(a, b)
+    for x32, x64 in zip(g32, g64):
+        assert x32.dtype == np.float32
+        # only radii below ~5e-4 (u1 within 2^-24 of 1) lose relative accuracy
+        assert np.max(np.abs(x32 - x64)) < 1e-3
+        assert np.percentile(np.abs(x32 - x64), 99.99) < 2e-6
+        assert scipy.stats.kstest(x32.astype(np.float64), "norm").pvalue > 1e-4
