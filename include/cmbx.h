@@ -120,14 +120,22 @@ typedef struct cmbx_job {
 } cmbx_job;
 
 /*
- * Capture the jobs' kernel chains into one HIP graph. Jobs that share a plan run one after
- * another; jobs of different plans are independent branches. Buffers stay caller-owned
- * and must outlive the ensemble. Errors: as cmbx_simulate_patch for each job, CMBX_EINVAL
- * for n_jobs < 1.
+ * Capture the jobs into one HIP graph of software-pipelined launches. Every realisation of
+ * every job (job j's plan has `batch` of them, seeds seed + b, maps at out + b n_pix) is an
+ * item; items of equal (precision, N) form one pipeline whose launch t runs, side by side
+ * in one kernel, the noise + x pass of item t, the y pass of item t-1, the z pass of item
+ * t-2 and the gather of item t-3, so that the ALU-bound noise work and the HBM-bound
+ * transforms share the GPU. Pipelines of different sizes run one after another. The
+ * ensemble owns min(4, items) workspaces per pipeline (the plans' workspaces are not
+ * touched); buffers passed in stay caller-owned and must outlive it, and so must the
+ * plans, whose weight and twiddle tables are read when the graph runs (interpolant, r and
+ * pixel counts are fixed at creation). Errors: as cmbx_simulate_patch for each job,
+ * CMBX_EINVAL for n_jobs < 1, CMBX_ENOMEM.
  */
 int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, cmbx_ensemble** out);
 /* Launch the captured graph on `stream` (a hipStream_t; NULL = the default stream). */
 int cmbx_ensemble_launch(cmbx_ensemble* ens, void* stream);
+/* Release an ensemble (waits for the device first). NULL is accepted. */
 int cmbx_ensemble_destroy(cmbx_ensemble* ens);
 
 /* ---- stage-by-stage entry points (tests and profiling) ---- */

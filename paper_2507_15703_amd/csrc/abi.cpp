@@ -39,6 +39,8 @@ struct cmbx_plan {
 struct cmbx_ensemble {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<void*> dev;  // rotating workspaces and the schedule
+  int device = 0;
 };
 
 namespace {
@@ -387,6 +389,38 @@ int cmbx_debug_gather(cmbx_plan* p, const void* field, double r, const double* d
   return ok();
 }
 
+namespace {
+
+// One realisation to simulate inside an ensemble.
+struct Item {
+  const cmbx_plan* plan;
+  uint64_t seed;
+  double r;
+  const double* dirs;
+  int64_t n_pix;
+  void* out;
+};
+
+// Interleave the roles' workgroups in proportion to their counts (largest-deficit
+// order), so every stretch of the launch carries the same mix of roles.
+void interleave(const int64_t cnt[4], std::vector<uint32_t>& sched) {
+  int64_t total = 0, issued[4] = {0, 0, 0, 0};
+  for (int r = 0; r < 4; ++r) total += cnt[r];
+  for (int64_t pos = 0; pos < total; ++pos) {
+    int best = -1;
+    double bd = -1e300;
+    for (int r = 0; r < 4; ++r) {
+      if (issued[r] >= cnt[r]) continue;
+      const double d = (double)cnt[r] * (double)(pos + 1) / (double)total - (double)issued[r];
+      if (d > bd) bd = d, best = r;
+    }
+    sched.push_back(((uint32_t)best << 30) | (uint32_t)issued[best]);
+    ++issued[best];
+  }
+}
+
+}  // namespace
+
 int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, cmbx_ensemble** out) {
   if (!out) return fail(CMBX_EINVAL, "out is NULL");
   *out = nullptr;
@@ -400,62 +434,114 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, cmbx_ensemble** out) 
     if (jobs[j].plan->device != jobs[0].plan->device) return fail(CMBX_EINVAL, "all jobs must be on one device");
   }
   DeviceGuard g(jobs[0].plan->device);
-  // Jobs of one plan share its workspace and form one chain; chains of different plans
-  // are independent branches of the graph.
-  std::vector<cmbx_plan*> plans;
-  std::map<cmbx_plan*, std::vector<int>> chains;
+  // Realisations grouped by (precision, N), in job order; each group is one software
+  // pipeline of pipelined launches.
+  std::vector<std::pair<int, int>> keys;
+  std::map<std::pair<int, int>, std::vector<Item>> groups;
   for (int j = 0; j < n_jobs; ++j) {
-    if (!chains.count(jobs[j].plan)) plans.push_back(jobs[j].plan);
-    chains[jobs[j].plan].push_back(j);
-  }
-  hipStream_t origin = nullptr;
-  std::vector<hipStream_t> branch(plans.size(), nullptr);
-  std::vector<hipEvent_t> ev(plans.size() + 1, nullptr);
-  hipGraph_t graph = nullptr;
-  int rc = CMBX_OK;
-  auto cleanup = [&]() {
-    for (auto s : branch)
-      if (s) (void)hipStreamDestroy(s);
-    for (auto e : ev)
-      if (e) (void)hipEventDestroy(e);
-    if (origin) (void)hipStreamDestroy(origin);
-  };
-  hipError_t e = hipStreamCreateWithFlags(&origin, hipStreamNonBlocking);
-  for (size_t i = 0; e == hipSuccess && i < plans.size(); ++i) e = hipStreamCreateWithFlags(&branch[i], hipStreamNonBlocking);
-  for (size_t i = 0; e == hipSuccess && i < ev.size(); ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
-  if (e != hipSuccess) {
-    cleanup();
-    return fail(CMBX_EHIP, "ensemble setup: %s", hipGetErrorString(e));
-  }
-  e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) e = hipEventRecord(ev[0], origin);
-  for (size_t i = 0; e == hipSuccess && rc == CMBX_OK && i < plans.size(); ++i) {
-    e = hipStreamWaitEvent(branch[i], ev[0], 0);
-    for (int j : chains[plans[i]]) {
-      if (e != hipSuccess || rc != CMBX_OK) break;
-      rc = enqueue_patch(plans[i], jobs[j].seed, jobs[j].r, jobs[j].dirs, jobs[j].n_pix, jobs[j].out, branch[i]);
-    }
-    if (e == hipSuccess && rc == CMBX_OK) e = hipEventRecord(ev[i + 1], branch[i]);
-    if (e == hipSuccess && rc == CMBX_OK) e = hipStreamWaitEvent(origin, ev[i + 1], 0);
-  }
-  const hipError_t e_end = hipStreamEndCapture(origin, &graph);
-  if (e == hipSuccess) e = e_end;
-  if (rc != CMBX_OK || e != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    cleanup();
-    if (rc != CMBX_OK) return rc;
-    return fail(CMBX_EHIP, "ensemble capture: %s", hipGetErrorString(e));
-  }
-  hipGraphExec_t exec = nullptr;
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  cleanup();
-  if (e != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return fail(CMBX_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    const cmbx_plan* p = jobs[j].plan;
+    const auto key = std::make_pair(p->dtype, p->N);
+    if (!groups.count(key)) keys.push_back(key);
+    for (int b = 0; b < p->batch; ++b)
+      groups[key].push_back(Item{p, jobs[j].seed + (uint64_t)b, jobs[j].r, jobs[j].dirs, jobs[j].n_pix,
+                                 (char*)jobs[j].out + (size_t)b * jobs[j].n_pix * p->real_size()});
   }
   cmbx_ensemble* en = new cmbx_ensemble;
+  en->device = jobs[0].plan->device;
+  auto bail = [&](int code, const std::string& msg) {
+    for (void* d : en->dev) (void)hipFree(d);
+    delete en;
+    return fail(code, "%s", msg.c_str());
+  };
+  struct Launch {
+    cmbx::PipeLaunch a;
+    size_t off;
+  };
+  std::vector<Launch> launches;
+  std::vector<uint32_t> sched;
+  for (const auto& key : keys) {
+    const std::vector<Item>& items = groups[key];
+    const int dtype = key.first, N = key.second, M = N / 2;
+    const cmbx_plan* p0 = items[0].plan;
+    int tx, ty, lz;
+    if (!cmbx::pipeline_shape(dtype, N, &tx, &ty, &lz)) return bail(CMBX_EUNSUPPORTED, "no pipelined kernel for N");
+    const int n = (int)items.size();
+    const int nbuf = n < 4 ? n : 4;
+    std::vector<void*> bufs(nbuf, nullptr);
+    for (int i = 0; i < nbuf; ++i) {
+      const hipError_t e = hipMalloc(&bufs[i], p0->field_bytes());
+      if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "ensemble workspace");
+      en->dev.push_back(bufs[i]);
+    }
+    for (int t = 0; t < n + 3; ++t) {
+      const int ix = t, iy = t - 1, iz = t - 2, ig = t - 3;
+      int64_t cnt[4] = {0, 0, 0, 0};
+      cmbx::PipeLaunch a{};
+      a.dtype = dtype;
+      a.N = N;
+      a.tw = p0->tw;
+      if (ix < n) {
+        cnt[0] = (int64_t)(M / tx) * N;
+        a.bx = bufs[ix % nbuf];
+        a.wtab_x = items[ix].plan->wtab;
+        a.k0 = (uint32_t)(items[ix].seed & 0xffffffffu);
+        a.k1 = (uint32_t)(items[ix].seed >> 32);
+      }
+      if (iy >= 0 && iy < n) {
+        cnt[1] = (int64_t)(M / ty) * N;
+        a.by = bufs[iy % nbuf];
+      }
+      if (iz >= 0 && iz < n) {
+        cnt[2] = (int64_t)N * N / lz;
+        a.bz = bufs[iz % nbuf];
+      }
+      if (ig >= 0 && ig < n) {
+        const Item& it = items[ig];
+        cnt[3] = (it.n_pix + cmbx::kPipeThreads - 1) / cmbx::kPipeThreads;
+        a.field_g = bufs[ig % nbuf];
+        a.dirs = it.dirs;
+        a.out = it.out;
+        a.npix = it.n_pix;
+        a.r = it.r;
+        a.scale = (double)N / it.plan->L;
+        a.half = 0.5 * it.plan->L;
+        a.cubic = it.plan->interp == CMBX_TRICUBIC;
+      }
+      const size_t off = sched.size();
+      interleave(cnt, sched);
+      a.nblocks = (int)(sched.size() - off);
+      launches.push_back(Launch{a, off});
+    }
+  }
+  void* dsched = nullptr;
+  hipError_t e = hipMalloc(&dsched, sched.size() * sizeof(uint32_t));
+  if (e != hipSuccess) return bail(CMBX_ENOMEM, "ensemble schedule");
+  en->dev.push_back(dsched);
+  e = hipMemcpy(dsched, sched.data(), sched.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(CMBX_EHIP, std::string("schedule upload: ") + hipGetErrorString(e));
+  hipStream_t cap = nullptr;
+  e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(CMBX_EHIP, "capture stream");
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  for (size_t i = 0; e == hipSuccess && i < launches.size(); ++i) {
+    cmbx::PipeLaunch a = launches[i].a;
+    a.sched = (const uint32_t*)dsched + launches[i].off;
+    e = cmbx::launch_pipeline(a, cap);
+  }
+  const hipError_t e_end = hipStreamEndCapture(cap, &graph);
+  if (e == hipSuccess) e = e_end;
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return bail(CMBX_EHIP, std::string("ensemble capture: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&en->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return bail(CMBX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
   en->graph = graph;
-  en->exec = exec;
   *out = en;
   return ok();
 }
@@ -468,8 +554,11 @@ int cmbx_ensemble_launch(cmbx_ensemble* en, void* stream) {
 
 int cmbx_ensemble_destroy(cmbx_ensemble* en) {
   if (!en) return ok();
+  DeviceGuard g(en->device);
+  (void)hipDeviceSynchronize();
   if (en->exec) (void)hipGraphExecDestroy(en->exec);
   if (en->graph) (void)hipGraphDestroy(en->graph);
+  for (void* d : en->dev) (void)hipFree(d);
   delete en;
   return ok();
 }

@@ -70,23 +70,21 @@ struct ZShape {
 };
 
 // ------------------------------------------------------------------ pass 1: noise + x
-// Workgroup = (z tile of TZ packed columns, one iy). Generates the N x TZ tile of weighted
-// modes in LDS (one Philox call per pair of neighbouring iz), then runs the length-N
-// inverse transform along x and writes the tile's N rows of TZ columns (128 B for FP32
-// TZ = 16) to the strided x axis.
-template <typename T, int N, int TZ>
-__global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __restrict__ buf,
-                                                                 const T* __restrict__ wtab,
-                                                                 const cpx<T>* __restrict__ twg,
-                                                                 uint32_t k0, uint32_t k1) {
+// Workgroup = (z tile zt of TZ packed columns, one iy). Generates the N x TZ tile of
+// weighted modes in LDS (one Philox call per pair of neighbouring iz), then runs the
+// length-N inverse transform along x and writes the tile's N rows of TZ columns (128 B for
+// FP32 TZ = 16) to the strided x axis. smem: N TZ + N complex (tile, then twiddles).
+template <typename T, int N, int TZ, int NT>
+__device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __restrict__ buf,
+                                       const T* __restrict__ wtab, const cpx<T>* __restrict__ twg, uint32_t k0,
+                                       uint32_t k1) {
   constexpr int M = N / 2;
-  constexpr int NT = XYShape<T, N, TZ>::NT;
   constexpr int PAIRS = TZ / 2;
-  __shared__ cpx<T> tile[N * TZ];
-  __shared__ cpx<T> tw[N];
+  static_assert(M % TZ == 0 && TZ % 2 == 0, "tile must divide N/2 and be even");
+  cpx<T>* tile = smem;
+  cpx<T>* tw = smem + N * TZ;
   const int tid = threadIdx.x;
-  const int zc0 = blockIdx.x * TZ;
-  const int iy = blockIdx.y;
+  const int zc0 = zt * TZ;
   const T* wself = wtab + 3 * M * M + 1;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   const int fy2 = freq2(iy, N);
@@ -119,38 +117,60 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __re
 }
 
 // ------------------------------------------------------------------ pass 2: y
-template <typename T, int N, int TZ>
-__global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __restrict__ buf,
-                                                                 const cpx<T>* __restrict__ twg) {
+// Workgroup = (z tile zt, one ix): N rows (iy) of TZ columns, read, transformed along y,
+// written back in place.
+template <typename T, int N, int TZ, int NT>
+__device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __restrict__ buf,
+                                       const cpx<T>* __restrict__ twg) {
   constexpr int M = N / 2;
-  constexpr int NT = XYShape<T, N, TZ>::NT;
-  __shared__ cpx<T> tile[N * TZ];
-  __shared__ cpx<T> tw[N];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  cpx<T>* tile = smem;
+  cpx<T>* tw = smem + N * TZ;
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
-  GlobalColIO<T> io{buf + (size_t)blockIdx.y * N * M + blockIdx.x * TZ, (size_t)M};
+  GlobalColIO<T> io{buf + (size_t)ix * N * M + zt * TZ, (size_t)M};
   fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, io, io);
 }
 
 // ------------------------------------------------------------------ pass 3: z (c2r)
-// Workgroup = LINES consecutive (ix, iy) lines of N/2 complex; they are contiguous, so
-// the whole block is loaded and stored with unit stride.
-template <typename T, int N, int LINES>
-__global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __restrict__ buf,
-                                                                   const cpx<T>* __restrict__ twg) {
+// Workgroup = LINES consecutive (ix, iy) lines of N/2 complex, starting at line blk LINES;
+// they are contiguous, so the block is loaded and stored with unit stride.
+template <typename T, int N, int LINES, int NT>
+__device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict__ buf,
+                                       const cpx<T>* __restrict__ twg) {
   constexpr int M = N / 2;
-  constexpr int NT = ZShape<T, N, LINES>::NT;
-  __shared__ cpx<T> tile[LINES * M];
-  __shared__ cpx<T> tw[N];
+  cpx<T>* tile = smem;
+  cpx<T>* tw = smem + LINES * M;
   const int tid = threadIdx.x;
-  cpx<T>* g = buf + (size_t)blockIdx.x * LINES * M;
+  cpx<T>* g = buf + (size_t)blk * LINES * M;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   for (int i = tid; i < LINES * M; i += NT) tile[i] = g[i];
   __syncthreads();
   HalfToComplex<T, M> first{tile, tw};
   GlobalLineIO<T, M> last{g};
   fft_run<T, M, LINES, NT, false, 2, 0>(tw, tile, first, last);
+}
+
+template <typename T, int N, int TZ>
+__global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __restrict__ buf,
+                                                                 const T* __restrict__ wtab,
+                                                                 const cpx<T>* __restrict__ twg,
+                                                                 uint32_t k0, uint32_t k1) {
+  __shared__ cpx<T> smem[N * TZ + N];
+  role_x<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, wtab, twg, k0, k1);
+}
+
+template <typename T, int N, int TZ>
+__global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __restrict__ buf,
+                                                                 const cpx<T>* __restrict__ twg) {
+  __shared__ cpx<T> smem[N * TZ + N];
+  role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg);
+}
+
+template <typename T, int N, int LINES>
+__global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __restrict__ buf,
+                                                                   const cpx<T>* __restrict__ twg) {
+  __shared__ cpx<T> smem[LINES * (N / 2) + N];
+  role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, blockIdx.x, buf, twg);
 }
 
 // ------------------------------------------------------------------ debug noise
@@ -172,7 +192,7 @@ __global__ void k_noise_debug(cpx<T>* __restrict__ out, int N, const T* __restri
 // One thread per pixel. The position p = (r n + L/2) N/L and its floor are formed in FP64
 // (no contraction, so CPU and GPU take the same integer decision); the fraction is then
 // rounded to T, and weights and accumulation are in T. The 2 or 4 nodes per axis wrap
-// modulo N. Blocks are assigned so that each XCD's L2 serves a contiguous pixel range.
+// modulo N.
 template <typename T>
 __device__ __forceinline__ void weights1d(T f, T* w, int interp) {
   if (interp == kTricubic) {
@@ -189,15 +209,9 @@ __device__ __forceinline__ void weights1d(T f, T* w, int interp) {
 __device__ __forceinline__ int wrap(int i, int N) { return i < 0 ? i + N : (i >= N ? i - N : i); }
 
 template <typename T, int K>
-__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int N, double scale, double half,
-                                                double r, const double* __restrict__ dirs, int64_t npix,
-                                                T* __restrict__ out) {
-  const int nb = gridDim.x;
-  const int per = nb / 8;
-  const int b = blockIdx.x;
-  const int logical = (nb % 8 == 0) ? (b % 8) * per + b / 8 : b;
-  const int64_t i = (int64_t)logical * blockDim.x + threadIdx.x;
-  if (i >= npix) return;
+__device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N, double scale, double half,
+                                             double r, const double* __restrict__ dirs, int64_t i,
+                                             T* __restrict__ out) {
   int i0[3];
   T w[3][4];
   {
@@ -234,6 +248,75 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int
     acc += w[0][a] * accb;
   }
   out[i] = acc;
+}
+
+// Blocks are assigned so that each XCD's L2 serves a contiguous pixel range.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int N, double scale, double half,
+                                                double r, const double* __restrict__ dirs, int64_t npix,
+                                                T* __restrict__ out) {
+  const int nb = gridDim.x;
+  const int per = nb / 8;
+  const int b = blockIdx.x;
+  const int logical = (nb % 8 == 0) ? (b % 8) * per + b / 8 : b;
+  const int64_t i = (int64_t)logical * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  gather_pixel<T, K>(field, N, scale, half, r, dirs, i, out);
+}
+
+// ------------------------------------------------------------------ pipelined passes
+// One launch runs the four stages of the hot path on four different realisations at once:
+// pass x of item t, pass y of item t-1, pass z of item t-2 and the gather of item t-3.
+// Each workgroup reads its (role, index) from a host-built schedule that interleaves the
+// roles in proportion to their workgroup counts, so the ALU-bound noise workgroups share
+// every CU with the HBM-bound transform and gather workgroups.
+template <typename T>
+struct PipeArgs {
+  cpx<T>* bx;          // pass x output buffer
+  const T* wtab_x;     // weights of the item in pass x
+  uint32_t k0, k1;     // its seed words
+  cpx<T>* by;          // pass y buffer
+  cpx<T>* bz;          // pass z buffer
+  const T* field_g;    // gather input field
+  const double* dirs;  // gather directions
+  T* out;              // gather output
+  int64_t npix;
+  double r, scale, half;
+  int cubic;
+  const cpx<T>* tw;    // twiddles of this N
+};
+
+constexpr int kPipeNT = 256;
+
+template <typename T, int N, int TX, int TY, int LZ>
+struct PipeShape {
+  static constexpr int M = N / 2;
+  static constexpr int SX = N * TX + N, SY = N * TY + N, SZ = LZ * M + N;
+  static constexpr int SMEM = SX > SY ? (SX > SZ ? SX : SZ) : (SY > SZ ? SY : SZ);
+};
+
+template <typename T, int N, int TX, int TY, int LZ>
+__global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict__ sched, PipeArgs<T> a) {
+  constexpr int M = N / 2;
+  __shared__ cpx<T> smem[PipeShape<T, N, TX, TY, LZ>::SMEM];
+  const uint32_t e = sched[blockIdx.x];
+  const int role = (int)(e >> 30);
+  const int idx = (int)(e & 0x3FFFFFFFu);
+  if (role == 0) {
+    role_x<T, N, TX, kPipeNT>(smem, idx % (M / TX), idx / (M / TX), a.bx, a.wtab_x, a.tw, a.k0, a.k1);
+  } else if (role == 1) {
+    role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw);
+  } else if (role == 2) {
+    role_z<T, N, LZ, kPipeNT>(smem, idx, a.bz, a.tw);
+  } else {
+    const int64_t i = (int64_t)idx * kPipeNT + threadIdx.x;
+    if (i < a.npix) {
+      if (a.cubic)
+        gather_pixel<T, 4>(a.field_g, N, a.scale, a.half, a.r, a.dirs, i, a.out);
+      else
+        gather_pixel<T, 2>(a.field_g, N, a.scale, a.half, a.r, a.dirs, i, a.out);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ dispatch tables
@@ -299,12 +382,45 @@ hipError_t run_z(const FieldArgs& a, hipStream_t s) {
 
 constexpr int kChoices = 3;
 
+using PipeFn = hipError_t (*)(const PipeLaunch&, hipStream_t);
+
+template <typename T, int N, int TX, int TY, int LZ>
+hipError_t run_pipe(const PipeLaunch& a, hipStream_t s) {
+  PipeArgs<T> p;
+  p.bx = (cpx<T>*)a.bx;
+  p.wtab_x = (const T*)a.wtab_x;
+  p.k0 = a.k0;
+  p.k1 = a.k1;
+  p.by = (cpx<T>*)a.by;
+  p.bz = (cpx<T>*)a.bz;
+  p.field_g = (const T*)a.field_g;
+  p.dirs = a.dirs;
+  p.out = (T*)a.out;
+  p.npix = a.npix;
+  p.r = a.r;
+  p.scale = a.scale;
+  p.half = a.half;
+  p.cubic = a.cubic;
+  p.tw = (const cpx<T>*)a.tw;
+  hipLaunchKernelGGL((k_pipeline<T, N, TX, TY, LZ>), dim3(a.nblocks), dim3(kPipeNT), 0, s, a.sched, p);
+  return hipGetLastError();
+}
+
+// pipelined tiles: half the default column tile (smaller LDS footprint, so more
+// workgroups of mixed roles fit on a CU) and z blocks of about the same LDS size
+template <typename T>
+constexpr int pipe_lines(int N, int tx) {
+  return (N * N) % (2 * tx) == 0 ? 2 * tx : default_lines<T>(N);
+}
+
 struct Entry {
   int dtype, N;
   int tz[kChoices];
   PassFn x[kChoices], y[kChoices];
   int lines[kChoices];
   PassFn z[kChoices];
+  int ptx, pty, plz;
+  PipeFn pipe;
 };
 
 template <typename T, int N>
@@ -312,13 +428,18 @@ constexpr Entry make_entry() {
   constexpr int d = default_tz<T>(N);
   constexpr int t0 = d, t1 = tz_choice(d, N, 1), t2 = tz_choice(d, N, 2);
   constexpr int l0 = lines_choice<T>(N, 0), l1 = lines_choice<T>(N, 1), l2 = lines_choice<T>(N, 2);
+  constexpr int px = t1, pz = pipe_lines<T>(N, t1);
   return Entry{sizeof(T) == 4 ? kF32 : kF64,
                N,
                {t0, t1, t2},
                {&run_x<T, N, t0>, &run_x<T, N, t1>, &run_x<T, N, t2>},
                {&run_y<T, N, t0>, &run_y<T, N, t1>, &run_y<T, N, t2>},
                {l0, l1, l2},
-               {&run_z<T, N, l0>, &run_z<T, N, l1>, &run_z<T, N, l2>}};
+               {&run_z<T, N, l0>, &run_z<T, N, l1>, &run_z<T, N, l2>},
+               px,
+               px,
+               pz,
+               &run_pipe<T, N, px, px, pz>};
 }
 
 #define CMBX_SIZES(T)                                                                                     \
@@ -383,6 +504,21 @@ hipError_t launch_pass_z(const FieldArgs& a, hipStream_t s) {
   const int i = e ? pick(e->lines, a.lines_z) : -1;
   if (i < 0) return hipErrorInvalidValue;
   return e->z[i](a, s);
+}
+
+bool pipeline_shape(int dtype, int N, int* tx, int* ty, int* lz) {
+  const Entry* e = find(dtype, N);
+  if (!e) return false;
+  *tx = e->ptx;
+  *ty = e->pty;
+  *lz = e->plz;
+  return true;
+}
+
+hipError_t launch_pipeline(const PipeLaunch& a, hipStream_t s) {
+  const Entry* e = find(a.dtype, a.N);
+  if (!e || a.nblocks < 1) return hipErrorInvalidValue;
+  return e->pipe(a, s);
 }
 
 hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uint32_t k0, uint32_t k1,

@@ -46,4 +46,29 @@ struct GatherArgs {
 };
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 
+// Pipelined launch: one workgroup per schedule entry (role << 30 | index), role 0 = pass x
+// (tile index zt + (N/2/tx) iy), 1 = pass y (zt + (N/2/ty) ix), 2 = pass z (line block of
+// lz lines), 3 = gather (pixel block of 256). Each role works on its own buffer.
+struct PipeLaunch {
+  int dtype, N;
+  const uint32_t* sched;
+  int nblocks;
+  void* bx;
+  const void* wtab_x;
+  uint32_t k0, k1;
+  void* by;
+  void* bz;
+  const void* field_g;
+  const double* dirs;
+  void* out;
+  int64_t npix;
+  double r, scale, half;
+  int cubic;
+  const void* tw;
+};
+hipError_t launch_pipeline(const PipeLaunch& a, hipStream_t s);
+// Tile shapes of the pipelined kernel for (dtype, N); false if N is not compiled.
+bool pipeline_shape(int dtype, int N, int* tx, int* ty, int* lz);
+constexpr int kPipeThreads = 256;
+
 }  // namespace cmbx
