@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--boxes", type=int, default=4, help="512^3 boxes per step (<= 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--mode", default="auto", choices=["auto", "chained", "pipelined"],
+                    help="ensemble execution mode of the batched path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): independent realisations "
@@ -109,7 +111,8 @@ def main():
     torch.cuda.set_device(0)
     jobs = build_jobs(torch, cmbx, workloads, args.boxes)
     nmaps = len(jobs)
-    ens = cmbx.Ensemble([dict(plan=j["plan"], seed=j["seed"], r=j["r"], dirs=j["dirs"], out=j["out"]) for j in jobs])
+    ens = cmbx.Ensemble([dict(plan=j["plan"], seed=j["seed"], r=j["r"], dirs=j["dirs"], out=j["out"]) for j in jobs],
+                        mode=args.mode)
 
     def step_batched():
         ens.launch()
@@ -175,6 +178,7 @@ def main():
         "config": {"workload": f"{nmaps}x512^3 FP32 batched (one hipGraph), r=0.45L, caps U[10,40] deg, tricubic",
                    "boxes": nmaps, "N": N, "pixels": [j["n_pix"] for j in jobs], "maps_per_step": nmaps},
         "plain_maps_per_s": round(plain, 2),
+        "ensemble_mode": ens.modes,
         "batched_over_plain": round(value / plain, 3),
         "wall_s": {"batched": round(wall_b, 4), "plain": round(wall_p, 4)},
         "path_GBps_alg": round(path_gbs, 1),

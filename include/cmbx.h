@@ -119,20 +119,32 @@ typedef struct cmbx_job {
   void* out;           /* device [batch][n_pix] */
 } cmbx_job;
 
+/* ensemble execution modes */
+#define CMBX_ENS_AUTO      0 /* time both modes per (precision, N) group at creation, keep the faster */
+#define CMBX_ENS_CHAINED   1 /* each realisation's four kernels in turn, in its plan's workspace */
+#define CMBX_ENS_PIPELINED 2 /* software pipeline of fused launches (see below) */
+
 /*
- * Capture the jobs into one HIP graph of software-pipelined launches. Every realisation of
- * every job (job j's plan has `batch` of them, seeds seed + b, maps at out + b n_pix) is an
- * item; items of equal (precision, N) form one pipeline whose launch t runs, side by side
- * in one kernel, the noise + x pass of item t, the y pass of item t-1, the z pass of item
- * t-2 and the gather of item t-3, so that the ALU-bound noise work and the HBM-bound
- * transforms share the GPU. Pipelines of different sizes run one after another. The
- * ensemble owns min(4, items) workspaces per pipeline (the plans' workspaces are not
- * touched); buffers passed in stay caller-owned and must outlive it, and so must the
- * plans, whose weight and twiddle tables are read when the graph runs (interpolant, r and
- * pixel counts are fixed at creation). Errors: as cmbx_simulate_patch for each job,
- * CMBX_EINVAL for n_jobs < 1, CMBX_ENOMEM.
+ * Capture the jobs into one HIP graph. Every realisation of every job (job j's plan has
+ * `batch` of them, seeds seed + b, maps at out + b n_pix) is an item; items of equal
+ * (precision, N) form a group, and groups run one after another in job order.
+ * - CMBX_ENS_CHAINED: the items of a group run one after another, each through the same
+ *   four kernels (tile shapes as set on its plan) in its plan's workspace slot b.
+ * - CMBX_ENS_PIPELINED: launch t of a group runs, side by side in one kernel, the noise + x
+ *   pass of item t, the y pass of item t-1, the z pass of item t-2 and the gather of item
+ *   t-3 (workgroups of the four roles interleaved), on min(4, items) workspaces owned by
+ *   the ensemble.
+ * - CMBX_ENS_AUTO: both are captured for each group and timed (the outputs are written
+ *   meanwhile); the faster is kept (cmbx_ensemble_modes reports the choice).
+ * Buffers passed in stay caller-owned and must outlive the ensemble, and so must the
+ * plans, whose weight and twiddle tables and workspaces are used when the graph runs
+ * (interpolant, r and pixel counts are fixed at creation). Errors: as cmbx_simulate_patch
+ * for each job, CMBX_EINVAL for n_jobs < 1 or an unknown mode, CMBX_ENOMEM.
  */
-int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, cmbx_ensemble** out);
+int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemble** out);
+/* Mode chosen for each group (in order of first appearance) written to modes[0 .. cap);
+ * returns the number of groups, or CMBX_EINVAL for a NULL ensemble. */
+int cmbx_ensemble_modes(const cmbx_ensemble* ens, int* modes, int cap);
 /* Launch the captured graph on `stream` (a hipStream_t; NULL = the default stream). */
 int cmbx_ensemble_launch(cmbx_ensemble* ens, void* stream);
 /* Release an ensemble (waits for the device first). NULL is accepted. */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libcmbx.so")
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 F32, F64 = 1, 2
 TRILINEAR, TRICUBIC = 1, 2
+ENS_AUTO, ENS_CHAINED, ENS_PIPELINED = 0, 1, 2
 OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y = 1, 2, 3, 4, 5, 6
 
 _DTYPES = {"f32": F32, "float32": F32, F32: F32, "f64": F64, "float64": F64, F64: F64}
@@ -53,7 +54,8 @@ def lib():
                                    ctypes.POINTER(P)]),
             "cmbx_spectrum_table": (I, [P, P, P, I64]),
             "cmbx_simulate_patch": (I, [P, U64, D, P, I64, P]),
-            "cmbx_ensemble_create": (I, [ctypes.POINTER(_Job), I, ctypes.POINTER(P)]),
+            "cmbx_ensemble_create": (I, [ctypes.POINTER(_Job), I, I, ctypes.POINTER(P)]),
+            "cmbx_ensemble_modes": (I, [P, ctypes.POINTER(I), I]),
             "cmbx_ensemble_launch": (I, [P, P]),
             "cmbx_ensemble_destroy": (I, [P]),
             "cmbx_debug_noise": (I, [P, U64, P]),
@@ -350,7 +352,9 @@ def _hip():
 class Ensemble:
     """Jobs captured into one HIP graph (cmbx_ensemble_create)."""
 
-    def __init__(self, jobs):
+    _MODES = {"auto": ENS_AUTO, "chained": ENS_CHAINED, "pipelined": ENS_PIPELINED}
+
+    def __init__(self, jobs, mode="auto"):
         """jobs: list of dict(plan=Plan, seed, r, dirs=tensor, out=tensor)."""
         arr = (_Job * len(jobs))()
         self._keep = []
@@ -360,8 +364,16 @@ class Ensemble:
             arr[i] = _Job(p.handle, int(j["seed"]), float(j["r"]), d, n_pix, o)
             self._keep.append(j)
         h = ctypes.c_void_p()
-        _check(lib().cmbx_ensemble_create(arr, len(jobs), ctypes.byref(h)))
+        _check(lib().cmbx_ensemble_create(arr, len(jobs), self._MODES.get(mode, mode), ctypes.byref(h)))
         self.handle = h.value
+
+    @property
+    def modes(self):
+        """Execution mode per (precision, N) group: "chained" or "pipelined"."""
+        buf = (ctypes.c_int * 64)()
+        n = lib().cmbx_ensemble_modes(self.handle, buf, 64)
+        names = {ENS_CHAINED: "chained", ENS_PIPELINED: "pipelined"}
+        return [names.get(buf[i], buf[i]) for i in range(min(n, 64))]
 
     def launch(self, stream=None):
         import torch

@@ -40,6 +40,7 @@ struct cmbx_ensemble {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<void*> dev;  // rotating workspaces and the schedule
+  std::vector<int> modes;  // execution mode chosen per (precision, N) group
   int device = 0;
 };
 
@@ -394,6 +395,7 @@ namespace {
 // One realisation to simulate inside an ensemble.
 struct Item {
   const cmbx_plan* plan;
+  int slot;  // batch slot of the plan's workspace (chained mode)
   uint64_t seed;
   double r;
   const double* dirs;
@@ -419,12 +421,88 @@ void interleave(const int64_t cnt[4], std::vector<uint32_t>& sched) {
   }
 }
 
+// A group of items of one (precision, N) and what each execution mode needs.
+struct Group {
+  int dtype = 0, N = 0;
+  std::vector<Item> items;
+  std::vector<void*> bufs;              // pipelined: rotating workspaces (owned)
+  std::vector<cmbx::PipeLaunch> pipe;   // pipelined launches (sched = offset until upload)
+  std::vector<size_t> sched_off;
+  int mode = CMBX_ENS_CHAINED;
+};
+
+int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t s) {
+  if (mode == CMBX_ENS_CHAINED) {
+    for (const Item& it : gr.items) {
+      char* buf = (char*)it.plan->field + (size_t)it.slot * it.plan->field_bytes();
+      if (int rc = enqueue_field(it.plan, it.seed, buf, s)) return rc;
+      if (int rc = enqueue_gather(it.plan, buf, it.r, it.dirs, it.n_pix, it.out, s)) return rc;
+    }
+    return CMBX_OK;
+  }
+  for (size_t i = 0; i < gr.pipe.size(); ++i) {
+    cmbx::PipeLaunch a = gr.pipe[i];
+    a.sched = dsched + gr.sched_off[i];
+    HIP_TRY(cmbx::launch_pipeline(a, s));
+  }
+  return CMBX_OK;
+}
+
+// Capture the groups (each in its chosen mode, or all in `force` if >= 0) into a graph.
+int capture(const std::vector<Group>& groups, const uint32_t* dsched, int only, int force, hipGraph_t* graph,
+            hipGraphExec_t* exec) {
+  hipStream_t cap = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  int rc = CMBX_OK;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  for (size_t gi = 0; e == hipSuccess && rc == CMBX_OK && gi < groups.size(); ++gi) {
+    if (only >= 0 && (int)gi != only) continue;
+    rc = enqueue_group(groups[gi], force >= 0 ? force : groups[gi].mode, dsched, cap);
+  }
+  hipGraph_t gph = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(cap, &gph);
+  if (e == hipSuccess) e = e_end;
+  (void)hipStreamDestroy(cap);
+  if (rc == CMBX_OK && e == hipSuccess) e = hipGraphInstantiate(exec, gph, nullptr, nullptr, 0);
+  if (rc != CMBX_OK || e != hipSuccess) {
+    if (gph) (void)hipGraphDestroy(gph);
+    if (rc != CMBX_OK) return rc;
+    return fail(CMBX_EHIP, "ensemble capture: %s", hipGetErrorString(e));
+  }
+  *graph = gph;
+  return CMBX_OK;
+}
+
+// Average milliseconds of a graph over three launches after two warm-ups (-1 on error).
+double time_graph(hipGraphExec_t exec) {
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double ms = -1.0;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+      hipEventCreate(&e1) == hipSuccess) {
+    hipError_t e = hipSuccess;
+    for (int i = 0; e == hipSuccess && i < 2; ++i) e = hipGraphLaunch(exec, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int i = 0; e == hipSuccess && i < 3; ++i) e = hipGraphLaunch(exec, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / 3.0;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  return ms;
+}
+
 }  // namespace
 
-int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, cmbx_ensemble** out) {
+int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemble** out) {
   if (!out) return fail(CMBX_EINVAL, "out is NULL");
   *out = nullptr;
   if (!jobs || n_jobs < 1) return fail(CMBX_EINVAL, "need at least one job");
+  if (mode != CMBX_ENS_AUTO && mode != CMBX_ENS_CHAINED && mode != CMBX_ENS_PIPELINED)
+    return fail(CMBX_EINVAL, "unknown ensemble mode %d", mode);
   for (int j = 0; j < n_jobs; ++j) {
     if (!jobs[j].plan) return fail(CMBX_EINVAL, "job %d has no plan", j);
     if (int rc = check_patch_args(jobs[j].plan, jobs[j].r, jobs[j].dirs, jobs[j].n_pix, jobs[j].out)) {
@@ -434,116 +512,134 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, cmbx_ensemble** out) 
     if (jobs[j].plan->device != jobs[0].plan->device) return fail(CMBX_EINVAL, "all jobs must be on one device");
   }
   DeviceGuard g(jobs[0].plan->device);
-  // Realisations grouped by (precision, N), in job order; each group is one software
-  // pipeline of pipelined launches.
-  std::vector<std::pair<int, int>> keys;
-  std::map<std::pair<int, int>, std::vector<Item>> groups;
+  // Realisations grouped by (precision, N), in job order.
+  std::vector<Group> groups;
+  std::map<std::pair<int, int>, size_t> index;
   for (int j = 0; j < n_jobs; ++j) {
     const cmbx_plan* p = jobs[j].plan;
     const auto key = std::make_pair(p->dtype, p->N);
-    if (!groups.count(key)) keys.push_back(key);
+    if (!index.count(key)) {
+      index[key] = groups.size();
+      groups.emplace_back();
+      groups.back().dtype = p->dtype;
+      groups.back().N = p->N;
+    }
+    Group& gr = groups[index[key]];
     for (int b = 0; b < p->batch; ++b)
-      groups[key].push_back(Item{p, jobs[j].seed + (uint64_t)b, jobs[j].r, jobs[j].dirs, jobs[j].n_pix,
-                                 (char*)jobs[j].out + (size_t)b * jobs[j].n_pix * p->real_size()});
+      gr.items.push_back(Item{p, b, jobs[j].seed + (uint64_t)b, jobs[j].r, jobs[j].dirs, jobs[j].n_pix,
+                              (char*)jobs[j].out + (size_t)b * jobs[j].n_pix * p->real_size()});
   }
+  // Within a group the chained mode runs items one after another in their plans'
+  // workspaces; a plan used by two jobs is fine there (they run in order).
   cmbx_ensemble* en = new cmbx_ensemble;
   en->device = jobs[0].plan->device;
   auto bail = [&](int code, const std::string& msg) {
     for (void* d : en->dev) (void)hipFree(d);
     delete en;
-    return fail(code, "%s", msg.c_str());
+    return code == CMBX_OK ? CMBX_OK : fail(code, "%s", msg.c_str());
   };
-  struct Launch {
-    cmbx::PipeLaunch a;
-    size_t off;
-  };
-  std::vector<Launch> launches;
   std::vector<uint32_t> sched;
-  for (const auto& key : keys) {
-    const std::vector<Item>& items = groups[key];
-    const int dtype = key.first, N = key.second, M = N / 2;
-    const cmbx_plan* p0 = items[0].plan;
-    int tx, ty, lz;
-    if (!cmbx::pipeline_shape(dtype, N, &tx, &ty, &lz)) return bail(CMBX_EUNSUPPORTED, "no pipelined kernel for N");
-    const int n = (int)items.size();
-    const int nbuf = n < 4 ? n : 4;
-    std::vector<void*> bufs(nbuf, nullptr);
-    for (int i = 0; i < nbuf; ++i) {
-      const hipError_t e = hipMalloc(&bufs[i], p0->field_bytes());
-      if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "ensemble workspace");
-      en->dev.push_back(bufs[i]);
+  if (mode != CMBX_ENS_CHAINED) {
+    for (Group& gr : groups) {
+      const int N = gr.N, M = N / 2;
+      const cmbx_plan* p0 = gr.items[0].plan;
+      int tx, ty, lz;
+      if (!cmbx::pipeline_shape(gr.dtype, N, &tx, &ty, &lz)) return bail(CMBX_EUNSUPPORTED, "no pipelined kernel");
+      const int n = (int)gr.items.size();
+      const int nbuf = n < 4 ? n : 4;
+      gr.bufs.assign(nbuf, nullptr);
+      for (int i = 0; i < nbuf; ++i) {
+        const hipError_t e = hipMalloc(&gr.bufs[i], p0->field_bytes());
+        if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "ensemble workspace");
+        en->dev.push_back(gr.bufs[i]);
+      }
+      for (int t = 0; t < n + 3; ++t) {
+        const int ix = t, iy = t - 1, iz = t - 2, ig = t - 3;
+        int64_t cnt[4] = {0, 0, 0, 0};
+        cmbx::PipeLaunch a{};
+        a.dtype = gr.dtype;
+        a.N = N;
+        a.tw = p0->tw;
+        if (ix < n) {
+          cnt[0] = (int64_t)(M / tx) * N;
+          a.bx = gr.bufs[ix % nbuf];
+          a.wtab_x = gr.items[ix].plan->wtab;
+          a.k0 = (uint32_t)(gr.items[ix].seed & 0xffffffffu);
+          a.k1 = (uint32_t)(gr.items[ix].seed >> 32);
+        }
+        if (iy >= 0 && iy < n) {
+          cnt[1] = (int64_t)(M / ty) * N;
+          a.by = gr.bufs[iy % nbuf];
+        }
+        if (iz >= 0 && iz < n) {
+          cnt[2] = (int64_t)N * N / lz;
+          a.bz = gr.bufs[iz % nbuf];
+        }
+        if (ig >= 0 && ig < n) {
+          const Item& it = gr.items[ig];
+          cnt[3] = (it.n_pix + cmbx::kPipeThreads - 1) / cmbx::kPipeThreads;
+          a.field_g = gr.bufs[ig % nbuf];
+          a.dirs = it.dirs;
+          a.out = it.out;
+          a.npix = it.n_pix;
+          a.r = it.r;
+          a.scale = (double)N / it.plan->L;
+          a.half = 0.5 * it.plan->L;
+          a.cubic = it.plan->interp == CMBX_TRICUBIC;
+        }
+        gr.sched_off.push_back(sched.size());
+        interleave(cnt, sched);
+        a.nblocks = (int)(sched.size() - gr.sched_off.back());
+        gr.pipe.push_back(a);
+      }
     }
-    for (int t = 0; t < n + 3; ++t) {
-      const int ix = t, iy = t - 1, iz = t - 2, ig = t - 3;
-      int64_t cnt[4] = {0, 0, 0, 0};
-      cmbx::PipeLaunch a{};
-      a.dtype = dtype;
-      a.N = N;
-      a.tw = p0->tw;
-      if (ix < n) {
-        cnt[0] = (int64_t)(M / tx) * N;
-        a.bx = bufs[ix % nbuf];
-        a.wtab_x = items[ix].plan->wtab;
-        a.k0 = (uint32_t)(items[ix].seed & 0xffffffffu);
-        a.k1 = (uint32_t)(items[ix].seed >> 32);
+  }
+  uint32_t* dsched = nullptr;
+  if (!sched.empty()) {
+    hipError_t e = hipMalloc((void**)&dsched, sched.size() * sizeof(uint32_t));
+    if (e != hipSuccess) return bail(CMBX_ENOMEM, "ensemble schedule");
+    en->dev.push_back(dsched);
+    e = hipMemcpy(dsched, sched.data(), sched.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(CMBX_EHIP, std::string("schedule upload: ") + hipGetErrorString(e));
+  }
+  for (Group& gr : groups) gr.mode = mode == CMBX_ENS_AUTO ? CMBX_ENS_CHAINED : mode;
+  if (mode == CMBX_ENS_AUTO) {
+    // time each group alone in both modes and keep the faster
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      double t[2] = {-1.0, -1.0};
+      const int modes[2] = {CMBX_ENS_CHAINED, CMBX_ENS_PIPELINED};
+      for (int k = 0; k < 2; ++k) {
+        hipGraph_t gph = nullptr;
+        hipGraphExec_t ex = nullptr;
+        if (int rc = capture(groups, dsched, (int)gi, modes[k], &gph, &ex)) return bail(rc, g_err);
+        t[k] = time_graph(ex);
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(gph);
+        if (t[k] < 0) return bail(CMBX_EHIP, "ensemble autotune launch failed");
       }
-      if (iy >= 0 && iy < n) {
-        cnt[1] = (int64_t)(M / ty) * N;
-        a.by = bufs[iy % nbuf];
-      }
-      if (iz >= 0 && iz < n) {
-        cnt[2] = (int64_t)N * N / lz;
-        a.bz = bufs[iz % nbuf];
-      }
-      if (ig >= 0 && ig < n) {
-        const Item& it = items[ig];
-        cnt[3] = (it.n_pix + cmbx::kPipeThreads - 1) / cmbx::kPipeThreads;
-        a.field_g = bufs[ig % nbuf];
-        a.dirs = it.dirs;
-        a.out = it.out;
-        a.npix = it.n_pix;
-        a.r = it.r;
-        a.scale = (double)N / it.plan->L;
-        a.half = 0.5 * it.plan->L;
-        a.cubic = it.plan->interp == CMBX_TRICUBIC;
-      }
-      const size_t off = sched.size();
-      interleave(cnt, sched);
-      a.nblocks = (int)(sched.size() - off);
-      launches.push_back(Launch{a, off});
+      groups[gi].mode = t[1] < t[0] ? CMBX_ENS_PIPELINED : CMBX_ENS_CHAINED;
     }
   }
-  void* dsched = nullptr;
-  hipError_t e = hipMalloc(&dsched, sched.size() * sizeof(uint32_t));
-  if (e != hipSuccess) return bail(CMBX_ENOMEM, "ensemble schedule");
-  en->dev.push_back(dsched);
-  e = hipMemcpy(dsched, sched.data(), sched.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return bail(CMBX_EHIP, std::string("schedule upload: ") + hipGetErrorString(e));
-  hipStream_t cap = nullptr;
-  e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-  if (e != hipSuccess) return bail(CMBX_EHIP, "capture stream");
-  hipGraph_t graph = nullptr;
-  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  for (size_t i = 0; e == hipSuccess && i < launches.size(); ++i) {
-    cmbx::PipeLaunch a = launches[i].a;
-    a.sched = (const uint32_t*)dsched + launches[i].off;
-    e = cmbx::launch_pipeline(a, cap);
+  if (int rc = capture(groups, dsched, -1, -1, &en->graph, &en->exec)) return bail(rc, g_err);
+  bool any_pipe = false;
+  for (const Group& gr : groups) {
+    en->modes.push_back(gr.mode);
+    any_pipe = any_pipe || gr.mode == CMBX_ENS_PIPELINED;
   }
-  const hipError_t e_end = hipStreamEndCapture(cap, &graph);
-  if (e == hipSuccess) e = e_end;
-  (void)hipStreamDestroy(cap);
-  if (e != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return bail(CMBX_EHIP, std::string("ensemble capture: ") + hipGetErrorString(e));
+  if (!any_pipe) {
+    // the rotating workspaces and the schedule are not used by the chosen graph
+    for (void* d : en->dev) (void)hipFree(d);
+    en->dev.clear();
   }
-  e = hipGraphInstantiate(&en->exec, graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return bail(CMBX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-  }
-  en->graph = graph;
   *out = en;
   return ok();
+}
+
+int cmbx_ensemble_modes(const cmbx_ensemble* en, int* modes, int cap) {
+  if (!en) return fail(CMBX_EINVAL, "ensemble is NULL");
+  const int n = (int)en->modes.size();
+  for (int i = 0; modes && i < n && i < cap; ++i) modes[i] = en->modes[i];
+  return n;
 }
 
 int cmbx_ensemble_launch(cmbx_ensemble* en, void* stream) {

@@ -196,10 +196,11 @@ def test_errors_on_device(cmbx):
 
 
 # ------------------------------------------------------------------ ensemble (graph)
+@pytest.mark.parametrize("mode", ["chained", "pipelined", "auto"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-def test_ensemble_graph_matches_plain_and_oracle(cmbx, dt):
-    """The pipelined hipGraph ensemble (mixed sizes, batches, both interpolants) gives the
-    plain path's maps up to rounding, and the oracle's to the parity bar, on every replay."""
+def test_ensemble_graph_matches_plain_and_oracle(cmbx, dt, mode):
+    """The hipGraph ensemble (mixed sizes, batches, both interpolants) gives the plain path's
+    maps up to rounding, and the oracle's to the parity bar, on every replay."""
     specs = [(32, 3, 12.0, "tricubic"), (48, 2, 25.0, "trilinear"), (32, 1, 33.0, "tricubic"),
              (64, 2, 18.0, "tricubic"), (48, 1, 40.0, "tricubic")]
     jobs, plans = [], []
@@ -210,7 +211,8 @@ def test_ensemble_graph_matches_plain_and_oracle(cmbx, dt):
         dirs = torch.tensor(dirs_np, device="cuda")
         out = torch.empty((batch, dirs.shape[0]), dtype=p.torch_dtype, device="cuda")
         jobs.append(dict(plan=p, seed=50 + 10 * i, r=0.45, dirs=dirs, out=out, dirs_np=dirs_np, k=k, pk=pk))
-    ens = cmbx.Ensemble([{kk: j[kk] for kk in ("plan", "seed", "r", "dirs", "out")} for j in jobs])
+    ens = cmbx.Ensemble([{kk: j[kk] for kk in ("plan", "seed", "r", "dirs", "out")} for j in jobs], mode=mode)
+    assert len(ens.modes) == 3 and (mode == "auto" or set(ens.modes) == {mode})
     refs = []
     for j in jobs:
         ref = j["plan"].simulate_patch(j["seed"], j["r"], j["dirs"]).cpu().numpy()
@@ -251,7 +253,8 @@ def test_ensemble_512_sampled(cmbx):
         dirs = torch.tensor(workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"]), device="cuda")
         out = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
         jobs.append(dict(plan=p, seed=j["seed"], r=0.45, dirs=dirs, out=out, amp=j["amp"], k=k, pk=pk))
-    ens = cmbx.Ensemble([{kk: j[kk] for kk in ("plan", "seed", "r", "dirs", "out")} for j in jobs])
+    ens = cmbx.Ensemble([{kk: j[kk] for kk in ("plan", "seed", "r", "dirs", "out")} for j in jobs],
+                        mode="pipelined")
     ens.launch()
     torch.cuda.synchronize()
     for j in jobs:
