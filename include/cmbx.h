@@ -162,7 +162,8 @@ int cmbx_debug_field(cmbx_plan* plan, uint64_t seed, void* field);
  * buf holds complex [N][N][N/2]: the half grid transformed along x (and y), with column
  * iz = 0 carrying Z(iz=0) + i Z(iz=N/2); after pass 3 it is the real field. */
 int cmbx_debug_passes(cmbx_plan* plan, uint64_t seed, int npasses, void* buf);
-/* Interpolate a caller-given device field [N][N][N] (plan precision) at the pixels. */
+/* Interpolate a caller-given device field [N][N][N] (plan precision, 16-byte aligned) at
+ * the pixels. CMBX_EINVAL for a misaligned field. */
 int cmbx_debug_gather(cmbx_plan* plan, const void* field, double r, const double* dirs,
                       int64_t n_pix, void* out);
 

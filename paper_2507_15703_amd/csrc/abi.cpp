@@ -382,6 +382,7 @@ int cmbx_debug_passes(cmbx_plan* p, uint64_t seed, int npasses, void* buf) {
 int cmbx_debug_gather(cmbx_plan* p, const void* field, double r, const double* dirs, int64_t n_pix, void* out) {
   if (int rc = check_plan(p)) return rc;
   if (!field) return fail(CMBX_EINVAL, "field is NULL");
+  if ((uintptr_t)field % 16 != 0) return fail(CMBX_EINVAL, "field must be 16-byte aligned");
   if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2", r);
   if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "bad n_pix %lld", (long long)n_pix);
   if (!dirs || !out) return fail(CMBX_EINVAL, "dirs and out must be non-NULL");

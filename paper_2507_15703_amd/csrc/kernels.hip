@@ -228,6 +228,51 @@ __device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N,
       weights1d<T>((T)(p - fl), w[d], K == 4 ? kTricubic : kTrilinear);
     }
   }
+  // Tricubic fast path: the four z taps of a line are read with aligned 16-byte vector
+  // loads (two for FP32, three for FP64) covering them, and the z weights are shifted to
+  // the taps' offset inside that window, so a line costs 2-3 load instructions instead of
+  // four. Taken when the window stays inside the line (no z wrap); otherwise the
+  // per-tap path below.
+  if constexpr (K == 4) {
+    constexpr int VEC = 16 / (int)sizeof(T);        // values per 16-byte load
+    constexpr int NV = sizeof(T) == 4 ? 2 : 3;       // loads per line
+    const int a0 = i0[2] - (((i0[2] % VEC) + VEC) % VEC);
+    const int sh = i0[2] - a0;                        // 0 .. VEC-1
+    if (i0[2] >= 0 && a0 + NV * VEC <= N) {
+      T wz[NV * VEC];
+#pragma unroll
+      for (int k = 0; k < NV * VEC; ++k) {
+        const int c = k - sh;
+        wz[k] = (c == 0) ? w[2][0] : (c == 1) ? w[2][1] : (c == 2) ? w[2][2] : (c == 3) ? w[2][3] : T(0);
+      }
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int ix = wrap(i0[0] + a, N);
+        T accb = 0;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+          const int iy = wrap(i0[1] + bb, N);
+          const T* line = field + ((size_t)ix * N + iy) * N + a0;
+          T sum = 0;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            if constexpr (sizeof(T) == 4) {
+              const float4 q = *reinterpret_cast<const float4*>(line + 4 * v);
+              sum += wz[4 * v] * q.x + wz[4 * v + 1] * q.y + wz[4 * v + 2] * q.z + wz[4 * v + 3] * q.w;
+            } else {
+              const double2 q = *reinterpret_cast<const double2*>(line + 2 * v);
+              sum += wz[2 * v] * q.x + wz[2 * v + 1] * q.y;
+            }
+          }
+          accb += w[1][bb] * sum;
+        }
+        acc += w[0][a] * accb;
+      }
+      out[i] = acc;
+      return;
+    }
+  }
   int iz[K];
 #pragma unroll
   for (int c = 0; c < K; ++c) iz[c] = wrap(i0[2] + c, N);
