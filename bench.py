@@ -154,11 +154,21 @@ def main():
     names = ["pass_x_noise", "pass_y", "pass_z_c2r", "gather_tricubic"]
     kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
                for n, t, b in zip(names, ms, kbytes)}
-    # dominant HBM-bound kernel among the FFT passes
-    dom = max(range(3), key=lambda i: ms[i])
-    ach = kbytes[dom] / (ms[dom] * 1e-3) / 1e9
-    roofline = {"kernel": names[dom], "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    # The dominant kernel is the noise + x pass, bound by plain ALU issue: its algorithmic
+    # work per mode is the binary32 Box-Muller sequence (70 flops) + the two weight products
+    # + half a Philox4x32-10 call (10 rounds x (2 wide multiplies + 4 xor) / 2 = 30 integer
+    # ops) + the x transform (5 log2 N flops per point); peak = 256 CUs x 4 SIMDs x 16
+    # lanes x 2.4 GHz = 39.3 T lane-ops/s for unfused, unpacked operations.
+    modes = N**3 // 2
+    ops_per_mode = 70 + 2 + 30 + 5 * math.log2(N)
+    alu_peak = 256 * 4 * 16 * 2.4e9
+    ach_ops = modes * ops_per_mode / (ms[0] * 1e-3)
+    roofline = {"kernel": names[0], "bound": "alu", "achieved": round(ach_ops / 1e12, 2),
+                "peak": round(alu_peak / 1e12, 2), "unit": "Tops/s", "frac": round(ach_ops / alu_peak, 4),
+                "traffic": None, "ops_per_launch": int(modes * ops_per_mode)}
+    # the two transform passes are HBM-bound: fraction of the 8 TB/s peak
+    for i in (1, 2):
+        kernels[names[i]]["hbm_frac"] = round(kbytes[i] / (ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     map_bytes = 20 * N**3 + sum(28 * j["n_pix"] for j in jobs) / nmaps
     path_gbs = map_bytes * value / 1e9
 

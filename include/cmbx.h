@@ -192,6 +192,18 @@ int cmbx_plan_autotune(cmbx_plan* plan, int reps, int* best, double* ms);
  * lines. Writes up to 4 values to out and returns their count (0 if none). */
 int cmbx_tile_choices(int dtype, int N, int which, int* out);
 
+/*
+ * Enqueue one stage of the hot path for realisation `seed` on `stream` (a hipStream_t;
+ * NULL = the null stream), for callers that schedule the stages themselves (e.g. on
+ * streams restricted to different compute units). stage 0: noise + x pass into buf;
+ * 1: y pass on buf; 2: z pass on buf; 3: gather from buf (r, dirs, n_pix, out as in
+ * cmbx_simulate_patch; ignored by stages 0-2). buf: device, N^3 reals of the plan's
+ * precision, 16-byte aligned. Tile shapes are the plan's. Errors: CMBX_ESTATE (no
+ * spectrum), CMBX_EINVAL, CMBX_EHIP.
+ */
+int cmbx_enqueue_stage(cmbx_plan* plan, int stage, uint64_t seed, void* buf, double r, const double* dirs,
+                       int64_t n_pix, void* out, void* stream);
+
 /* Message of the calling thread's last failed call ("" if none). Valid until its next call. */
 const char* cmbx_last_error(void);
 /* Library version string. */

@@ -65,6 +65,7 @@ def lib():
             "cmbx_time_passes": (I, [P, U64, D, P, I64, P, I, ctypes.POINTER(D)]),
             "cmbx_plan_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
             "cmbx_tile_choices": (I, [I, I, I, ctypes.POINTER(I)]),
+            "cmbx_enqueue_stage": (I, [P, I, U64, P, D, P, I64, P, P]),
             "cmbx_last_error": (ctypes.c_char_p, []),
             "cmbx_version": (ctypes.c_char_p, []),
         }
@@ -272,6 +273,16 @@ class Plan:
         ms = (ctypes.c_double * 4)()
         _check(lib().cmbx_time_passes(self.handle, int(seed), float(r), d, n_pix, o, int(reps), ms))
         return list(ms)
+
+    def enqueue_stage(self, stage, seed, buf, r=0.0, dirs=None, out=None, stream=None):
+        """One stage (0 noise + x, 1 y, 2 z, 3 gather) of realisation ``seed`` on ``buf``."""
+        b = _ptr(buf, self.N**3 * self.real_size, self.torch_dtype, "buf")
+        d = o = None
+        n_pix = 0
+        if stage == 3:
+            d, o, n_pix = self._check_dirs_out(dirs, out)
+        s = 0 if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+        _check(lib().cmbx_enqueue_stage(self.handle, int(stage), int(seed), b, float(r), d, int(n_pix), o, s))
 
     def debug_noise(self, seed):
         import torch

@@ -755,6 +755,27 @@ int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
   return ok();
 }
 
+int cmbx_enqueue_stage(cmbx_plan* p, int stage, uint64_t seed, void* buf, double r, const double* dirs,
+                       int64_t n_pix, void* out, void* stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set");
+  if (!buf || (uintptr_t)buf % 16 != 0) return fail(CMBX_EINVAL, "buf must be a 16-byte aligned device pointer");
+  if (stage < 0 || stage > 3) return fail(CMBX_EINVAL, "stage = %d must be 0..3", stage);
+  if (stage == 3)
+    if (int rc = check_patch_args(p, r, dirs, n_pix, out)) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  const cmbx::FieldArgs a = field_args(p, seed, buf);
+  switch (stage) {
+    case 0: HIP_TRY(cmbx::launch_pass_x(a, s)); break;
+    case 1: HIP_TRY(cmbx::launch_pass_y(a, s)); break;
+    case 2: HIP_TRY(cmbx::launch_pass_z(a, s)); break;
+    default:
+      if (int rc = enqueue_gather(p, buf, r, dirs, n_pix, out, s)) return rc;
+  }
+  return ok();
+}
+
 const char* cmbx_last_error(void) { return g_err.c_str(); }
 
 const char* cmbx_version(void) { return "cmbx 0.1.0 (gfx950)"; }

@@ -1,7 +1,7 @@
 """A short, fixed launch sequence for rocprofv3 (kernel trace and counter passes).
 
-Runs, on one 512^3 FP32 plan (tricubic, r = 0.45 L, 30 deg cap of 768 x 2048 pixels):
-one warm-up realisation, then ``--reps`` launches of each kernel of the hot path through
+Runs, on one 512^3 FP32 plan (tricubic, r = 0.45 L, 30 deg cap of 768 x 2048 pixels,
+autotuned tile shapes unless given): one warm-up realisation, then ``--reps`` launches of each kernel of the hot path through
 cmbx_time_passes, and a device-to-device copy of exactly 512 MiB (torch) whose counter
 readings calibrate the HBM byte counters. Usage:
 
@@ -32,9 +32,12 @@ def main():
 
     N = args.N
     plan = cmbx.Plan(N, 1.0, args.dtype, batch=1, interp="tricubic")
-    plan.set_tiles(args.tile_xy, args.lines_z)
     k, p = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N / 4)
     plan.spectrum_table(k, p)
+    if args.tile_xy or args.lines_z:
+        plan.set_tiles(args.tile_xy, args.lines_z)
+    else:
+        plan.autotune(reps=3)  # the tile shapes bench.py uses
     dirs = torch.tensor(workloads.cap_directions(30.0, 768, 2048), device="cuda")
     out = torch.empty((1, dirs.shape[0]), dtype=plan.torch_dtype, device="cuda")
     plan.simulate_patch(1, 0.45, dirs, out)
