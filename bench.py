@@ -163,9 +163,13 @@ def main():
     ops_per_mode = 70 + 2 + 30 + 5 * math.log2(N)
     alu_peak = 256 * 4 * 16 * 2.4e9
     ach_ops = modes * ops_per_mode / (ms[0] * 1e-3)
+    # HBM bytes per launch of this kernel from rocprofv3 FETCH_SIZE (x2.0 calibration against
+    # a plain copy) + WRITE_SIZE, by tile width (counters of the current kernel code)
+    traffic_by_tile = {8: (5485.0625 * 2.0 + 524288.0) * 1024, 16: (6018.875 * 2.0 + 524288.0) * 1024}
+    tile_x = jobs[0]["tuned"]["tile_x"]
     roofline = {"kernel": names[0], "bound": "alu", "achieved": round(ach_ops / 1e12, 2),
                 "peak": round(alu_peak / 1e12, 2), "unit": "Tops/s", "frac": round(ach_ops / alu_peak, 4),
-                "traffic": None, "ops_per_launch": int(modes * ops_per_mode)}
+                "traffic": traffic_by_tile.get(tile_x), "ops_per_launch": int(modes * ops_per_mode)}
     # the two transform passes are HBM-bound: fraction of the 8 TB/s peak
     for i in (1, 2):
         kernels[names[i]]["hbm_frac"] = round(kbytes[i] / (ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
