@@ -204,6 +204,37 @@ int cmbx_tile_choices(int dtype, int N, int which, int* out);
 int cmbx_enqueue_stage(cmbx_plan* plan, int stage, uint64_t seed, void* buf, double r, const double* dirs,
                        int64_t n_pix, void* out, void* stream);
 
+/* ---- spectrum surrogate network (Sec. II B inversion, learned) ----
+ * Building blocks of a small MLP that maps a C_l vector to a P_inf table. All pointers are
+ * device memory, row-major, caller-owned; work is enqueued on `stream` (NULL = null
+ * stream). Errors: CMBX_EINVAL for non-positive sizes, NULL pointers or leading
+ * dimensions shorter than a row; CMBX_EHIP for launch failures. */
+
+/* C = op(A) op(B) (+ bias), Y = GELU(C) (act = 1) or C (act = 0; Y may be NULL).
+ * op(A) is M x K: A is FP32, stored M x K (lda >= K) or, with transA, K x M (lda >= M).
+ * op(B) is K x N: B is BF16 (b_bf16 = 1, raw 16-bit words) or FP32, stored K x N
+ * (ldb >= N) or, with transB, N x K (ldb >= K). Both operands are rounded to BF16 (nearest
+ * even) and multiplied on the matrix cores with FP32 accumulation. GELU is the exact
+ * x Phi(x). C is M x N FP32 (ldc >= N); bias has N values or is NULL. */
+int cmbx_mlp_gemm(int M, int N, int K, const float* A, int lda, int transA, const void* B, int ldb,
+                  int transB, int b_bf16, float* C, int ldc, const float* bias, int act, float* Y,
+                  int ldy, void* stream);
+/* dZ = dY * GELU'(Z), elementwise over n values. */
+int cmbx_mlp_gelu_backward(const float* Z, const float* dY, float* dZ, int64_t n, void* stream);
+/* out[c] = sum_r X[r][c] for a rows x cols matrix (the bias gradient). */
+int cmbx_mlp_colsum(const float* X, int rows, int cols, float* out, void* stream);
+/* Mean squared error over n values: dY = 2 (Y - T) / n and *loss = mean (Y - T)^2 (device
+ * scalar); `partial` is device scratch of at least cmbx_mlp_mse_partials(n) floats. */
+int cmbx_mlp_mse(const float* Y, const float* T, int64_t n, float* dY, float* partial, float* loss,
+                 void* stream);
+int64_t cmbx_mlp_mse_partials(int64_t n);
+/* One Adam step (Kingma & Ba) on n FP32 master weights w with moments m, v and gradient g
+ * at step `step` >= 1; writes the BF16 copy w_bf16 (raw 16-bit words) if not NULL. */
+int cmbx_mlp_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float beta1,
+                  float beta2, float eps, int step, uint16_t* w_bf16, void* stream);
+/* y = BF16(x), round to nearest even, n values. */
+int cmbx_bf16_round(const float* x, uint16_t* y, int64_t n, void* stream);
+
 /* Message of the calling thread's last failed call ("" if none). Valid until its next call. */
 const char* cmbx_last_error(void);
 /* Library version string. */

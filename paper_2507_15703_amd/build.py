@@ -17,7 +17,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libcmbx.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["kernels.hip", "abi.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "abi.cpp"]
 ARCH = "gfx950"
 
 

@@ -66,6 +66,14 @@ def lib():
             "cmbx_plan_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
             "cmbx_tile_choices": (I, [I, I, I, ctypes.POINTER(I)]),
             "cmbx_enqueue_stage": (I, [P, I, U64, P, D, P, I64, P, P]),
+            "cmbx_mlp_gemm": (I, [I, I, I, P, I, I, P, I, I, I, P, I, P, I, P, I, P]),
+            "cmbx_mlp_gelu_backward": (I, [P, P, P, I64, P]),
+            "cmbx_mlp_colsum": (I, [P, I, I, P, P]),
+            "cmbx_mlp_mse": (I, [P, P, I64, P, P, P, P]),
+            "cmbx_mlp_mse_partials": (I64, [I64]),
+            "cmbx_mlp_adam": (I, [P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, I, P, P]),
+            "cmbx_bf16_round": (I, [P, P, I64, P]),
             "cmbx_last_error": (ctypes.c_char_p, []),
             "cmbx_version": (ctypes.c_char_p, []),
         }

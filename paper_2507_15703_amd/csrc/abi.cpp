@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 struct cmbx_plan {
   int N = 0;
@@ -773,6 +774,56 @@ int cmbx_enqueue_stage(cmbx_plan* p, int stage, uint64_t seed, void* buf, double
     default:
       if (int rc = enqueue_gather(p, buf, r, dirs, n_pix, out, s)) return rc;
   }
+  return ok();
+}
+
+int cmbx_mlp_gemm(int M, int N, int K, const float* A, int lda, int transA, const void* B, int ldb, int transB,
+                  int b_bf16, float* C, int ldc, const float* bias, int act, float* Y, int ldy, void* stream) {
+  if (M < 1 || N < 1 || K < 1) return fail(CMBX_EINVAL, "gemm sizes must be >= 1 (M=%d N=%d K=%d)", M, N, K);
+  if (!A || !B || !C) return fail(CMBX_EINVAL, "gemm operands must be non-NULL");
+  if (lda < (transA ? M : K) || ldb < (transB ? K : N) || ldc < N || (Y && ldy < N))
+    return fail(CMBX_EINVAL, "gemm leading dimension shorter than a row");
+  cmbx::GemmArgs g{M, N, K, A, lda, transA ? 1 : 0, B, ldb, transB ? 1 : 0, b_bf16 ? 1 : 0, C, ldc, bias, act ? 1 : 0,
+                   Y, ldy};
+  HIP_TRY(cmbx::launch_gemm(g, (hipStream_t)stream));
+  return ok();
+}
+
+int cmbx_mlp_gelu_backward(const float* Z, const float* dY, float* dZ, int64_t n, void* stream) {
+  if (!Z || !dY || !dZ || n < 1) return fail(CMBX_EINVAL, "gelu_backward: bad arguments");
+  HIP_TRY(cmbx::launch_gelu_backward(Z, dY, dZ, n, (hipStream_t)stream));
+  return ok();
+}
+
+int cmbx_mlp_colsum(const float* X, int rows, int cols, float* out, void* stream) {
+  if (!X || !out || rows < 1 || cols < 1) return fail(CMBX_EINVAL, "colsum: bad arguments");
+  HIP_TRY(cmbx::launch_colsum(X, rows, cols, out, (hipStream_t)stream));
+  return ok();
+}
+
+int64_t cmbx_mlp_mse_partials(int64_t n) { return n < 1 ? 0 : cmbx::mse_partials(n); }
+
+int cmbx_mlp_mse(const float* Y, const float* T, int64_t n, float* dY, float* partial, float* loss, void* stream) {
+  if (!Y || !T || !dY || !partial || !loss || n < 1) return fail(CMBX_EINVAL, "mse: bad arguments");
+  if (cmbx::mse_partials(n) > (1 << 24)) return fail(CMBX_EINVAL, "mse: n too large");
+  HIP_TRY(cmbx::launch_mse(Y, T, n, dY, partial, loss, (hipStream_t)stream));
+  return ok();
+}
+
+int cmbx_mlp_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float beta1, float beta2, float eps,
+                  int step, uint16_t* w_bf16, void* stream) {
+  if (!w || !m || !v || !g || n < 1 || step < 1) return fail(CMBX_EINVAL, "adam: bad arguments");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    return fail(CMBX_EINVAL, "adam: betas must be in [0, 1) and eps > 0");
+  cmbx::AdamArgs a{w, m, v, g, n, lr, beta1, beta2, eps, 1.f - std::pow(beta1, (float)step),
+                   1.f - std::pow(beta2, (float)step), w_bf16};
+  HIP_TRY(cmbx::launch_adam(a, (hipStream_t)stream));
+  return ok();
+}
+
+int cmbx_bf16_round(const float* x, uint16_t* y, int64_t n, void* stream) {
+  if (!x || !y || n < 1) return fail(CMBX_EINVAL, "bf16_round: bad arguments");
+  HIP_TRY(cmbx::launch_to_bf16(x, y, n, (hipStream_t)stream));
   return ok();
 }
 

@@ -1,0 +1,126 @@
+"""The surrogate network's kernels against the FP64 oracle (same BF16-rounded operands)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cmbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_15703_amd import cmbx as c
+    c.lib()
+    return c
+
+
+def _bf16_words(x):
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)).view(np.int16)
+
+
+def _rel(a, b):
+    b = np.asarray(b, dtype=np.float64)
+    return np.max(np.abs(np.asarray(a, dtype=np.float64) - b)) / max(np.sqrt(np.mean(b * b)), 1e-30)
+
+
+@pytest.mark.parametrize("M,N,K", [(70, 45, 37), (256, 512, 130), (1, 3, 1), (129, 64, 513)])
+@pytest.mark.parametrize("ta", [0, 1])
+@pytest.mark.parametrize("tb", [0, 1])
+@pytest.mark.parametrize("bbf", [0, 1])
+def test_gemm_matches_bf16_product(cmbx, M, N, K, ta, tb, bbf):
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
+    Bm = rng.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
+    bias = rng.standard_normal(N).astype(np.float32)
+    Ad = torch.tensor(A, device="cuda")
+    Bd = torch.tensor(_bf16_words(Bm) if bbf else Bm, device="cuda")
+    biasd = torch.tensor(bias, device="cuda")
+    C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    Y = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    lda = M if ta else K
+    ldb = K if tb else N
+    cmbx._check(cmbx.lib().cmbx_mlp_gemm(M, N, K, Ad.data_ptr(), lda, ta, Bd.data_ptr(), ldb, tb, bbf, C.data_ptr(),
+                                         N, biasd.data_ptr(), 1, Y.data_ptr(), N, 0))
+    torch.cuda.synchronize()
+    opA = omlp.bf16(A.T if ta else A)
+    opB = omlp.bf16(Bm.T if tb else Bm)
+    ref = opA @ opB + bias
+    assert _rel(C.cpu().numpy(), ref) < 2e-6 * max(1.0, np.sqrt(K) / 8)
+    assert _rel(Y.cpu().numpy(), omlp.gelu(ref)) < 5e-6 * max(1.0, np.sqrt(K) / 8)
+
+
+def test_gemm_rejects_bad_arguments(cmbx):
+    L = cmbx.lib()
+    assert L.cmbx_mlp_gemm(0, 4, 4, 1, 4, 0, 1, 4, 0, 0, 1, 4, None, 0, None, 4, None) == cmbx.EINVAL
+    assert L.cmbx_mlp_gemm(4, 4, 4, 1, 3, 0, 1, 4, 0, 0, 1, 4, None, 0, None, 4, None) == cmbx.EINVAL
+
+
+def _net(seed, sizes=(130, 64, 48, 256)):
+    from paper_2507_15703_amd import surrogate
+    return surrogate.MLP(sizes=sizes, seed=seed)
+
+
+def test_forward_backward_match_oracle(cmbx):
+    net = _net(0)
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((37, 130)).astype(np.float32)
+    T = rng.standard_normal((37, 256)).astype(np.float32)
+    out, cache = net.forward(torch.tensor(X, device="cuda"))
+    loss, dY = net.loss_grad(out, torch.tensor(T, device="cuda"))
+    dWs, dbs = net.backward(cache, dY)
+    torch.cuda.synchronize()
+    Ws = [omlp.bf16(w.cpu().numpy()) for w in net.W]
+    bs = [b.cpu().numpy().astype(np.float64) for b in net.b]
+    ref, rc = omlp.forward(X, Ws, bs)
+    rloss, rdY = omlp.mse(ref, T)
+    rdW, rdb = omlp.backward(rc, Ws, rdY)
+    assert _rel(out.cpu().numpy(), ref) < 2e-3
+    assert float(loss.item()) == pytest.approx(rloss, rel=2e-3)
+    for li in range(3):
+        assert _rel(dWs[li].cpu().numpy(), rdW[li]) < 1e-2, li
+        assert _rel(dbs[li].cpu().numpy(), rdb[li]) < 1e-2, li
+
+
+def test_adam_matches_oracle(cmbx):
+    rng = np.random.default_rng(2)
+    n = 1000
+    w, m, v = rng.standard_normal(n).astype(np.float32), np.zeros(n, np.float32), np.zeros(n, np.float32)
+    wd, md, vd = (torch.tensor(a, device="cuda") for a in (w, m, v))
+    wb = torch.empty(n, dtype=torch.int16, device="cuda")
+    rw, rm, rv = w.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in range(1, 4):
+        g = rng.standard_normal(n).astype(np.float32)
+        gd = torch.tensor(g, device="cuda")
+        cmbx._check(cmbx.lib().cmbx_mlp_adam(wd.data_ptr(), md.data_ptr(), vd.data_ptr(), gd.data_ptr(), n, 1e-2, 0.9,
+                                             0.999, 1e-8, step, wb.data_ptr(), 0))
+        rw, rm, rv = omlp.adam(rw, rm, rv, g.astype(np.float64), step, 1e-2)
+    torch.cuda.synchronize()
+    assert np.allclose(wd.cpu().numpy(), rw, rtol=0, atol=1e-5)
+    assert np.array_equal(wb.cpu().numpy(), _bf16_words(wd.cpu().numpy()))
+
+
+def test_training_reduces_loss_on_inversion_pairs(cmbx):
+    from paper_2507_15703_amd import surrogate
+    X, Y = surrogate.generate_pairs(96, seed=123, workers=16)
+    net = surrogate.MLP(seed=1)
+    losses = net.train(X, Y, steps=300, batch=64, lr=1e-3, log_every=50)
+    assert losses[-1][1] < 0.2 * losses[0][1], losses
+
+
+def test_surrogate_falls_back_out_of_domain(cmbx):
+    from paper_2507_15703_amd import surrogate, workloads
+    net = surrogate.MLP(seed=2)
+    sur = surrogate.Surrogate(net, tol=0.01)
+    cl = workloads.shaped_cl(surrogate.lmax_of(192, 0.4), 1e-10, 0.0, 200.0, 0.0, 0.6 * surrogate.lmax_of(192, 0.4))
+    k, p, fb, res = sur.spectrum(cl, 192, 0.4)   # N outside the training domain
+    assert fb and res < 1e-3 and sur.stats["fallback"] == 1
+    cl = workloads.shaped_cl(surrogate.lmax_of(256, 0.4), 1e-10, 0.0, 200.0, 0.0, 0.6 * surrogate.lmax_of(256, 0.4))
+    k, p, fb, res = sur.spectrum(cl, 256, 0.4)   # untrained net: its answer fails the check
+    assert fb and res < 1e-3
