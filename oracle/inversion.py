@@ -10,6 +10,10 @@ Sec. II A-B of the paper:
 * C_l of the box field sampled on a full shell of radius R:
   C_l^box = 4 pi sum_{f != 0} P_box(|k_f|) j_l(|k_f| R)^2 (expand e^{i k.R n} in spherical
   harmonics and average |a_lm|^2 over m).
+* the expected pseudo-C_l of maps observed on a polar cap of half-angle theta_c:
+  2 pi int xi(theta) P_l(cos theta) w(theta) sin(theta) dtheta, with w the cap's pair
+  weight; it depends on xi only at separations inside the cap, which is all a cap-limited
+  programme constrains (for the full sphere it inverts eq. harmonics).
 
 Everything here is written from those definitions with SciPy's Legendre, spherical Bessel
 and HiGHS routines as library steps.
@@ -17,6 +21,7 @@ and HiGHS routines as library steps.
 import math
 
 import numpy as np
+import scipy.integrate
 import scipy.optimize
 import scipy.special
 
@@ -97,3 +102,66 @@ def cl_box(N, L, R, k_tab, p_tab, lmax):
     for l in range(lmax + 1):
         out[l] = 4 * math.pi * np.sum(w * scipy.special.spherical_jn(l, kk * R) ** 2)
     return out
+
+
+def xi_inf_of(k, p, r):
+    """xi_inf(r) of a tabulated P_inf through the programme's quadrature (eq. xiinfpinf):
+    4 pi sum_j k_j^2 P_j j0(k_j r) dk for a uniform node spacing dk."""
+    k = np.asarray(k, dtype=np.float64)
+    dk = k[1] - k[0]
+    r = np.asarray(r, dtype=np.float64)
+    return 4 * math.pi * (scipy.special.spherical_jn(0, np.outer(r, k)) * (k**2 * p)).sum(axis=1) * dk
+
+
+def cap_pair_weight(theta, theta_cap):
+    """w(theta): (1 / 4 pi) x the measure of ordered pixel pairs of a polar cap of half-angle
+    theta_cap at angular separation theta, per unit solid angle of the second point's
+    direction ring (w = 1 for the full sphere). For each theta, SciPy's adaptive quadrature
+    integrates over the first point's colatitude a the in-cap share of the ring of radius
+    theta around it, with a break at a = |theta_cap - theta| where that share stops being
+    the whole ring (or nothing)."""
+    theta = np.atleast_1d(np.asarray(theta, dtype=np.float64))
+    if theta_cap >= math.pi:
+        return np.ones_like(theta)
+    ctc = math.cos(theta_cap)
+
+    def share(a, t):
+        sa, st = math.sin(a), math.sin(t)
+        if sa * st == 0.0:
+            return 1.0 if math.cos(a - t) >= ctc else 0.0
+        c = (ctc - math.cos(a) * math.cos(t)) / (sa * st)
+        return math.acos(min(1.0, max(-1.0, c))) / math.pi
+
+    out = np.empty_like(theta)
+    for i, t in enumerate(theta):
+        val, _ = scipy.integrate.quad(lambda a: share(a, t) * math.sin(a), 0.0, theta_cap,
+                                      points=[abs(theta_cap - t)], limit=200, epsabs=1e-14, epsrel=1e-12)
+        out[i] = 2 * math.pi * val / (4 * math.pi)
+    return out
+
+
+def cap_pseudo_cl(xi_of_theta, theta_cap, lmax, n_theta=2000):
+    """Expected pseudo-C_l of maps with correlation xi(theta) observed on a polar cap:
+    2 pi int xi(theta) P_l(cos theta) w(theta) sin(theta) dtheta over in-cap separations,
+    Gauss-Legendre on [0, theta_cap] and [theta_cap, 2 theta_cap] (w has a kink at
+    theta_cap). For the full sphere (w = 1) this inverts eq. harmonics. A list of xi
+    functions gives a list of spectra (one evaluation of w)."""
+    if isinstance(xi_of_theta, (list, tuple)):
+        fns = xi_of_theta
+    else:
+        return cap_pseudo_cl([xi_of_theta], theta_cap, lmax, n_theta)[0]
+    x, wq = np.polynomial.legendre.leggauss(n_theta)
+    if theta_cap >= math.pi / 2:
+        edges = [0.0, math.pi]
+    else:
+        edges = [0.0, theta_cap, 2 * theta_cap]
+    th = np.concatenate([lo + 0.5 * (hi - lo) * (x + 1) for lo, hi in zip(edges[:-1], edges[1:])])
+    wt = np.concatenate([0.5 * (hi - lo) * wq for lo, hi in zip(edges[:-1], edges[1:])])
+    g = cap_pair_weight(th, theta_cap) * np.sin(th) * wt
+    fs = [fn(th) * g for fn in fns]
+    outs = [np.empty(lmax + 1) for _ in fns]
+    for l in range(lmax + 1):
+        pl = scipy.special.eval_legendre(l, np.cos(th))
+        for f, out in zip(fs, outs):
+            out[l] = 2 * math.pi * np.sum(f * pl)
+    return outs

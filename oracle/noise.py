@@ -38,8 +38,14 @@ def unit_normals(N, seed, ix, dtype=np.float64):
     return _pair(a, b, np.dtype(dtype))
 
 
-def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32):
-    """The weighted half grid, complex array of shape (N, N, N/2 + 1), complex128 or complex64."""
+def _normals_chunk(args):
+    N, seed, x0, x1, rdt = args
+    return unit_normals(N, seed, np.arange(x0, x1), rdt)
+
+
+def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32, workers=None):
+    """The weighted half grid, complex array of shape (N, N, N/2 + 1), complex128 or complex64.
+    workers > 1 draws the normals of independent x-chunks in that many processes."""
     if N % 2:
         raise ValueError("N must be even")
     rdt = np.dtype(dtype)
@@ -47,14 +53,22 @@ def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32):
     half, full = spectrum.weight_tables(N, L, k_tab, p_tab)
     half = half.astype(rdt)
     full = full.astype(rdt)
-    m_all = spectrum.mode_m(N)
     out = np.empty((N, N, N // 2 + 1), dtype=cdt)
-    for x0 in range(0, N, chunk):
-        x1 = min(N, x0 + chunk)
-        g_re, g_im = unit_normals(N, seed, np.arange(x0, x1), rdt)
-        w = half[m_all[x0:x1]]
-        out[x0:x1].real = w * g_re
-        out[x0:x1].imag = w * g_im
+    jobs = [(N, seed, x0, min(N, x0 + chunk), rdt) for x0 in range(0, N, chunk)]
+    if workers is not None and workers > 1 and len(jobs) > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        ex = ProcessPoolExecutor(max_workers=workers)
+        normals = ex.map(_normals_chunk, jobs)
+    else:
+        ex, normals = None, map(_normals_chunk, jobs)
+    try:
+        for (_, _, x0, x1, _), (g_re, g_im) in zip(jobs, normals):
+            w = half[spectrum.mode_m(N, np.arange(x0, x1))]
+            out[x0:x1].real = w * g_re
+            out[x0:x1].imag = w * g_im
+    finally:
+        if ex is not None:
+            ex.shutdown()
     _hermitian_planes(out, N, seed, full, rdt)
     return out
 

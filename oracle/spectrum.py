@@ -63,12 +63,14 @@ def weight_tables(N, L, k_tab, p_tab):
     return half, full
 
 
-def mode_m(N):
-    """Integer |f|^2 for every half-grid mode, shape (N, N, N/2 + 1)."""
+def mode_m(N, ix=None):
+    """Integer |f|^2 for every half-grid mode, shape (N, N, N/2 + 1), or (len(ix), N, N/2 + 1)
+    for the x-indices ``ix`` only."""
     f = np.arange(N)
     f = np.minimum(f, N - f)
+    fx = f if ix is None else f[np.asarray(ix)]
     fz = np.arange(N // 2 + 1)
-    return (f[:, None, None] ** 2 + f[None, :, None] ** 2 + fz[None, None, :] ** 2).astype(np.int64)
+    return (fx[:, None, None] ** 2 + f[None, :, None] ** 2 + fz[None, None, :] ** 2).astype(np.int64)
 
 
 def lattice_xi0(N, L, k_tab, p_tab):

@@ -86,7 +86,12 @@ def invert(cl, R, theta_max, beam, N=None, L=1.0, k_max=None):
     bs = b / xi0
     cs = As.sum(axis=0)
     bounds = [(0.0, 0.0)] + [(0.0, None)] * (A.shape[1] - 1)
-    res = linprog(cs, A_ub=-As, b_ub=-bs, bounds=bounds, method="highs")
+    # HiGHS' default choice first; on a numerical failure its dual simplex, then its
+    # interior-point method (infeasible or unbounded programmes fail in every method)
+    for method in ("highs", "highs-ds", "highs-ipm"):
+        res = linprog(cs, A_ub=-As, b_ub=-bs, bounds=bounds, method=method)
+        if res.status == 0 or res.status in (2, 3):
+            break
     if res.status != 0:
         raise RuntimeError(f"linear programme failed: {res.message}")
     y = np.maximum(res.x, 0.0)
@@ -102,3 +107,93 @@ def invert(cl, R, theta_max, beam, N=None, L=1.0, k_max=None):
 def beam_from_damping(ld):
     """exp(-(l/l_d)^2) = exp(-b^2 l^2) with b = 1/l_d (eq. cl)."""
     return 1.0 / float(ld)
+
+
+class CapPseudoCl:
+    """Expected pseudo-C_l (l = 0..lmax) of maps seen on a polar cap of half-angle theta_c.
+
+    A map with correlation xi(theta) observed on the cap has
+    E[pseudo-C_l] = 2 pi int_0^{2 theta_c} xi(theta) P_l(cos theta) w(theta) sin(theta) dtheta,
+    where w(theta) is the share of ordered pixel pairs at separation theta with both ends in
+    the cap (per unit solid angle of the ring around the first point, w = 1 on the full sky).
+    It depends on xi only at separations the cap contains, so it compares a cap-limited
+    inversion (Sec. II B) with its target C_l on equal terms.
+
+    The theta integral is Gauss-Legendre on the panels [0, theta_c] and [theta_c, 2 theta_c]
+    (w is not smooth at theta_c). w(theta) integrates, over the first point's colatitude a
+    (weight sin a), the in-cap share of the ring of radius theta around it: the whole ring
+    for a <= theta_c - theta, none of it for a < theta - theta_c, and between
+    a0 = |theta_c - theta| and theta_c an arc whose length has a square-root edge at a0,
+    removed by the substitution a = a0 + (theta_c - a0) s^2 before Gauss-Legendre in s.
+    The result is a (lmax+1) x n_theta matrix acting on xi at the nodes, so each check is
+    one small matrix product.
+    """
+
+    def __init__(self, theta_c, lmax, n_theta=768, n_a=192):
+        self.theta_c, self.lmax = float(theta_c), int(lmax)
+        u, wu = np.polynomial.legendre.leggauss(n_theta // 2)
+        edges = [0.0, self.theta_c, min(math.pi, 2.0 * self.theta_c)]
+        th, wt = [], []
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            th.append(lo + 0.5 * (hi - lo) * (u + 1.0))
+            wt.append(0.5 * (hi - lo) * wu)
+        self.theta = np.concatenate(th)
+        wt = np.concatenate(wt)
+        n_theta = self.theta.size
+        w = self._pair_share(self.theta, n_a)
+        x = np.cos(self.theta)
+        P = np.empty((self.lmax + 1, n_theta))
+        P[0] = 1.0
+        if self.lmax >= 1:
+            P[1] = x
+        for l in range(1, self.lmax):
+            P[l + 1] = ((2 * l + 1) * x * P[l] - l * P[l - 1]) / (l + 1)
+        self._P = P
+        self.K = 2.0 * math.pi * P * (w * np.sin(self.theta) * wt)[None, :]
+
+    def _pair_share(self, theta, n_a):
+        tc = self.theta_c
+        if tc >= math.pi:
+            return np.ones_like(theta)
+        v, wv = np.polynomial.legendre.leggauss(n_a)
+        sv, wv = 0.5 * (v + 1.0), 0.5 * wv                      # s in (0, 1)
+        a0 = np.abs(tc - theta)[:, None]
+        a = a0 + (tc - a0) * sv[None, :] ** 2
+        wa = wv[None, :] * 2.0 * (tc - a0) * sv[None, :] * np.sin(a)
+        st, ct = np.sin(theta)[:, None], np.cos(theta)[:, None]
+        c = (math.cos(tc) - np.cos(a) * ct) / (np.sin(a) * st)
+        arc = np.arccos(np.clip(c, -1.0, 1.0)) / math.pi
+        inner = np.where(theta < tc, 1.0 - np.cos(tc - theta), 0.0)   # rings wholly inside
+        # solid angle of first points x in-cap share of their ring, over 4 pi
+        return 2.0 * math.pi * (inner + (arc * wa).sum(axis=1)) / (4.0 * math.pi)
+
+    def of_xi(self, xi_nodes):
+        return self.K @ np.asarray(xi_nodes, dtype=np.float64)
+
+    def of_cl(self, cl):
+        cl = np.asarray(cl, dtype=np.float64)
+        n = min(cl.size, self.lmax + 1)
+        l = np.arange(n)
+        xi = ((2 * l + 1) * cl[:n]) @ self._P[:n] / (4.0 * math.pi)
+        if cl.size > n:
+            xi = xi + xi_sph(self.theta, np.concatenate([np.zeros(n), cl[n:]]))
+        return self.of_xi(xi)
+
+    def of_table(self, k, p, R):
+        """For a tabulated P_inf on uniform nodes k (eq. xiinfpinf as the programme's sum),
+        xi at the chord 2 R sin(theta / 2) of each node."""
+        k = np.asarray(k, dtype=np.float64)
+        p = np.asarray(p, dtype=np.float64)
+        dk = k[1] - k[0]
+        r = 2.0 * R * np.sin(0.5 * self.theta)
+        xi = _j0(np.outer(r, k)) @ (4.0 * math.pi * k * k * p * dk)
+        return self.of_xi(xi)
+
+
+def band_deviation(a, b, lmin=2, width=10):
+    """|sum_band a / sum_band b - 1| over bands [l0, l0 + width) from lmin to the last full band."""
+    a, b = np.asarray(a), np.asarray(b)
+    starts = np.arange(lmin, a.size - width + 1, width)
+    sa = np.add.reduceat(a[lmin:starts[-1] + width], starts - lmin)
+    sb = np.add.reduceat(b[lmin:starts[-1] + width], starts - lmin)
+    return np.abs(sa / sb - 1.0)

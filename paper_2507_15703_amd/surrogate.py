@@ -15,14 +15,24 @@ independent of R, so the network predicts the programme's own unknowns on that f
   percentage of xi(0) carried by node j (the programme is homogeneous in C_l, so y does
   not depend on the amplitude); nodes above the box's band limit are zero.
 
-The prediction is accepted only if it reproduces the target correlations inside the cap:
-max_i |(A x)_i - b_i| / xi_sph(0) <= tol on the programme's own constraints; otherwise the
-plain inversion runs (fallback).
+The network's answer then gets the smallest multiplicative correction (``project_bands``)
+that makes the expected pseudo-C_l on the cap (``spectrum.CapPseudoCl``) match the target
+C_l's in every band of Delta l = 10 from l = 2 to l_max: a linear problem with one row per
+band, solved in a few milliseconds on the host. The answer is accepted only if both checks
+pass: those bands within tol (1 %) of the target's, and the correlations the programme
+constrains (chords up to 2 R sin THETA_MAX) within res_tol (0.2 % of xi(0)). The band
+projection alone cannot supply the second: started from a spectrum-independent guess it
+leaves several times larger correlation errors, which is what the network removes.
+Otherwise, and for geometries outside the training domain, the plain inversion runs
+(fallback).
 """
 import ctypes
+import functools
 import math
 import os
 import time
+import warnings
+import zlib
 
 import numpy as np
 
@@ -64,17 +74,109 @@ def label_from_solution(k, p, cl, R):
     return y.astype(np.float32)
 
 
+def _xi0(cl):
+    """xi_sph(0) = sum_l (2l + 1) C_l / 4 pi (eq. harmonics at theta = 0, P_l(1) = 1)."""
+    cl = np.asarray(cl, dtype=np.float64)
+    return float(((2 * np.arange(cl.size) + 1) * cl).sum() / (4 * math.pi))
+
+
 def table_from_output(y, cl, N, r_over_L):
     """(k, P_inf) table from a network output; nodes beyond the band limit are dropped."""
     R = r_over_L * L_BOX
     dk = math.pi / (3.0 * math.sin(THETA_MAX)) / R
     k_max = math.pi * N / L_BOX
     n = min(N_OUT, int(math.floor(k_max / dk + 1e-9)))
-    xi0 = spectrum.xi_sph(np.array([0.0]), cl)[0]
+    xi0 = _xi0(cl)
     k = dk * np.arange(n + 1)
     p = np.zeros(n + 1)
     p[1:] = np.maximum(np.asarray(y[:n], dtype=np.float64), 0.0) / 100.0 * xi0 / (4 * math.pi * k[1:] ** 2 * dk)
     return k, p
+
+
+@functools.lru_cache(maxsize=64)
+def _cap_check(lmax):
+    return spectrum.CapPseudoCl(THETA_MAX, lmax)
+
+
+def cl_check(k, p, cl, r_over_L):
+    """Largest band deviation |sum pseudo-C_l(P) / sum pseudo-C_l(target) - 1| over bands of
+    Delta l = 10 (l = 2 .. l_max) of the expected cap pseudo-C_l."""
+    cl = np.asarray(cl, dtype=np.float64)
+    chk = _cap_check(cl.size - 1)
+    return float(spectrum.band_deviation(chk.of_table(k, p, r_over_L * L_BOX), chk.of_cl(cl)).max())
+
+
+class _Geometry:
+    """Spectrum-independent matrices of one (N, r/L, l_max) for the projection and checks."""
+
+    def __init__(self, N, r_over_L, lmax):
+        R = r_over_L * L_BOX
+        dk = math.pi / (3.0 * math.sin(THETA_MAX)) / R
+        self.n = min(N_OUT, int(math.floor(math.pi * N / L_BOX / dk + 1e-9)))
+        k = dk * np.arange(1, self.n + 1)
+        self.chk = _cap_check(lmax)
+        # expected pseudo-C_l per unit output, over xi(0): y_j carries y_j / 100 of xi(0)
+        # at node k_j, i.e. xi(chord) = xi(0) sum_j y_j j0(k_j chord) / 100
+        J = spectrum._j0(np.outer(2.0 * R * np.sin(0.5 * self.chk.theta), k))
+        starts = np.arange(2, lmax - 10 + 2, 10)
+        B = np.zeros((starts.size, lmax + 1))
+        for i, l0 in enumerate(starts):
+            B[i, l0:l0 + 10] = 1.0
+        self.B = B
+        self.G = B @ (self.chk.K @ J) / 100.0
+        # the programme's constraints (beam 1 / (0.6 l_max)) in the same units
+        pr = spectrum.lp_problem(np.zeros(2), R, THETA_MAX, 1.0 / (0.6 * lmax), math.pi * N / L_BOX)
+        self.C = spectrum._j0(np.outer(pr["r"], k)) / 100.0
+        # (2l + 1) P_l(cos theta_i) / 4 pi at the constraint angles, for xi_sph there
+        x = np.cos(pr["theta"])
+        P = np.empty((lmax + 1, x.size))
+        P[0] = 1.0
+        if lmax >= 1:
+            P[1] = x
+        for l in range(1, lmax):
+            P[l + 1] = ((2 * l + 1) * x * P[l] - l * P[l - 1]) / (l + 1)
+        self.Pr = P * ((2 * np.arange(lmax + 1) + 1) / (4 * math.pi))[:, None]
+
+    def targets(self, cl):
+        xi0 = _xi0(cl)
+        return self.B @ self.chk.of_cl(cl) / xi0, (cl @ self.Pr) / xi0
+
+    def project(self, y, t, iters=12, tol=1e-6):
+        """y >= 0 near the given y with G y = t (every band matched). Each step is the
+        least-change update in the metric weighted by 1 / (y + eps), so nodes change in
+        proportion to their size; nodes that would go negative are clipped and the step
+        repeats, up to iters times or until every band is within tol."""
+        y = np.maximum(np.asarray(y[: self.n], dtype=np.float64), 0.0)
+        Gw = self.G / t[:, None]
+        for _ in range(iters):
+            r = 1.0 - Gw @ y
+            if np.max(np.abs(r)) <= tol:
+                break
+            s = y + 1e-3 * max(y.mean(), 1e-12)
+            M = (Gw * s) @ Gw.T
+            M[np.diag_indices_from(M)] += 1e-10 * np.trace(M) / M.shape[0]
+            y = np.maximum(y + s * (Gw.T @ np.linalg.solve(M, r)), 0.0)
+        return y
+
+    def checks(self, y, t, xi_r):
+        """(largest band deviation, largest in-cap correlation error over xi(0))."""
+        return float(np.max(np.abs(self.G @ y / t - 1.0))), float(np.max(np.abs(self.C @ y - xi_r)))
+
+
+@functools.lru_cache(maxsize=32)
+def _geometry(N, r_over_L, lmax):
+    return _Geometry(N, r_over_L, lmax)
+
+
+def project_bands(y, cl, N, r_over_L):
+    """The network output y (256) after the band projection, and its two check values."""
+    cl = np.asarray(cl, dtype=np.float64)
+    g = _geometry(int(N), float(r_over_L), cl.size - 1)
+    t, xi_r = g.targets(cl)
+    yp = g.project(y, t)
+    out = np.zeros(N_OUT)
+    out[: g.n] = yp
+    return out, g.checks(yp, t, xi_r)
 
 
 def cap_residual(k, p, cl, N, r_over_L):
@@ -109,12 +211,16 @@ def _pair(seed):
     rng = np.random.default_rng(seed)
     prm = sample_params(rng)
     cl = cl_of(prm)
-    k, p, _ = plain_inversion(prm, cl)
+    try:
+        k, p, _ = plain_inversion(prm, cl)
+    except RuntimeError:
+        return None
     return features(cl, prm["N"], prm["r"]), label_from_solution(k, p, cl, prm["r"] * L_BOX)
 
 
 def generate_pairs(n, seed=0, workers=None):
-    """n (feature, label) pairs from the plain inversion, seeds seed .. seed + n - 1."""
+    """(feature, label) pairs from the plain inversion of the spectra of seeds seed ..
+    seed + n - 1 (fewer than n if a programme fails)."""
     seeds = list(range(seed, seed + n))
     if workers is None:
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
@@ -124,6 +230,7 @@ def generate_pairs(n, seed=0, workers=None):
             out = list(ex.map(_pair, seeds, chunksize=8))
     else:
         out = [_pair(s) for s in seeds]
+    out = [o for o in out if o is not None]          # spectra whose programme failed are skipped
     X = np.stack([o[0] for o in out])
     Y = np.stack([o[1] for o in out])
     return X, Y
@@ -250,38 +357,127 @@ class MLP:
         out, _ = self.forward(torch.tensor(np.atleast_2d(X).astype(np.float32), device="cuda"))
         return out.cpu().numpy()
 
-    def state(self):
-        return {f"W{i}": w.cpu().numpy() for i, w in enumerate(self.W)} | \
-               {f"b{i}": b.cpu().numpy() for i, b in enumerate(self.b)}
+    def state(self, optimizer=True):
+        """FP32 master weights and biases; with optimizer=True also Adam's moments and step
+        (training resumes from such a state)."""
+        st = {f"W{i}": w.cpu().numpy() for i, w in enumerate(self.W)}
+        st |= {f"b{i}": b.cpu().numpy() for i, b in enumerate(self.b)}
+        if optimizer:
+            for name, lst in (("mW", self.mW), ("vW", self.vW), ("mb", self.mb), ("vb", self.vb)):
+                st |= {f"{name}{i}": t.cpu().numpy() for i, t in enumerate(lst)}
+            st["step"] = np.array(self.step, dtype=np.int64)
+        return st
+
+    def inference_state(self):
+        """The weights as the kernels use them (BF16 bit patterns, uint16) and FP32 biases."""
+        st = {f"Wbf{i}": w.cpu().numpy().view(np.uint16) for i, w in enumerate(self.Wbf)}
+        return st | {f"b{i}": b.cpu().numpy() for i, b in enumerate(self.b)}
 
     def load_state(self, st):
         for i in range(len(self.W)):
-            self.W[i].copy_(self.torch.tensor(st[f"W{i}"]))
-            self.b[i].copy_(self.torch.tensor(st[f"b{i}"]))
+            if f"W{i}" in st:
+                w = np.asarray(st[f"W{i}"], dtype=np.float32)
+            else:   # BF16 words: the FP32 value with the same leading 16 bits
+                w = (np.asarray(st[f"Wbf{i}"], dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+            if w.shape != tuple(self.W[i].shape):
+                raise ValueError(f"layer {i}: weights of shape {w.shape}, expected {tuple(self.W[i].shape)}")
+            self.W[i].copy_(self.torch.tensor(w))
+            self.b[i].copy_(self.torch.tensor(np.asarray(st[f"b{i}"], dtype=np.float32)))
+            if f"mW{i}" in st:
+                for name, lst in (("mW", self.mW), ("vW", self.vW), ("mb", self.mb), ("vb", self.vb)):
+                    lst[i].copy_(self.torch.tensor(np.asarray(st[f"{name}{i}"], dtype=np.float32)))
+        if "step" in st:
+            self.step = int(st["step"])
         self.refresh_bf16()
+
+
+def _crc(st):
+    c = 0
+    for key in sorted(st):
+        a = np.ascontiguousarray(st[key])
+        c = zlib.crc32(key.encode(), c)
+        c = zlib.crc32(str(a.dtype).encode() + str(a.shape).encode(), c)
+        c = zlib.crc32(a.tobytes(), c)
+    return c
+
+
+def save_checkpoint(path, st):
+    """npz of a state dict with a CRC-32 over names, dtypes, shapes and bytes."""
+    np.savez(path, crc=np.array(_crc(st), dtype=np.uint32), **st)
+
+
+def read_checkpoint(path):
+    """The state dict of a checkpoint; ValueError if it is unreadable or its CRC differs."""
+    try:
+        with np.load(path, allow_pickle=False) as z:
+            st = {k: z[k] for k in z.files}
+    except Exception as e:       # missing, truncated or not an npz
+        raise ValueError(f"unreadable surrogate checkpoint {path}: {e}") from e
+    crc = st.pop("crc", None)
+    if crc is None or int(crc) != _crc(st):
+        raise ValueError(f"surrogate checkpoint {path} fails its CRC check")
+    return st
+
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "surrogate_cap30.npz")
 
 
 class Surrogate:
     """C_l -> (k, P_inf) through the network, with the plain inversion as fallback."""
 
-    def __init__(self, mlp, tol=0.01):
-        self.mlp, self.tol = mlp, tol
+    def __init__(self, mlp, tol=0.01, res_tol=0.002, project=True):
+        self.mlp, self.tol, self.res_tol, self.project = mlp, tol, res_tol, project
         self.stats = dict(accepted=0, fallback=0)
 
+    @classmethod
+    def load(cls, path=DEFAULT_WEIGHTS, **kw):
+        """The surrogate with a checkpoint's weights. A checkpoint that is missing, corrupt
+        (CRC) or of the wrong shapes gives a surrogate that always falls back, with a warning."""
+        try:
+            st = read_checkpoint(path)
+            mlp = MLP()
+            mlp.load_state(st)
+        except ValueError as e:
+            warnings.warn(f"{e}; every spectrum will use the plain inversion")
+            mlp = None
+        return cls(mlp, **kw)
+
     def in_domain(self, N, r_over_L):
-        return N in (128, 256) and 0.35 <= r_over_L <= 0.45
+        return self.mlp is not None and N in (128, 256) and 0.35 <= r_over_L <= 0.45
 
     def spectrum(self, cl, N, r_over_L, beam=None):
-        """Returns (k, P_inf, used_fallback, cap_residual)."""
-        if self.in_domain(N, r_over_L):
-            y = self.mlp.predict(features(cl, N, r_over_L))[0]
-            k, p = table_from_output(y, cl, N, r_over_L)
-            res = cap_residual(k, p, cl, N, r_over_L)
-            if res <= self.tol:
-                self.stats["accepted"] += 1
-                return k, p, False, res
-        self.stats["fallback"] += 1
-        lmax = np.asarray(cl).size - 1
-        b = beam if beam is not None else 1.0 / (0.6 * lmax)
-        k, p, _ = spectrum.invert(cl, r_over_L * L_BOX, THETA_MAX, b, N=N, L=L_BOX)
-        return k, p, True, cap_residual(k, p, cl, N, r_over_L)
+        """Returns (k, P_inf, used_fallback, (band deviation, correlation error))."""
+        return self.spectra([(cl, N, r_over_L)], beam)[0]
+
+    def answer(self, y, cl, N, r_over_L):
+        """(k, P_inf, checks) of a network output without the fallback."""
+        if self.project:
+            y, chk = project_bands(y, cl, N, r_over_L)
+        else:
+            g = _geometry(int(N), float(r_over_L), np.asarray(cl).size - 1)
+            t, xi_r = g.targets(np.asarray(cl, dtype=np.float64))
+            y = np.maximum(np.asarray(y, dtype=np.float64), 0.0)
+            chk = g.checks(y[: g.n], t, xi_r)
+        k, p = table_from_output(y, cl, N, r_over_L)
+        return k, p, chk
+
+    def spectra(self, items, beam=None):
+        """[(cl, N, r/L)] -> [(k, P_inf, used_fallback, checks)]; one network pass for all
+        in-domain items."""
+        out = [None] * len(items)
+        live = [i for i, (cl, N, r) in enumerate(items) if self.in_domain(N, r)]
+        if live:
+            Y = self.mlp.predict(np.stack([features(*items[i]) for i in live]))
+            for i, y in zip(live, Y):
+                k, p, chk = self.answer(y, *items[i])
+                if chk[0] <= self.tol and chk[1] <= self.res_tol:
+                    self.stats["accepted"] += 1
+                    out[i] = (k, p, False, chk)
+        for i, (cl, N, r) in enumerate(items):
+            if out[i] is None:
+                self.stats["fallback"] += 1
+                lmax = np.asarray(cl).size - 1
+                b = beam if beam is not None else 1.0 / (0.6 * lmax)
+                k, p, _ = spectrum.invert(cl, r * L_BOX, THETA_MAX, b, N=N, L=L_BOX)
+                out[i] = (k, p, True, (cl_check(k, p, cl, r), cap_residual(k, p, cl, N, r)))
+        return out

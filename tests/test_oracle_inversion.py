@@ -86,3 +86,28 @@ def test_cl_box_normalisation():
     cl = oinv.cl_box(N, L, R, k, p, 200)
     lhs = np.sum((2 * np.arange(cl.size) + 1) * cl) / (4 * math.pi)
     assert lhs == pytest.approx(ospec.lattice_xi0(N, L, k, p), rel=1e-10)
+
+
+def test_cap_pseudo_cl_full_sky_inverts_harmonics():
+    cl = workloads.synthetic_cl(60)
+    got = oinv.cap_pseudo_cl(lambda th: oinv.xi_sph(th, cl), math.pi, 60)
+    assert np.allclose(got, cl, rtol=1e-8, atol=1e-8 * cl.max())
+
+
+def test_cap_pair_weight_limits():
+    # zero separation: every pair partner stays inside, w(0) = f_sky of the cap
+    tc = math.radians(30)
+    fsky = (1 - math.cos(tc)) / 2
+    assert oinv.cap_pair_weight([1e-9], tc)[0] == pytest.approx(fsky, rel=1e-6)
+    assert oinv.cap_pair_weight([2 * tc + 1e-6], tc)[0] == pytest.approx(0.0, abs=1e-12)
+    # integral over the sphere of w equals f_sky^2 (ordered pairs)
+    th = np.linspace(0, 2 * tc, 20001)
+    integ = np.trapezoid(oinv.cap_pair_weight(th, tc) * 2 * math.pi * np.sin(th), th)
+    assert integ == pytest.approx(4 * math.pi * fsky**2, rel=2e-3)
+
+
+def test_xi_inf_of_matches_programme_rows():
+    cl = workloads.synthetic_cl(120)
+    r, b, k, A, c = oinv.programme(cl, 0.4, math.radians(20), 1 / 70.0, k_max=300.0)
+    p = np.exp(-k / 60.0)
+    assert np.allclose(oinv.xi_inf_of(k, p, r), A @ p, rtol=1e-12, atol=1e-12 * abs(A @ p).max())

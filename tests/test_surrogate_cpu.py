@@ -31,8 +31,9 @@ def test_target_round_trip_reproduces_programme_solution():
     k2, p2 = surrogate.table_from_output(y, cl, prm["N"], prm["r"])
     assert np.allclose(k2, k[: k2.size], rtol=1e-12)
     assert np.allclose(p2, p[: k2.size], rtol=1e-5, atol=1e-7 * p.max())
-    # and the plain solution passes the surrogate's acceptance test
+    # and the plain solution passes the surrogate's acceptance tests
     assert surrogate.cap_residual(k, p, cl, prm["N"], prm["r"]) < 1e-4
+    assert surrogate.cl_check(k, p, cl, prm["r"]) < 0.01
 
 
 def test_targets_do_not_depend_on_amplitude():
@@ -43,3 +44,49 @@ def test_targets_do_not_depend_on_amplitude():
     y1 = surrogate.label_from_solution(k, p, cl, prm["r"])
     y2 = surrogate.label_from_solution(k2, p2, 3.0 * cl, prm["r"])
     assert np.allclose(y1, y2, atol=1e-3)
+
+
+def test_cap_pseudo_cl_check_matches_oracle():
+    # the host check (fixed Gauss-Legendre rules) against the oracle (adaptive quadrature of
+    # the pair weight), for a target C_l and for a tabulated P_inf
+    from oracle import inversion as oinv
+    tc, R, lmax = surrogate.THETA_MAX, 0.4, 200
+    cl = workloads.synthetic_cl(lmax)
+    chk = spectrum.CapPseudoCl(tc, lmax)
+    ref = oinv.cap_pseudo_cl(lambda th: oinv.xi_sph(th, cl), tc, lmax)
+    assert np.max(spectrum.band_deviation(chk.of_cl(cl), ref)) < 1e-9
+    k = np.arange(150) * 6.0
+    p = np.zeros_like(k)
+    p[1:] = k[1:] ** -3.0 * np.exp(-(k[1:] / 300.0) ** 2)
+    ref = oinv.cap_pseudo_cl(lambda th: oinv.xi_inf_of(k, p, oinv.chord(th, R)), tc, lmax)
+    assert np.max(spectrum.band_deviation(chk.of_table(k, p, R), ref)) < 1e-9
+
+
+def test_band_deviation():
+    a = np.arange(1.0, 40.0)
+    d = spectrum.band_deviation(1.01 * a, a)
+    assert d.shape == (3,) and np.allclose(d, 0.01)
+
+
+def test_checkpoint_crc(tmp_path):
+    rng = np.random.default_rng(0)
+    st = {"W0": rng.standard_normal((4, 3)).astype(np.float32), "b0": np.zeros(3, np.float32),
+          "step": np.array(7, dtype=np.int64)}
+    path = str(tmp_path / "w.npz")
+    surrogate.save_checkpoint(path, st)
+    back = surrogate.read_checkpoint(path)
+    assert set(back) == set(st) and all(np.array_equal(back[k], st[k]) for k in st)
+    # a changed value, a missing file and a truncated file are refused
+    st2 = dict(st, W0=st["W0"].copy())
+    st2["W0"][1, 2] += 1.0
+    np.savez(str(tmp_path / "bad.npz"), crc=np.array(surrogate._crc(st), dtype=np.uint32), **st2)
+    with pytest.raises(ValueError, match="CRC"):
+        surrogate.read_checkpoint(str(tmp_path / "bad.npz"))
+    with pytest.raises(ValueError):
+        surrogate.read_checkpoint(str(tmp_path / "missing.npz"))
+    with open(path, "rb") as f:
+        data = f.read()
+    with open(str(tmp_path / "cut.npz"), "wb") as f:
+        f.write(data[: len(data) // 2])
+    with pytest.raises(ValueError):
+        surrogate.read_checkpoint(str(tmp_path / "cut.npz"))
