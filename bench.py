@@ -6,8 +6,9 @@ each with its own seed, shell radius r = 0.45 L, a polar cap of half-angle drawn
 uniformly in [10, 40] deg (n_ring = round(25.6 theta) rings x 1024 or 2048 pixels) and
 tricubic sampling. One step = one pass of the whole hot path (noise + inverse 3-D FFT +
 sphere gather) over the four boxes, i.e. four maps. The batched path replays the four
-independent kernel chains as one HIP graph; the plain path runs the same jobs one after
-another through cmbx_simulate_patch on one stream. Inputs (directions, spectrum tables)
+independent kernel chains as a HIP-graph ensemble (one graph, or two graphs on two
+streams when that is faster); the plain path runs the same jobs one after another
+through cmbx_simulate_patch on one stream. Inputs (directions, spectrum tables)
 are resident in device memory before timing starts.
 
 Prints one JSON line (see the keys below). ``--gpus`` above 1 is refused: this build
@@ -189,10 +190,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{nmaps}x512^3 FP32 batched (one hipGraph), r=0.45L, caps U[10,40] deg, tricubic",
+        "config": {"workload": f"{nmaps}x512^3 FP32 batched (hipGraph ensemble), r=0.45L, caps U[10,40] deg, tricubic",
                    "boxes": nmaps, "N": N, "pixels": [j["n_pix"] for j in jobs], "maps_per_step": nmaps},
         "plain_maps_per_s": round(plain, 2),
         "ensemble_mode": ens.modes,
+        "ensemble_lanes": ens.lanes,
         "batched_over_plain": round(value / plain, 3),
         "wall_s": {"batched": round(wall_b, 4), "plain": round(wall_p, 4)},
         "path_GBps_alg": round(path_gbs, 1),

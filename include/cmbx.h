@@ -123,6 +123,9 @@ typedef struct cmbx_job {
 #define CMBX_ENS_AUTO      0 /* time both modes per (precision, N) group at creation, keep the faster */
 #define CMBX_ENS_CHAINED   1 /* each realisation's four kernels in turn, in its plan's workspace */
 #define CMBX_ENS_PIPELINED 2 /* software pipeline of fused launches (see below) */
+/* lane flags, OR-ed into the mode */
+#define CMBX_ENS_ONE_LANE  0x100 /* one graph on the launch stream */
+#define CMBX_ENS_TWO_LANES 0x200 /* chained items split by plan over two graphs on two streams */
 
 /*
  * Capture the jobs into one HIP graph. Every realisation of every job (job j's plan has
@@ -136,16 +139,29 @@ typedef struct cmbx_job {
  *   the ensemble.
  * - CMBX_ENS_AUTO: both are captured for each group and timed (the outputs are written
  *   meanwhile); the faster is kept (cmbx_ensemble_modes reports the choice).
+ * Lanes: with CMBX_ENS_TWO_LANES the chained items are split by plan (all items of one plan
+ * in one lane, since they share its workspace; heaviest plans first into the lighter lane)
+ * into two graphs. Lane 0 (with every pipelined group) runs on the launch stream, lane 1
+ * on a stream the ensemble owns, forked from and joined back into the launch stream, so
+ * the chains of different plans can overlap on the device. With fewer than two chained
+ * plans there is one lane. Without a lane flag, CMBX_ENS_AUTO times one and two lanes and
+ * keeps the faster, and the explicit modes use one lane. Launches of one ensemble must be
+ * ordered (one launch stream, or synchronised).
  * Buffers passed in stay caller-owned and must outlive the ensemble, and so must the
  * plans, whose weight and twiddle tables and workspaces are used when the graph runs
  * (interpolant, r and pixel counts are fixed at creation). Errors: as cmbx_simulate_patch
- * for each job, CMBX_EINVAL for n_jobs < 1 or an unknown mode, CMBX_ENOMEM.
+ * for each job, CMBX_EINVAL for n_jobs < 1, an unknown mode or both lane flags,
+ * CMBX_ENOMEM.
  */
 int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemble** out);
+/* Number of lanes (1 or 2) the ensemble runs in, or CMBX_EINVAL for a NULL ensemble. */
+int cmbx_ensemble_lanes(const cmbx_ensemble* ens);
 /* Mode chosen for each group (in order of first appearance) written to modes[0 .. cap);
  * returns the number of groups, or CMBX_EINVAL for a NULL ensemble. */
 int cmbx_ensemble_modes(const cmbx_ensemble* ens, int* modes, int cap);
-/* Launch the captured graph on `stream` (a hipStream_t; NULL = the default stream). */
+/* Launch the captured graphs on `stream` (a hipStream_t; NULL = the default stream): the
+ * work is ordered after what `stream` already holds, and what is later enqueued on
+ * `stream` runs after all of it. */
 int cmbx_ensemble_launch(cmbx_ensemble* ens, void* stream);
 /* Release an ensemble (waits for the device first). NULL is accepted. */
 int cmbx_ensemble_destroy(cmbx_ensemble* ens);

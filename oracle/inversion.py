@@ -18,6 +18,7 @@ Sec. II A-B of the paper:
 Everything here is written from those definitions with SciPy's Legendre, spherical Bessel
 and HiGHS routines as library steps.
 """
+import functools
 import math
 
 import numpy as np
@@ -140,6 +141,20 @@ def cap_pair_weight(theta, theta_cap):
     return out
 
 
+@functools.lru_cache(maxsize=8)
+def _cap_nodes(theta_cap, n_theta):
+    """Separation nodes and weights w(theta) sin(theta) dtheta of the cap integral below
+    (remembered per cap: the pair weight is the slow part)."""
+    x, wq = np.polynomial.legendre.leggauss(n_theta)
+    if theta_cap >= math.pi / 2:
+        edges = [0.0, math.pi]
+    else:
+        edges = [0.0, theta_cap, 2 * theta_cap]
+    th = np.concatenate([lo + 0.5 * (hi - lo) * (x + 1) for lo, hi in zip(edges[:-1], edges[1:])])
+    wt = np.concatenate([0.5 * (hi - lo) * wq for lo, hi in zip(edges[:-1], edges[1:])])
+    return th, cap_pair_weight(th, theta_cap) * np.sin(th) * wt
+
+
 def cap_pseudo_cl(xi_of_theta, theta_cap, lmax, n_theta=2000):
     """Expected pseudo-C_l of maps with correlation xi(theta) observed on a polar cap:
     2 pi int xi(theta) P_l(cos theta) w(theta) sin(theta) dtheta over in-cap separations,
@@ -150,14 +165,7 @@ def cap_pseudo_cl(xi_of_theta, theta_cap, lmax, n_theta=2000):
         fns = xi_of_theta
     else:
         return cap_pseudo_cl([xi_of_theta], theta_cap, lmax, n_theta)[0]
-    x, wq = np.polynomial.legendre.leggauss(n_theta)
-    if theta_cap >= math.pi / 2:
-        edges = [0.0, math.pi]
-    else:
-        edges = [0.0, theta_cap, 2 * theta_cap]
-    th = np.concatenate([lo + 0.5 * (hi - lo) * (x + 1) for lo, hi in zip(edges[:-1], edges[1:])])
-    wt = np.concatenate([0.5 * (hi - lo) * wq for lo, hi in zip(edges[:-1], edges[1:])])
-    g = cap_pair_weight(th, theta_cap) * np.sin(th) * wt
+    th, g = _cap_nodes(float(theta_cap), int(n_theta))
     fs = [fn(th) * g for fn in fns]
     outs = [np.empty(lmax + 1) for _ in fns]
     for l in range(lmax + 1):

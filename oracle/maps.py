@@ -49,12 +49,15 @@ def ring_alm(maps, cos_theta, n_phi, lmax, d_omega, mmax=None):
     n_ring = cos_theta.size
     if mmax is None:
         mmax = min(lmax, n_phi // 2)
-    F = np.fft.fft(maps.reshape(maps.shape[0], n_ring, n_phi), axis=2)   # sum_j T e^{-i m phi_j}
-    F = F * np.broadcast_to(np.asarray(d_omega, dtype=np.float64), (n_ring,))[None, :, None]
+    F = np.fft.rfft(maps.reshape(maps.shape[0], n_ring, n_phi), axis=2)  # sum_j T e^{-i m phi_j}, m <= n_phi / 2
+    # (m, map, ring) for m <= mmax, times the solid angle of each ring's pixels
+    F = np.ascontiguousarray(np.moveaxis(F[:, :, : mmax + 1], 2, 0)) * np.broadcast_to(
+        np.asarray(d_omega, dtype=np.float64), (n_ring,))[None, None, :]
+    Fr, Fi = np.ascontiguousarray(F.real), np.ascontiguousarray(F.imag)
     alm = np.zeros((maps.shape[0], lmax + 1, mmax + 1), dtype=np.complex128)
     for m in range(mmax + 1):
         lam = legendre_lambda(m, lmax, cos_theta)                      # (lmax - m + 1, n_ring)
-        alm[:, m:, m] = F[:, :, m] @ lam.T
+        alm[:, m:, m] = Fr[m] @ lam.T + 1j * (Fi[m] @ lam.T)
     return alm
 
 

@@ -19,6 +19,7 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 F32, F64 = 1, 2
 TRILINEAR, TRICUBIC = 1, 2
 ENS_AUTO, ENS_CHAINED, ENS_PIPELINED = 0, 1, 2
+ENS_ONE_LANE, ENS_TWO_LANES = 0x100, 0x200
 OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y = 1, 2, 3, 4, 5, 6
 
 _DTYPES = {"f32": F32, "float32": F32, F32: F32, "f64": F64, "float64": F64, F64: F64}
@@ -56,6 +57,7 @@ def lib():
             "cmbx_simulate_patch": (I, [P, U64, D, P, I64, P]),
             "cmbx_ensemble_create": (I, [ctypes.POINTER(_Job), I, I, ctypes.POINTER(P)]),
             "cmbx_ensemble_modes": (I, [P, ctypes.POINTER(I), I]),
+            "cmbx_ensemble_lanes": (I, [P]),
             "cmbx_ensemble_launch": (I, [P, P]),
             "cmbx_ensemble_destroy": (I, [P]),
             "cmbx_debug_noise": (I, [P, U64, P]),
@@ -373,8 +375,9 @@ class Ensemble:
 
     _MODES = {"auto": ENS_AUTO, "chained": ENS_CHAINED, "pipelined": ENS_PIPELINED}
 
-    def __init__(self, jobs, mode="auto"):
-        """jobs: list of dict(plan=Plan, seed, r, dirs=tensor, out=tensor)."""
+    def __init__(self, jobs, mode="auto", lanes=None):
+        """jobs: list of dict(plan=Plan, seed, r, dirs=tensor, out=tensor). lanes: None
+        (auto mode times one and two lanes; explicit modes use one), 1 or 2."""
         arr = (_Job * len(jobs))()
         self._keep = []
         for i, j in enumerate(jobs):
@@ -383,7 +386,8 @@ class Ensemble:
             arr[i] = _Job(p.handle, int(j["seed"]), float(j["r"]), d, n_pix, o)
             self._keep.append(j)
         h = ctypes.c_void_p()
-        _check(lib().cmbx_ensemble_create(arr, len(jobs), self._MODES.get(mode, mode), ctypes.byref(h)))
+        flags = {None: 0, 1: ENS_ONE_LANE, 2: ENS_TWO_LANES}[lanes]
+        _check(lib().cmbx_ensemble_create(arr, len(jobs), self._MODES.get(mode, mode) | flags, ctypes.byref(h)))
         self.handle = h.value
 
     @property
@@ -393,6 +397,14 @@ class Ensemble:
         n = lib().cmbx_ensemble_modes(self.handle, buf, 64)
         names = {ENS_CHAINED: "chained", ENS_PIPELINED: "pipelined"}
         return [names.get(buf[i], buf[i]) for i in range(min(n, 64))]
+
+    @property
+    def lanes(self):
+        """Number of graphs (and streams) the ensemble runs in."""
+        n = lib().cmbx_ensemble_lanes(self.handle)
+        if n < 0:
+            _check(n)
+        return n
 
     def launch(self, stream=None):
         import torch

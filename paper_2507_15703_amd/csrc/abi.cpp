@@ -38,8 +38,13 @@ struct cmbx_plan {
 };
 
 struct cmbx_ensemble {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // lane 0 runs on the caller's stream; lane i > 0 on streams[i - 1], forked from and
+  // joined back into the caller's stream at every launch
+  std::vector<hipGraph_t> graph;
+  std::vector<hipGraphExec_t> exec;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> done;
+  hipEvent_t fork = nullptr;
   std::vector<void*> dev;  // rotating workspaces and the schedule
   std::vector<int> modes;  // execution mode chosen per (precision, N) group
   int device = 0;
@@ -403,6 +408,7 @@ struct Item {
   const double* dirs;
   int64_t n_pix;
   void* out;
+  int lane = 0;  // chained mode: the graph (and stream) the item runs in
 };
 
 // Interleave the roles' workgroups in proportion to their counts (largest-deficit
@@ -433,15 +439,17 @@ struct Group {
   int mode = CMBX_ENS_CHAINED;
 };
 
-int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t s) {
+int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t s, int lane) {
   if (mode == CMBX_ENS_CHAINED) {
     for (const Item& it : gr.items) {
+      if (lane >= 0 && it.lane != lane) continue;
       char* buf = (char*)it.plan->field + (size_t)it.slot * it.plan->field_bytes();
       if (int rc = enqueue_field(it.plan, it.seed, buf, s)) return rc;
       if (int rc = enqueue_gather(it.plan, buf, it.r, it.dirs, it.n_pix, it.out, s)) return rc;
     }
     return CMBX_OK;
   }
+  if (lane > 0) return CMBX_OK;  // pipelined groups run in lane 0
   for (size_t i = 0; i < gr.pipe.size(); ++i) {
     cmbx::PipeLaunch a = gr.pipe[i];
     a.sched = dsched + gr.sched_off[i];
@@ -450,16 +458,17 @@ int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t
   return CMBX_OK;
 }
 
-// Capture the groups (each in its chosen mode, or all in `force` if >= 0) into a graph.
-int capture(const std::vector<Group>& groups, const uint32_t* dsched, int only, int force, hipGraph_t* graph,
-            hipGraphExec_t* exec) {
+// Capture the groups (each in its chosen mode, or all in `force` if >= 0; only group
+// `only` if >= 0; only the items of `lane` if >= 0) into a graph.
+int capture(const std::vector<Group>& groups, const uint32_t* dsched, int only, int force, int lane,
+            hipGraph_t* graph, hipGraphExec_t* exec) {
   hipStream_t cap = nullptr;
   HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   int rc = CMBX_OK;
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   for (size_t gi = 0; e == hipSuccess && rc == CMBX_OK && gi < groups.size(); ++gi) {
     if (only >= 0 && (int)gi != only) continue;
-    rc = enqueue_group(groups[gi], force >= 0 ? force : groups[gi].mode, dsched, cap);
+    rc = enqueue_group(groups[gi], force >= 0 ? force : groups[gi].mode, dsched, cap, lane);
   }
   hipGraph_t gph = nullptr;
   const hipError_t e_end = hipStreamEndCapture(cap, &gph);
@@ -473,6 +482,119 @@ int capture(const std::vector<Group>& groups, const uint32_t* dsched, int only, 
   }
   *graph = gph;
   return CMBX_OK;
+}
+
+// Split the chained items over two lanes by plan, largest work first into the lighter
+// lane. Returns false (everything in lane 0) when fewer than two plans are chained.
+bool assign_lanes(std::vector<Group>& groups) {
+  std::vector<const cmbx_plan*> plans;
+  std::vector<double> cost;
+  for (Group& gr : groups) {
+    for (Item& it : gr.items) {
+      it.lane = 0;
+      if (gr.mode != CMBX_ENS_CHAINED) continue;
+      size_t k = 0;
+      while (k < plans.size() && plans[k] != it.plan) ++k;
+      if (k == plans.size()) plans.push_back(it.plan), cost.push_back(0.0);
+      cost[k] += (double)it.plan->N * it.plan->N * it.plan->N + (double)it.n_pix;
+    }
+  }
+  if (plans.size() < 2) return false;
+  std::vector<size_t> order(plans.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  double load[2] = {0.0, 0.0};
+  std::vector<int> lane_of(plans.size(), 0);
+  for (size_t k : order) {
+    const int l = load[1] < load[0] ? 1 : 0;
+    lane_of[k] = l;
+    load[l] += cost[k];
+  }
+  for (Group& gr : groups)
+    for (Item& it : gr.items) {
+      if (gr.mode != CMBX_ENS_CHAINED) continue;
+      size_t k = 0;
+      while (plans[k] != it.plan) ++k;
+      it.lane = lane_of[k];
+    }
+  return true;
+}
+
+void clear_lanes(cmbx_ensemble* en) {
+  for (hipGraphExec_t x : en->exec)
+    if (x) (void)hipGraphExecDestroy(x);
+  for (hipGraph_t gph : en->graph)
+    if (gph) (void)hipGraphDestroy(gph);
+  for (hipStream_t st : en->streams)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : en->done)
+    if (ev) (void)hipEventDestroy(ev);
+  if (en->fork) (void)hipEventDestroy(en->fork);
+  en->exec.clear();
+  en->graph.clear();
+  en->streams.clear();
+  en->done.clear();
+  en->fork = nullptr;
+}
+
+// Capture `lanes` graphs (lane 0 also holds the pipelined groups) and their streams.
+int build_lanes(cmbx_ensemble* en, const std::vector<Group>& groups, const uint32_t* dsched, int lanes) {
+  for (int l = 0; l < lanes; ++l) {
+    hipGraph_t gph = nullptr;
+    hipGraphExec_t ex = nullptr;
+    if (int rc = capture(groups, dsched, -1, -1, lanes == 1 ? -1 : l, &gph, &ex)) return rc;
+    en->graph.push_back(gph);
+    en->exec.push_back(ex);
+  }
+  if (lanes > 1) {
+    HIP_TRY(hipEventCreateWithFlags(&en->fork, hipEventDisableTiming));
+    for (int l = 1; l < lanes; ++l) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      en->streams.push_back(st);
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      en->done.push_back(ev);
+    }
+  }
+  return CMBX_OK;
+}
+
+// Lane 0 on s; the other lanes forked from s onto their streams and joined back into s.
+int launch_lanes(cmbx_ensemble* en, hipStream_t s) {
+  const size_t nl = en->exec.size();
+  if (nl > 1) HIP_TRY(hipEventRecord(en->fork, s));
+  for (size_t i = 1; i < nl; ++i) {
+    HIP_TRY(hipStreamWaitEvent(en->streams[i - 1], en->fork, 0));
+    HIP_TRY(hipGraphLaunch(en->exec[i], en->streams[i - 1]));
+    HIP_TRY(hipEventRecord(en->done[i - 1], en->streams[i - 1]));
+  }
+  HIP_TRY(hipGraphLaunch(en->exec[0], s));
+  for (size_t i = 1; i < nl; ++i) HIP_TRY(hipStreamWaitEvent(s, en->done[i - 1], 0));
+  return CMBX_OK;
+}
+
+// Average milliseconds of an ensemble's launch over three launches after two warm-ups
+// (-1 on error).
+double time_ensemble(cmbx_ensemble* en) {
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double ms = -1.0;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+      hipEventCreate(&e1) == hipSuccess) {
+    int rc = CMBX_OK;
+    for (int i = 0; rc == CMBX_OK && i < 2; ++i) rc = launch_lanes(en, s);
+    hipError_t e = rc == CMBX_OK ? hipEventRecord(e0, s) : hipErrorUnknown;
+    for (int i = 0; e == hipSuccess && rc == CMBX_OK && i < 3; ++i) rc = launch_lanes(en, s);
+    if (e == hipSuccess && rc == CMBX_OK) e = hipEventRecord(e1, s);
+    if (e == hipSuccess && rc == CMBX_OK) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess && rc == CMBX_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / 3.0;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  return ms;
 }
 
 // Average milliseconds of a graph over three launches after two warm-ups (-1 on error).
@@ -503,8 +625,12 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
   if (!out) return fail(CMBX_EINVAL, "out is NULL");
   *out = nullptr;
   if (!jobs || n_jobs < 1) return fail(CMBX_EINVAL, "need at least one job");
+  const int lanes_flag = mode & (CMBX_ENS_ONE_LANE | CMBX_ENS_TWO_LANES);
+  mode &= ~(CMBX_ENS_ONE_LANE | CMBX_ENS_TWO_LANES);
   if (mode != CMBX_ENS_AUTO && mode != CMBX_ENS_CHAINED && mode != CMBX_ENS_PIPELINED)
     return fail(CMBX_EINVAL, "unknown ensemble mode %d", mode);
+  if (lanes_flag == (CMBX_ENS_ONE_LANE | CMBX_ENS_TWO_LANES))
+    return fail(CMBX_EINVAL, "CMBX_ENS_ONE_LANE and CMBX_ENS_TWO_LANES exclude each other");
   for (int j = 0; j < n_jobs; ++j) {
     if (!jobs[j].plan) return fail(CMBX_EINVAL, "job %d has no plan", j);
     if (int rc = check_patch_args(jobs[j].plan, jobs[j].r, jobs[j].dirs, jobs[j].n_pix, jobs[j].out)) {
@@ -536,6 +662,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
   cmbx_ensemble* en = new cmbx_ensemble;
   en->device = jobs[0].plan->device;
   auto bail = [&](int code, const std::string& msg) {
+    clear_lanes(en);
     for (void* d : en->dev) (void)hipFree(d);
     delete en;
     return code == CMBX_OK ? CMBX_OK : fail(code, "%s", msg.c_str());
@@ -613,7 +740,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
       for (int k = 0; k < 2; ++k) {
         hipGraph_t gph = nullptr;
         hipGraphExec_t ex = nullptr;
-        if (int rc = capture(groups, dsched, (int)gi, modes[k], &gph, &ex)) return bail(rc, g_err);
+        if (int rc = capture(groups, dsched, (int)gi, modes[k], -1, &gph, &ex)) return bail(rc, g_err);
         t[k] = time_graph(ex);
         (void)hipGraphExecDestroy(ex);
         (void)hipGraphDestroy(gph);
@@ -622,7 +749,24 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
       groups[gi].mode = t[1] < t[0] ? CMBX_ENS_PIPELINED : CMBX_ENS_CHAINED;
     }
   }
-  if (int rc = capture(groups, dsched, -1, -1, &en->graph, &en->exec)) return bail(rc, g_err);
+  // Lanes: with two, the chained items are split by plan (items of one plan share its
+  // workspace and stay in one lane) into two graphs that run on two streams.
+  const bool two_possible = assign_lanes(groups);
+  int lanes = 1;
+  if (two_possible && (lanes_flag == CMBX_ENS_TWO_LANES || (lanes_flag == 0 && mode == CMBX_ENS_AUTO))) lanes = 2;
+  if (int rc = build_lanes(en, groups, dsched, lanes)) return bail(rc, g_err);
+  if (lanes == 2 && lanes_flag == 0) {
+    // AUTO: keep two lanes only if they are faster than one
+    const double t2 = time_ensemble(en);
+    clear_lanes(en);
+    if (int rc = build_lanes(en, groups, dsched, 1)) return bail(rc, g_err);
+    const double t1 = time_ensemble(en);
+    if (t1 < 0 || t2 < 0) return bail(CMBX_EHIP, "ensemble lane timing failed");
+    if (t2 < t1) {
+      clear_lanes(en);
+      if (int rc = build_lanes(en, groups, dsched, 2)) return bail(rc, g_err);
+    }
+  }
   bool any_pipe = false;
   for (const Group& gr : groups) {
     en->modes.push_back(gr.mode);
@@ -644,9 +788,15 @@ int cmbx_ensemble_modes(const cmbx_ensemble* en, int* modes, int cap) {
   return n;
 }
 
+int cmbx_ensemble_lanes(const cmbx_ensemble* en) {
+  if (!en) return fail(CMBX_EINVAL, "ensemble is NULL");
+  return (int)en->exec.size();
+}
+
 int cmbx_ensemble_launch(cmbx_ensemble* en, void* stream) {
   if (!en) return fail(CMBX_EINVAL, "ensemble is NULL");
-  HIP_TRY(hipGraphLaunch(en->exec, (hipStream_t)stream));
+  DeviceGuard g(en->device);
+  if (int rc = launch_lanes(en, (hipStream_t)stream)) return rc;
   return ok();
 }
 
@@ -654,8 +804,7 @@ int cmbx_ensemble_destroy(cmbx_ensemble* en) {
   if (!en) return ok();
   DeviceGuard g(en->device);
   (void)hipDeviceSynchronize();
-  if (en->exec) (void)hipGraphExecDestroy(en->exec);
-  if (en->graph) (void)hipGraphDestroy(en->graph);
+  clear_lanes(en);
   for (void* d : en->dev) (void)hipFree(d);
   delete en;
   return ok();

@@ -71,6 +71,7 @@ def test_null_arguments(L):
     assert L.cmbx_plan_set(None, cmbx.OPT_INTERP, 1) == cmbx.EINVAL
     assert L.cmbx_ensemble_create(None, 0, 0, None) == cmbx.EINVAL
     assert L.cmbx_ensemble_launch(None, None) == cmbx.EINVAL
+    assert L.cmbx_ensemble_lanes(None) == cmbx.EINVAL
     assert L.cmbx_plan_destroy(None) == cmbx.OK
     assert L.cmbx_ensemble_destroy(None) == cmbx.OK
 
