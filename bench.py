@@ -155,13 +155,14 @@ def main():
     names = ["pass_x_noise", "pass_y", "pass_z_c2r", "gather_tricubic"]
     kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
                for n, t, b in zip(names, ms, kbytes)}
-    # The dominant kernel is the noise + x pass, bound by plain ALU issue: its algorithmic
-    # work per mode is the binary32 Box-Muller sequence (70 flops) + the two weight products
-    # + half a Philox4x32-10 call (10 rounds x (2 wide multiplies + 4 xor) / 2 = 30 integer
-    # ops) + the x transform (5 log2 N flops per point); peak = 256 CUs x 4 SIMDs x 16
-    # lanes x 2.4 GHz = 39.3 T lane-ops/s for unfused, unpacked operations.
+    # The dominant kernel is the noise + x pass, bound by the vector ALU: its algorithmic
+    # work per mode is the binary32 Box-Muller sequence (49 floating-point operations with
+    # its four conversions) + the two weight products + half a Philox4x32-10 call (10 rounds
+    # x (2 wide multiplies + 4 xor) / 2 = 30 integer ops) + the x transform (5 log2 N flops
+    # per point); peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s for
+    # unfused, unpacked operations.
     modes = N**3 // 2
-    ops_per_mode = 70 + 2 + 30 + 5 * math.log2(N)
+    ops_per_mode = 49 + 2 + 30 + 5 * math.log2(N)
     alu_peak = 256 * 4 * 16 * 2.4e9
     ach_ops = modes * ops_per_mode / (ms[0] * 1e-3)
     # HBM bytes per launch of this kernel from rocprofv3 FETCH_SIZE (x2.0 calibration against

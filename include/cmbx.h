@@ -45,6 +45,10 @@ extern "C" {
 #define CMBX_ENOMEM       -3  /* a device or host allocation failed */
 #define CMBX_EHIP         -4  /* a HIP runtime call failed (no device, launch error) */
 #define CMBX_ESTATE       -5  /* call out of order (e.g. simulate before a spectrum is set) */
+/* Tests of the error paths can make some sites fail as the runtime would: the environment
+ * variable CMBX_FAULT, read at each call, holds a comma-separated list of "alloc" (plan
+ * allocation: CMBX_ENOMEM), "capture" (ensemble graph capture: CMBX_EHIP) and "launch"
+ * (ensemble launch: CMBX_EHIP). Unset, it costs one getenv per such call. */
 
 /* working precision of a plan */
 #define CMBX_F32 1
@@ -167,6 +171,13 @@ int cmbx_ensemble_launch(cmbx_ensemble* ens, void* stream);
 int cmbx_ensemble_destroy(cmbx_ensemble* ens);
 
 /* ---- stage-by-stage entry points (tests and profiling) ---- */
+
+/* The 768 binary32 entries of the single-precision Box-Muller tables, computed on the host
+ * (no device needed): ln(1 + j/128), or ln((1 + j/128)/2) for j >= 54, then 1/(1 + j/128)
+ * for j = 0..127, then sin and cos of (k + 1/2) 2 pi/256 for k = 0..255, each the binary64
+ * value rounded once. The noise of Sec. II D 1 in FP32 plans reads them. out: host buffer
+ * of cap >= 768 floats. Returns 768, or CMBX_EINVAL. */
+int cmbx_noise_tables(float* out, int cap);
 
 /* Write the unpacked weighted half grid of realisation `seed`: device complex array
  * [N][N][N/2+1] of the plan's precision (re, im interleaved). */

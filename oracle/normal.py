@@ -28,6 +28,12 @@ cos, sin of 2 pi u2: the top two bits of b give the quadrant; the remaining 30 b
 folded to an angle t = rho (2 pi 2^-32) in [0, pi/4], rho <= 2^29 an integer, with sin and
 cos swapped when folded. sin t = t sum_{k=0..8} (-1)^k t^{2k}/(2k+1)! and
 cos t = sum_{k=0..9} (-1)^k t^{2k}/(2k)! (truncation < 1e-16).
+
+Single-precision plans use their own binary32 sequence (the ``*_f32`` functions), built
+for fewer operations: ln by a 128-entry table of ln(1 + j/128) and a cubic in the
+remainder, sin and cos by a 256-entry table of sector mid-points and the angle-sum
+formulas with a short series in the offset, sqrt as above with three Newton steps. Its
+tables are binary64 values rounded once to binary32.
 """
 import numpy as np
 
@@ -130,16 +136,34 @@ def box_muller(a, b):
 F32 = np.float32
 LN2_HI_F = F32(float.fromhex("0x1.62e4p-1"))
 LN2_LO_F = F32(float.fromhex("0x1.7f7d1cp-20"))
-SQRT2_F = F32(float.fromhex("0x1.6a09e6p+0"))
 TWO_PI_2M32_F = F32(float.fromhex("0x1.921fb6p-30"))
 RSQRT_MAGIC_F = np.uint32(0x5F3759DF)
-_ATANH_CF = [F32(1.0 / (2 * k + 1)) for k in range(5)]
-_SIN_CF = [F32(c) for c in _SIN_C[:5]]
-_COS_CF = [F32(c) for c in _COS_C[:6]]
+THIRD_F = F32(1.0 / 3.0)
+SIXTH_F = F32(1.0 / 6.0)
+FOLD_J = 54   # table entries with c_j = 1 + j/128 >= sqrt 2 hold ln(c_j / 2)
+
+
+def _tables_f32():
+    """The binary32 tables of the single-precision sequence, each entry the binary64 value
+    of its definition rounded once to binary32:
+      LN[j]  = ln(c_j), or ln(c_j / 2) for j >= 54, with c_j = 1 + j/128 (j = 0..127);
+      INV[j] = 1 / c_j;
+      SIN[k], COS[k] = sin, cos of (k + 1/2) 2 pi / 256 (k = 0..255)."""
+    c = 1.0 + np.arange(128, dtype=np.float64) / 128.0
+    ln = np.where(np.arange(128) >= FOLD_J, np.log(c / 2.0), np.log(c))
+    ang = (np.arange(256, dtype=np.float64) + 0.5) * (2.0 * np.pi / 256.0)
+    return ln.astype(F32), (1.0 / c).astype(F32), np.sin(ang).astype(F32), np.cos(ang).astype(F32)
+
+
+LN_TAB_F, INV_TAB_F, SIN_TAB_F, COS_TAB_F = _tables_f32()
 
 
 def canonical_log_u1_f32(a):
-    """ln((a + 1) 2^-32) in binary32 by the fixed operation sequence."""
+    """ln((a + 1) 2^-32) in binary32 by the table sequence: a + 1 = mi 2^(e0 - 23) with
+    mi the leading 24 bits, m = mi 2^-23 in [1, 2), j = the 7 bits of mi after its leading
+    one, c_j = 1 + j/128 (exact), r = (m - c_j) INV[j] (the subtraction is exact),
+    ln(1 + r) ~ r (1 + r (r/3 - 1/2)) (|r| < 2^-7, truncation < 1e-9), and
+    ln u1 = e ln 2 + (LN[j] + ln(1 + r)) with e = e0 - 32, plus one for j >= 54."""
     a = np.asarray(a, dtype=np.uint64)
     v = a + np.uint64(1)                                 # 1 .. 2^32
     _, ex = np.frexp(v.astype(np.float64))               # exact exponent: v in [2^(ex-1), 2^ex)
@@ -147,56 +171,47 @@ def canonical_log_u1_f32(a):
     sh = e0 - 23
     mi = np.where(sh >= 0, v >> np.maximum(sh, 0).astype(np.uint64),
                   v << np.maximum(-sh, 0).astype(np.uint64))       # [2^23, 2^24)
+    j = ((mi >> np.uint64(16)) & np.uint64(127)).astype(np.int64)
     m = mi.astype(F32) * F32(2.0**-23)                   # [1, 2), exact
-    big = m >= SQRT2_F
-    m = np.where(big, m * F32(0.5), m)
-    e = np.where(big, e0 + 1, e0) - 32
-    d = m + F32(1.0)
-    y = np.full_like(d, F32(0.5))
-    for _ in range(4):
-        y = y * (F32(2.0) - d * y)
-    s = (m - F32(1.0)) * y
-    s2 = s * s
-    p = np.full_like(s, _ATANH_CF[4])
-    for k in range(3, -1, -1):
-        p = p * s2 + _ATANH_CF[k]
-    lnm = (s + s) * p
+    c = (j + 128).astype(F32) * F32(2.0**-7)             # exact
+    r = (m - c) * INV_TAB_F[j]
+    q = r * THIRD_F - F32(0.5)
+    lp = r * (q * r + F32(1.0))
+    lnm = LN_TAB_F[j] + lp
+    e = e0 - 32 + (j >= FOLD_J)
     ef = e.astype(F32)
     return ef * LN2_HI_F + (ef * LN2_LO_F + lnm)
 
 
 def canonical_sqrt_f32(x):
+    """sqrt(x) for x >= 0 by three Newton steps for 1/sqrt from the integer-shift seed;
+    x <= 0 gives 0."""
     x = np.asarray(x, dtype=F32)
-    bits = x.view(np.uint32)
+    bits = np.maximum(x, F32(0.0)).view(np.uint32)
     y = (RSQRT_MAGIC_F - (bits >> np.uint32(1))).view(F32)
     hx = F32(0.5) * x
     for _ in range(3):
         y = y * (F32(1.5) - hx * (y * y))
     r = x * y
-    return np.where(x == F32(0.0), F32(0.0), r).astype(F32)
+    return np.where(x <= F32(0.0), F32(0.0), r).astype(F32)
 
 
 def canonical_sincos_2pi_f32(b):
+    """sin, cos of 2 pi b 2^-32 in binary32 by the table sequence: k = the top 8 bits of b,
+    d = (low 24 bits - 2^23) 2 pi 2^-32 (|d| <= pi/256; the integer is exact in binary32),
+    sin d ~ d - d (d^2 / 6), cos d ~ 1 - d^2 / 2 (truncation < 1e-9), and the sum formulas
+    sin = SIN[k] cos d + COS[k] sin d, cos = COS[k] cos d - SIN[k] sin d."""
     b = np.asarray(b, dtype=np.uint64)
-    q = b >> np.uint64(30)
-    r = b & np.uint64(0x3FFFFFFF)
-    swap = r >= np.uint64(1 << 29)
-    rho = np.where(swap, np.uint64(1 << 30) - r, r)
-    t = rho.astype(F32) * TWO_PI_2M32_F
-    t2 = t * t
-    ps = np.full_like(t, _SIN_CF[4])
-    for k in range(3, -1, -1):
-        ps = ps * t2 + _SIN_CF[k]
-    st = t * ps
-    pc = np.full_like(t, _COS_CF[5])
-    for k in range(4, -1, -1):
-        pc = pc * t2 + _COS_CF[k]
-    ct = pc
-    s_in = np.where(swap, ct, st)
-    c_in = np.where(swap, st, ct)
-    sin = np.select([q == 0, q == 1, q == 2], [s_in, c_in, -s_in], -c_in).astype(F32)
-    cos = np.select([q == 0, q == 1, q == 2], [c_in, -s_in, -c_in], s_in).astype(F32)
-    return sin, cos
+    k = (b >> np.uint64(24)).astype(np.int64)
+    low = (b & np.uint64(0xFFFFFF)).astype(np.int64) - (1 << 23)
+    d = low.astype(F32) * TWO_PI_2M32_F
+    d2 = d * d
+    sd = d - d * (d2 * SIXTH_F)
+    cd = F32(1.0) - d2 * F32(0.5)
+    S, C = SIN_TAB_F[k], COS_TAB_F[k]
+    sin = S * cd + C * sd
+    cos = C * cd - S * sd
+    return sin.astype(F32), cos.astype(F32)
 
 
 def box_muller_f32(a, b):

@@ -58,6 +58,7 @@ def lib():
             "cmbx_ensemble_create": (I, [ctypes.POINTER(_Job), I, I, ctypes.POINTER(P)]),
             "cmbx_ensemble_modes": (I, [P, ctypes.POINTER(I), I]),
             "cmbx_ensemble_lanes": (I, [P]),
+            "cmbx_noise_tables": (I, [P, I]),
             "cmbx_ensemble_launch": (I, [P, P]),
             "cmbx_ensemble_destroy": (I, [P]),
             "cmbx_debug_noise": (I, [P, U64, P]),

@@ -8,8 +8,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -199,6 +202,45 @@ int enqueue_patch(cmbx_plan* p, uint64_t seed, double r, const double* dirs, int
   return CMBX_OK;
 }
 
+// Fault injection for tests of the error paths: the environment variable CMBX_FAULT holds
+// a comma-separated list of sites ("alloc": plan allocation, "capture": ensemble graph
+// capture, "launch": ensemble launch) that then fail as the runtime would.
+bool fault(const char* site) {
+  const char* e = std::getenv("CMBX_FAULT");
+  if (!e || !*e) return false;
+  const std::string list = std::string(",") + e + ",";
+  return list.find(std::string(",") + site + ",") != std::string::npos;
+}
+
+// The binary32 Box-Muller tables (layout in noise_device.hpp): each entry the binary64
+// value of its definition rounded once to binary32.
+void fill_noise_tables(float* t) {
+  for (int j = 0; j < 128; ++j) {
+    const double c = 1.0 + j / 128.0;
+    t[j] = (float)std::log(j >= 54 ? c / 2.0 : c);
+    t[128 + j] = (float)(1.0 / c);
+  }
+  const double step = 2.0 * M_PI / 256.0;
+  for (int k = 0; k < 256; ++k) {
+    const double ang = (k + 0.5) * step;
+    t[256 + k] = (float)std::sin(ang);
+    t[512 + k] = (float)std::cos(ang);
+  }
+}
+
+// Upload the tables to the current device once per process.
+hipError_t ensure_noise_tables(int device) {
+  static std::mutex mu;
+  static std::set<int> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count(device)) return hipSuccess;
+  std::vector<float> t(cmbx::kNoiseTableSize);
+  fill_noise_tables(t.data());
+  const hipError_t e = cmbx::upload_noise_tables(t.data());
+  if (e == hipSuccess) done.insert(device);
+  return e;
+}
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -233,9 +275,11 @@ int cmbx_plan_box(int N, double L, int dtype, int batch, cmbx_plan** out) {
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking);
   p->stream = p->own_stream;
+  if (e == hipSuccess && fault("alloc")) e = hipErrorOutOfMemory;
   if (e == hipSuccess) e = hipMalloc(&p->field, p->field_bytes() * batch);
   if (e == hipSuccess) e = hipMalloc(&p->tw, (size_t)N * 2 * p->real_size());
   if (e == hipSuccess) e = hipMalloc(&p->wtab, (size_t)p->wtab_len() * p->real_size());
+  if (e == hipSuccess && dtype == CMBX_F32) e = ensure_noise_tables(p->device);
   if (e != hipSuccess) {
     const int code = (e == hipErrorOutOfMemory) ? CMBX_ENOMEM : CMBX_EHIP;
     const std::string msg = hipGetErrorString(e);
@@ -462,6 +506,7 @@ int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t
 // `only` if >= 0; only the items of `lane` if >= 0) into a graph.
 int capture(const std::vector<Group>& groups, const uint32_t* dsched, int only, int force, int lane,
             hipGraph_t* graph, hipGraphExec_t* exec) {
+  if (fault("capture")) return fail(CMBX_EHIP, "ensemble capture: injected fault (CMBX_FAULT)");
   hipStream_t cap = nullptr;
   HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   int rc = CMBX_OK;
@@ -788,6 +833,13 @@ int cmbx_ensemble_modes(const cmbx_ensemble* en, int* modes, int cap) {
   return n;
 }
 
+int cmbx_noise_tables(float* out, int cap) {
+  if (!out || cap < cmbx::kNoiseTableSize)
+    return fail(CMBX_EINVAL, "noise tables need a buffer of %d floats", cmbx::kNoiseTableSize);
+  fill_noise_tables(out);
+  return cmbx::kNoiseTableSize;
+}
+
 int cmbx_ensemble_lanes(const cmbx_ensemble* en) {
   if (!en) return fail(CMBX_EINVAL, "ensemble is NULL");
   return (int)en->exec.size();
@@ -795,6 +847,7 @@ int cmbx_ensemble_lanes(const cmbx_ensemble* en) {
 
 int cmbx_ensemble_launch(cmbx_ensemble* en, void* stream) {
   if (!en) return fail(CMBX_EINVAL, "ensemble is NULL");
+  if (fault("launch")) return fail(CMBX_EHIP, "ensemble launch: injected fault (CMBX_FAULT)");
   DeviceGuard g(en->device);
   if (int rc = launch_lanes(en, (hipStream_t)stream)) return rc;
   return ok();

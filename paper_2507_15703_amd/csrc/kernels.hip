@@ -53,6 +53,15 @@ struct HalfToComplex {
   __device__ __forceinline__ void done() const { __syncthreads(); }
 };
 
+// ------------------------------------------------------------------ noise tables
+// The binary32 Box-Muller tables (bmf layout), one copy per device, written by
+// upload_noise_tables before the first single-precision plan runs there.
+__device__ float g_bm_tab[bmf::kTabSize];
+
+// LDS slots (complex units) the pass-x tile reserves for the tables: binary32 only.
+template <typename T>
+constexpr int tab_cpx() { return sizeof(T) == 4 ? bmf::kTabSize / 2 : 0; }
+
 // ------------------------------------------------------------------ launch shapes
 constexpr int clamp_nt(int work) { return work >= 2048 ? 256 : work >= 1024 ? 128 : 64; }
 
@@ -73,7 +82,8 @@ struct ZShape {
 // Workgroup = (z tile zt of TZ packed columns, one iy). Generates the N x TZ tile of
 // weighted modes in LDS (one Philox call per pair of neighbouring iz), then runs the
 // length-N inverse transform along x and writes the tile's N rows of TZ columns (128 B for
-// FP32 TZ = 16) to the strided x axis. smem: N TZ + N complex (tile, then twiddles).
+// FP32 TZ = 16) to the strided x axis. smem: N TZ + N complex (tile, then twiddles), then
+// for binary32 the Box-Muller tables.
 template <typename T, int N, int TZ, int NT>
 __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __restrict__ buf,
                                        const T* __restrict__ wtab, const cpx<T>* __restrict__ twg, uint32_t k0,
@@ -87,14 +97,20 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   const int zc0 = zt * TZ;
   const T* wself = wtab + 3 * M * M + 1;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  float* tab = nullptr;
+  if constexpr (tab_cpx<T>() > 0) {
+    tab = reinterpret_cast<float*>(smem + N * TZ + N);
+    for (int i = tid; i < bmf::kTabSize; i += NT) tab[i] = g_bm_tab[i];
+    __syncthreads();
+  }
   const int fy2 = freq2(iy, N);
   if (zc0 == 0) {
     // column 0 packs the Hermitian planes iz = 0 and N/2; column 1 is iz = 1
     for (int ix = tid; ix < N; ix += NT) {
-      const cpx<T> a = mode_value<T>(N, ix, iy, 0, k0, k1, wtab, wself);
-      const cpx<T> b = mode_value<T>(N, ix, iy, M, k0, k1, wtab, wself);
+      const cpx<T> a = mode_value<T>(N, ix, iy, 0, k0, k1, wtab, wself, tab);
+      const cpx<T> b = mode_value<T>(N, ix, iy, M, k0, k1, wtab, wself, tab);
       tile[ix * TZ] = {a.x - b.y, a.y + b.x};  // Z_0 + i Z_{N/2}
-      tile[ix * TZ + 1] = mode_value<T>(N, ix, iy, 1, k0, k1, wtab, wself);
+      tile[ix * TZ + 1] = mode_value<T>(N, ix, iy, 1, k0, k1, wtab, wself, tab);
     }
   }
   // every other pair of columns (2p, 2p + 1) holds two generic modes drawn from one
@@ -107,8 +123,8 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
     const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
     const int m0 = freq2(ix, N) + fy2 + zc * zc;
     const int m1 = m0 + 2 * zc + 1;
-    tile[ix * TZ + 2 * pr] = weighted<T>(wtab[m0], w.x, w.y);
-    tile[ix * TZ + 2 * pr + 1] = weighted<T>(wtab[m1], w.z, w.w);
+    tile[ix * TZ + 2 * pr] = weighted<T>(wtab[m0], w.x, w.y, tab);
+    tile[ix * TZ + 2 * pr + 1] = weighted<T>(wtab[m1], w.z, w.w, tab);
   }
   __syncthreads();
   LdsIO<T, N, TZ, true> first{tile};
@@ -155,7 +171,7 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __re
                                                                  const T* __restrict__ wtab,
                                                                  const cpx<T>* __restrict__ twg,
                                                                  uint32_t k0, uint32_t k1) {
-  __shared__ cpx<T> smem[N * TZ + N];
+  __shared__ cpx<T> smem[N * TZ + N + tab_cpx<T>()];
   role_x<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, wtab, twg, k0, k1);
 }
 
@@ -185,7 +201,7 @@ __global__ void k_noise_debug(cpx<T>* __restrict__ out, int N, const T* __restri
   const int64_t t = i / (M + 1);
   const int iy = (int)(t % N);
   const int ix = (int)(t / N);
-  out[i] = mode_value<T>(N, ix, iy, iz, k0, k1, wtab, wtab + 3 * M * M + 1);
+  out[i] = mode_value<T>(N, ix, iy, iz, k0, k1, wtab, wtab + 3 * M * M + 1, g_bm_tab);
 }
 
 // ------------------------------------------------------------------ gather
@@ -336,7 +352,7 @@ constexpr int kPipeNT = 256;
 template <typename T, int N, int TX, int TY, int LZ>
 struct PipeShape {
   static constexpr int M = N / 2;
-  static constexpr int SX = N * TX + N, SY = N * TY + N, SZ = LZ * M + N;
+  static constexpr int SX = N * TX + N + tab_cpx<T>(), SY = N * TY + N, SZ = LZ * M + N;
   static constexpr int SMEM = SX > SY ? (SX > SZ ? SX : SZ) : (SY > SZ ? SY : SZ);
 };
 
@@ -564,6 +580,10 @@ hipError_t launch_pipeline(const PipeLaunch& a, hipStream_t s) {
   const Entry* e = find(a.dtype, a.N);
   if (!e || a.nblocks < 1) return hipErrorInvalidValue;
   return e->pipe(a, s);
+}
+
+hipError_t upload_noise_tables(const float* host) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_bm_tab), host, sizeof(float) * bmf::kTabSize, 0, hipMemcpyHostToDevice);
 }
 
 hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uint32_t k0, uint32_t k1,

@@ -31,6 +31,11 @@ hipError_t launch_pass_y(const FieldArgs& a, hipStream_t s);
 // Pass 3: complex-to-real inverse FFT along z (unpacks the iz = 0 / N/2 column).
 hipError_t launch_pass_z(const FieldArgs& a, hipStream_t s);
 
+// Number of binary32 Box-Muller table entries and their upload to the current device
+// (before the first single-precision field there; the values never change).
+constexpr int kNoiseTableSize = 768;
+hipError_t upload_noise_tables(const float* host);
+
 // Unpacked weighted half grid [N][N][N/2+1] (tests).
 hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uint32_t k0, uint32_t k1,
                               hipStream_t s);

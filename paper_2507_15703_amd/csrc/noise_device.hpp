@@ -16,8 +16,8 @@
 //   sqrt x: four Newton steps for 1/sqrt(x) from the integer-shift seed, times x;
 //   cos, sin of 2 pi b 2^-32: quadrant from the top two bits, the rest folded to
 //     t in [0, pi/4] with sin/cos swapped when folded, Taylor series to t^17 / t^18.
-// Single-precision plans use a binary32 variant of the same steps (below); double
-// precision plans use the binary64 one.
+// Single-precision plans use their own binary32 sequence with small tables (below);
+// double precision plans use the binary64 one.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -125,73 +125,70 @@ namespace bmf {
 // binary32 constants
 constexpr float kLn2Head = 0x1.62e4p-1f;     // ln 2 with a 16-bit significand
 constexpr float kLn2Tail = 0x1.7f7d1cp-20f;  // ln 2 - head, rounded to binary32
-constexpr float kSqrt2 = 0x1.6a09e6p+0f;
 constexpr float kTwoPi2m32 = 0x1.921fb6p-30f;
+constexpr float kThird = 0x1.555556p-2f;     // 1/3 rounded to binary32
+constexpr float kSixth = 0x1.555556p-3f;     // 1/6 rounded to binary32
 constexpr uint32_t kRsqrtMagic = 0x5F3759DFu;
-// the binary64 quotients rounded to binary32
-constexpr float kSin[5] = {(float)bm::kSin[0], (float)bm::kSin[1], (float)bm::kSin[2], (float)bm::kSin[3],
-                           (float)bm::kSin[4]};
-constexpr float kCos[6] = {(float)bm::kCos[0], (float)bm::kCos[1], (float)bm::kCos[2],
-                           (float)bm::kCos[3], (float)bm::kCos[4], (float)bm::kCos[5]};
-constexpr float kAtanh[5] = {(float)bm::kAtanh[0], (float)bm::kAtanh[1], (float)bm::kAtanh[2],
-                             (float)bm::kAtanh[3], (float)bm::kAtanh[4]};
+constexpr uint32_t kFoldJ = 54;              // entries with c_j = 1 + j/128 >= sqrt 2 hold ln(c_j / 2)
+// table layout (binary32): ln c_j (or ln(c_j / 2)) and 1 / c_j for j = 0..127, then
+// sin and cos of (k + 1/2) 2 pi / 256 for k = 0..255
+constexpr int kTabLn = 0, kTabInv = 128, kTabSin = 256, kTabCos = 512, kTabSize = 768;
 }  // namespace bmf
 
-// binary32 variant for single-precision plans: the same steps in binary32 with series
-// sized to it. a + 1 is cut to its leading 24 bits (m = mi 2^-23, mi in [2^23, 2^24)),
-// four Newton steps for 1/(m + 1), artanh series to s^8, three Newton steps for
-// 1/sqrt(x), sine series to t^9 and cosine series to t^10.
-__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& g_re, float& g_im) {
+// binary32 sequence for single-precision plans (tab: the table above, in LDS or global):
+//   ln u1: a + 1 = mi 2^(e0 - 23), mi its leading 24 bits; m = mi 2^-23 in [1, 2);
+//     j = the 7 bits after mi's leading one, c_j = 1 + j/128 (exact), r = (m - c_j) / c_j
+//     by the table reciprocal (m - c_j is exact), ln(1 + r) ~ r (1 + r (r/3 - 1/2));
+//     ln u1 = e ln2_head + (e ln2_tail + (ln c_j + ln(1 + r))), e = e0 - 32 (+1 when the
+//     entry holds ln(c_j / 2));
+//   sqrt x: three Newton steps for 1/sqrt(x) from the integer-shift seed, times x; x <= 0
+//     gives 0;
+//   sin, cos of 2 pi b 2^-32: k = b >> 24, d = ((b & 0xFFFFFF) - 2^23) 2 pi 2^-32,
+//     sin d ~ d - d (d^2/6), cos d ~ 1 - d^2/2, then the angle-sum formulas with the
+//     tabulated sin and cos of the sector mid-point.
+__device__ __forceinline__ void box_muller_f32(uint32_t a, uint32_t b, float& g_re, float& g_im,
+                                               const float* __restrict__ tab) {
 #pragma clang fp contract(off)
   using namespace bmf;
   const uint64_t v = (uint64_t)a + 1ull;
   const int e0 = 63 - __clzll((long long)v);
   const uint32_t mi = e0 >= 23 ? (uint32_t)(v >> (e0 - 23)) : (uint32_t)(v << (23 - e0));
-  float m = (float)mi * 0x1p-23f;  // [1, 2), exact
-  const bool big = m >= kSqrt2;
-  m = big ? m * 0.5f : m;
-  const int e = (big ? e0 + 1 : e0) - 32;
-  const float d = m + 1.0f;
-  float y = 0.5f;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) y = y * (2.0f - d * y);
-  const float s = (m - 1.0f) * y;
-  const float s2 = s * s;
-  float p = kAtanh[4];
-#pragma unroll
-  for (int k = 3; k >= 0; --k) p = p * s2 + kAtanh[k];
-  const float lnm = (s + s) * p;
+  const uint32_t j = (mi >> 16) & 127u;
+  const float m = (float)mi * 0x1p-23f;            // exact
+  const float c = (float)(j + 128u) * 0x1p-7f;     // exact
+  const float r = (m - c) * tab[kTabInv + j];
+  const float q = r * kThird - 0.5f;
+  const float lp = r * (q * r + 1.0f);
+  const float lnm = tab[kTabLn + j] + lp;
+  const int e = e0 - 32 + (j >= kFoldJ ? 1 : 0);
   const float ef = (float)e;
   const float lnu = ef * kLn2Head + (ef * kLn2Tail + lnm);
   const float x = -(lnu + lnu);
-  float r = __uint_as_float(kRsqrtMagic - (__float_as_uint(x) >> 1));
+  float y = __uint_as_float(kRsqrtMagic - (__float_as_uint(x) >> 1));
   const float hx = 0.5f * x;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) r = r * (1.5f - hx * (r * r));
-  const float rad = (x == 0.0f) ? 0.0f : x * r;
-  const uint32_t q = b >> 30;
-  const uint32_t rr = b & 0x3FFFFFFFu;
-  const bool swap = rr >= (1u << 29);
-  const uint32_t rho = swap ? (1u << 30) - rr : rr;
-  const float t = (float)rho * kTwoPi2m32;
-  const float t2 = t * t;
-  float ps = kSin[4];
-#pragma unroll
-  for (int k = 3; k >= 0; --k) ps = ps * t2 + kSin[k];
-  const float st = t * ps;
-  float pc = kCos[5];
-#pragma unroll
-  for (int k = 4; k >= 0; --k) pc = pc * t2 + kCos[k];
-  const float ct = pc;
-  const float si = swap ? ct : st;
-  const float ci = swap ? st : ct;
-  const bool odd = (q & 1u) != 0u;
-  float sn = odd ? ci : si;
-  float cs = odd ? si : ci;
-  sn = (q & 2u) ? -sn : sn;
-  cs = ((q + 1u) & 2u) ? -cs : cs;
+  for (int i = 0; i < 3; ++i) y = y * (1.5f - hx * (y * y));
+  const float rad = (x <= 0.0f) ? 0.0f : x * y;
+  const uint32_t k = b >> 24;
+  const int low = (int)(b & 0xFFFFFFu) - (1 << 23);
+  const float d = (float)low * kTwoPi2m32;         // (float)low is exact
+  const float d2 = d * d;
+  const float sd = d - d * (d2 * kSixth);
+  const float cd = 1.0f - d2 * 0.5f;
+  const float S = tab[kTabSin + k], C = tab[kTabCos + k];
+  const float sn = S * cd + C * sd;
+  const float cs = C * cd - S * sd;
   g_re = rad * cs;
   g_im = rad * sn;
+}
+
+// the pair of the plan precision (the binary64 sequence needs no table)
+__device__ __forceinline__ void normal_pair(uint32_t a, uint32_t b, double& g_re, double& g_im, const float*) {
+  box_muller(a, b, g_re, g_im);
+}
+__device__ __forceinline__ void normal_pair(uint32_t a, uint32_t b, float& g_re, float& g_im,
+                                            const float* __restrict__ tab) {
+  box_muller_f32(a, b, g_re, g_im, tab);
 }
 
 // Words (a, b) of mode (ix, iy, iz).
@@ -203,9 +200,9 @@ __device__ __forceinline__ uint2 mode_words(uint32_t k0, uint32_t k1, int ix, in
 // A generic mode from its words: weight x (g_re, g_im), the pair from the transform of
 // the working precision T and the product formed in T.
 template <typename T>
-__device__ __forceinline__ cpx<T> weighted(T w, uint32_t a, uint32_t b) {
+__device__ __forceinline__ cpx<T> weighted(T w, uint32_t a, uint32_t b, const float* __restrict__ tab) {
   T gr, gi;
-  box_muller(a, b, gr, gi);
+  normal_pair(a, b, gr, gi, tab);
   return {w * gr, w * gi};
 }
 
@@ -220,7 +217,8 @@ __device__ __forceinline__ int freq2(int i, int N) {
 // wh: sqrt(P_box/2) per |f|^2; wself[c]: sqrt(P_box) at |f|^2 = c (N/2)^2.
 template <typename T>
 __device__ __forceinline__ cpx<T> mode_value(int N, int ix, int iy, int iz, uint32_t k0, uint32_t k1,
-                                             const T* __restrict__ wh, const T* __restrict__ wself) {
+                                             const T* __restrict__ wh, const T* __restrict__ wself,
+                                             const float* __restrict__ tab) {
   const int M = N / 2;
   const int m = freq2(ix, N) + freq2(iy, N) + iz * iz;
   int sx = ix, sy = iy;  // mode whose words are drawn
@@ -239,7 +237,7 @@ __device__ __forceinline__ cpx<T> mode_value(int N, int ix, int iy, int iz, uint
   }
   const uint2 w = mode_words(k0, k1, sx, sy, iz);
   T gr, gi;
-  box_muller(w.x, w.y, gr, gi);
+  normal_pair(w.x, w.y, gr, gi, tab);
   if (self) {
     const int c = (ix == M) + (iy == M) + (iz == M);
     return {wself[c] * gr, T(0)};

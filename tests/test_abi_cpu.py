@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2507_15703_amd import cmbx
@@ -83,3 +84,18 @@ def test_valid_plan_without_device_reports_ehip(L):
     rc, h = _plan(64, 1.0, cmbx.F32, 1)
     assert rc == cmbx.EHIP and h is None
     assert "device" in cmbx.last_error()
+
+
+def test_noise_tables_match_oracle(L):
+    """The library's binary32 Box-Muller tables (host-generated, no device) equal the
+    oracle's entry for entry."""
+    import ctypes
+
+    from oracle import normal
+    buf = (ctypes.c_float * 768)()
+    assert L.cmbx_noise_tables(buf, 768) == 768
+    got = np.frombuffer(buf, dtype=np.float32)
+    ref = np.concatenate([normal.LN_TAB_F, normal.INV_TAB_F, normal.SIN_TAB_F, normal.COS_TAB_F])
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    assert L.cmbx_noise_tables(buf, 100) == cmbx.EINVAL
+    assert L.cmbx_noise_tables(None, 768) == cmbx.EINVAL

@@ -195,6 +195,38 @@ def test_errors_on_device(cmbx):
     p.close()
 
 
+def test_fault_injection_leaves_library_usable(cmbx, monkeypatch):
+    """Failures forced from the host (CMBX_FAULT) return their codes and leave nothing
+    behind: the next plan, ensemble and launch work and give the plain path's maps."""
+    monkeypatch.setenv("CMBX_FAULT", "alloc")
+    with pytest.raises(cmbx.CmbxError) as e:
+        cmbx.Plan(32, 1.0, "f32")
+    assert e.value.code == cmbx.ENOMEM
+    monkeypatch.delenv("CMBX_FAULT")
+    p, _ = _plan(cmbx, 32, 1.0, "f32", interp="tricubic")
+    dirs = torch.tensor(workloads.cap_directions(20.0, 16, 64), device="cuda")
+    out = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
+    job = dict(plan=p, seed=9, r=0.45, dirs=dirs, out=out)
+    monkeypatch.setenv("CMBX_FAULT", "capture")
+    with pytest.raises(cmbx.CmbxError) as e:
+        cmbx.Ensemble([job], mode="chained")
+    assert e.value.code == cmbx.EHIP
+    monkeypatch.delenv("CMBX_FAULT")
+    ens = cmbx.Ensemble([job], mode="chained")
+    monkeypatch.setenv("CMBX_FAULT", "launch")
+    with pytest.raises(cmbx.CmbxError) as e:
+        ens.launch()
+    assert e.value.code == cmbx.EHIP
+    monkeypatch.delenv("CMBX_FAULT")
+    out.fill_(float("nan"))
+    ens.launch()
+    torch.cuda.synchronize()
+    ref = p.simulate_patch(9, 0.45, dirs).cpu().numpy()
+    assert _rel(out.cpu().numpy()[0], ref[0]) <= 1e-6
+    ens.close()
+    p.close()
+
+
 # ------------------------------------------------------------------ ensemble (graph)
 @pytest.mark.parametrize("mode", ["chained", "pipelined", "auto", "chained-2-lanes"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])

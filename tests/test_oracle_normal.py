@@ -127,3 +127,31 @@ def test_f32_pair_close_to_f64_pair_and_normal():
         assert np.max(np.abs(x32 - x64)) < 1e-3
         assert np.percentile(np.abs(x32 - x64), 99.99) < 2e-6
         assert scipy.stats.kstest(x32.astype(np.float64), "norm").pvalue > 1e-4
+
+
+def test_f32_tables():
+    # each entry is its defining value rounded once to binary32: the identities below hold
+    # to the rounding of the entries, and the symmetries of sin and cos exactly
+    j = np.arange(128)
+    c = 1.0 + j / 128.0
+    arg = np.where(j >= normal.FOLD_J, c / 2.0, c)
+    ln = normal.LN_TAB_F.astype(np.float64)
+    assert np.all(np.abs(np.exp(ln) - arg) <= 2 * 2.0**-24 * arg)
+    assert np.all(np.abs(normal.INV_TAB_F.astype(np.float64) * c - 1.0) <= 2.0**-24)
+    S, C = normal.SIN_TAB_F.astype(np.float64), normal.COS_TAB_F.astype(np.float64)
+    assert np.all(np.abs(S * S + C * C - 1.0) <= 2 * 2.0**-24)
+    assert np.array_equal(normal.SIN_TAB_F[:64], normal.COS_TAB_F[63::-1])   # sin x = cos(pi/2 - x)
+    assert np.array_equal(normal.SIN_TAB_F[128:], -normal.SIN_TAB_F[:128])   # sin(x + pi) = -sin x
+    assert np.array_equal(normal.COS_TAB_F[128:], -normal.COS_TAB_F[:128])
+    # fold entries are negative, the others non-negative: ln(c_j / 2) < 0 <= ln c_j
+    assert np.all(ln[j >= normal.FOLD_J] < 0) and np.all(ln[j < normal.FOLD_J] >= 0) and ln[0] == 0.0
+
+
+def test_f32_log_sign_near_one():
+    # u1 = 1 gives exactly 0 (a zero radius); every u1 < 1 gives ln u1 < 0, also across the
+    # fold entries next to u1 = 1
+    a = np.arange(2**32 - 2**18, 2**32, dtype=np.uint64)
+    got = normal.canonical_log_u1_f32(a)
+    assert got[-1] == 0.0 and np.all(got[:-1] < 0)
+    g_re, g_im = normal.box_muller_f32(a[-1:], a[:1])
+    assert g_re[0] == 0.0 and g_im[0] == 0.0
