@@ -619,7 +619,7 @@ int launch_lanes(cmbx_ensemble* en, hipStream_t s) {
   return CMBX_OK;
 }
 
-// Average milliseconds of an ensemble's launch over three launches after two warm-ups
+// Average milliseconds of an ensemble's launch over eight launches after two warm-ups
 // (-1 on error).
 double time_ensemble(cmbx_ensemble* en) {
   hipStream_t s = nullptr;
@@ -630,11 +630,11 @@ double time_ensemble(cmbx_ensemble* en) {
     int rc = CMBX_OK;
     for (int i = 0; rc == CMBX_OK && i < 2; ++i) rc = launch_lanes(en, s);
     hipError_t e = rc == CMBX_OK ? hipEventRecord(e0, s) : hipErrorUnknown;
-    for (int i = 0; e == hipSuccess && rc == CMBX_OK && i < 3; ++i) rc = launch_lanes(en, s);
+    for (int i = 0; e == hipSuccess && rc == CMBX_OK && i < 8; ++i) rc = launch_lanes(en, s);
     if (e == hipSuccess && rc == CMBX_OK) e = hipEventRecord(e1, s);
     if (e == hipSuccess && rc == CMBX_OK) e = hipEventSynchronize(e1);
     float t = 0.f;
-    if (e == hipSuccess && rc == CMBX_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / 3.0;
+    if (e == hipSuccess && rc == CMBX_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / 8.0;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
