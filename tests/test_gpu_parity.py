@@ -67,6 +67,35 @@ def test_noise_bit_exact_256(cmbx):
     p.close()
 
 
+def test_largest_box_1024_sampled(cmbx):
+    """The largest compiled box, 1024^3 FP32 (the precision-study size): the generic modes
+    of sampled x-planes are bit-identical to the oracle's, and the FP32 map of a 40-degree
+    cap agrees with the FP64 plan's to the FP32 bar (both plans are checked against the
+    oracle at smaller sizes; the full 1024^3 oracle comparison is the precision study)."""
+    from oracle import spectrum as ospec
+    N, L, seed = 1024, 1.0, 11
+    k, pk = workloads.powerlaw_cutoff_table(N, L, kc_modes=N // 4)
+    p32, _ = _plan(cmbx, N, L, "f32", interp="tricubic", table=(k, pk))
+    half, _ = ospec.weight_tables(N, L, k, pk)
+    grid = p32.debug_noise(seed)
+    for ix in (0, 1, 511, 512, 1023):
+        g_re, g_im = onoise.unit_normals(N, seed, np.array([ix]), np.float32)
+        w = half[ospec.mode_m(N, np.array([ix]))].astype(np.float32)
+        ref = np.empty((N, N // 2 + 1), dtype=np.complex64)
+        ref.real, ref.imag = (w * g_re)[0], (w * g_im)[0]
+        got = grid[ix].cpu().numpy()
+        # generic modes (the planes iz = 0 and N/2 follow the Hermitian rule, checked at smaller N)
+        assert np.array_equal(_bits(got[:, 1:N // 2]), _bits(ref[:, 1:N // 2])), ix
+    del grid
+    dirs = torch.tensor(workloads.cap_directions(40.0, 1024, 1024), device="cuda")
+    m32 = p32.simulate_patch(seed, 0.45, dirs).cpu().numpy()[0]
+    p32.close()
+    p64, _ = _plan(cmbx, N, L, "f64", interp="tricubic", table=(k, pk))
+    m64 = p64.simulate_patch(seed, 0.45, dirs).cpu().numpy()[0]
+    p64.close()
+    assert np.all(np.isfinite(m32)) and _rel(m32, m64) <= 1e-5
+
+
 # ------------------------------------------------------------------ field
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("N", [8, 12, 16, 24, 32, 48, 64, 96, 128])
