@@ -63,7 +63,9 @@ template <typename T>
 constexpr int tab_cpx() { return sizeof(T) == 4 ? bmf::kTabSize / 2 : 0; }
 
 // ------------------------------------------------------------------ launch shapes
-constexpr int clamp_nt(int work) { return work >= 2048 ? 256 : work >= 1024 ? 128 : 64; }
+// threads per workgroup for `work` points in LDS: 512 from 4096 points (two butterflies
+// per thread and stage or fewer), down to one wave for small tiles
+constexpr int clamp_nt(int work) { return work >= 4096 ? 512 : work >= 2048 ? 256 : work >= 1024 ? 128 : 64; }
 
 template <typename T, int N, int TZ>
 struct XYShape {
