@@ -167,7 +167,7 @@ def main():
     ach_ops = modes * ops_per_mode / (ms[0] * 1e-3)
     # HBM bytes per launch of this kernel from rocprofv3 FETCH_SIZE (x2.0 calibration against
     # a plain copy) + WRITE_SIZE, by tile width (counters of the current kernel code)
-    traffic_by_tile = {8: (6212.06 * 2.0 + 524288.0) * 1024, 16: (6067.38 * 2.0 + 524288.0) * 1024}
+    traffic_by_tile = {8: (5171.06 * 2.0 + 524288.0) * 1024, 16: (5049.06 * 2.0 + 524288.0) * 1024}
     tile_x = jobs[0]["tuned"]["tile_x"]
     roofline = {"kernel": names[0], "bound": "alu", "achieved": round(ach_ops / 1e12, 2),
                 "peak": round(alu_peak / 1e12, 2), "unit": "Tops/s", "frac": round(ach_ops / alu_peak, 4),
