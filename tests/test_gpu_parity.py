@@ -338,3 +338,32 @@ def test_ensemble_512_sampled(cmbx):
     ens.close()
     for j in jobs:
         j["plan"].close()
+
+
+def test_ensemble_mixed_sizes_full_workload(cmbx):
+    """The mixed-size ensemble workload (16 x 128^3 + 8 x 256^3 + 4 x 384^3 + 4 x 512^3 FP32,
+    caps of 10-40 degrees, tricubic) in one auto-mode ensemble gives every job's plain-path
+    map (sampled pixels, to rounding) on two replays."""
+    jobs = []
+    for j in workloads.ensemble_jobs():
+        N = j["N"]
+        k, pk = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N // 4)
+        p, _ = _plan(cmbx, N, 1.0, "f32", interp="tricubic", table=(k, pk * j["amp"]))
+        dirs = torch.tensor(workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"]), device="cuda")
+        out = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
+        jobs.append(dict(plan=p, seed=j["seed"], r=0.45, dirs=dirs, out=out))
+    ens = cmbx.Ensemble([dict(j) for j in jobs], mode="auto")
+    assert len(ens.modes) == 4
+    refs = [j["plan"].simulate_patch(j["seed"], j["r"], j["dirs"]).cpu().numpy()[0] for j in jobs]
+    for rep in range(2):
+        for j in jobs:
+            j["out"].fill_(float("nan"))
+        ens.launch()
+        torch.cuda.synchronize()
+        for i, (j, ref) in enumerate(zip(jobs, refs)):
+            got = j["out"].cpu().numpy()[0]
+            idx = np.random.default_rng(i).choice(got.size, min(got.size, 8192), replace=False)
+            assert np.all(np.isfinite(got)) and _rel(got[idx], ref[idx]) <= 1e-6, (rep, i, j["plan"].N)
+    ens.close()
+    for j in jobs:
+        j["plan"].close()
