@@ -4,7 +4,10 @@
 Workload: the 512^3 part of the mixed-size ensemble -- four FP32 boxes of side L = 1,
 each with its own seed, shell radius r = 0.45 L, a polar cap of half-angle drawn
 uniformly in [10, 40] deg (n_ring = round(25.6 theta) rings x 1024 or 2048 pixels) and
-tricubic sampling. One step = one pass of the whole hot path (noise + inverse 3-D FFT +
+tricubic sampling. Each box's P(k) is the programme's solution (host FP64 inversion) for
+the synthetic C_l family scaled by the job's amplitude, on the job's cap; it ends at the
+box's band limit pi N / L, so the modes beyond it (about half) have zero weight and are
+not drawn. One step = one pass of the whole hot path (noise + inverse 3-D FFT +
 sphere gather) over the four boxes, i.e. four maps. The batched path replays the four
 independent kernel chains as a HIP-graph ensemble (one graph, or two graphs on two
 streams when that is faster); the plain path runs the same jobs one after another
@@ -28,19 +31,48 @@ METRIC = "maps/s batched FP32 vs plain at 512³ box+cap sample, px err≤1e-5; H
 HBM_PEAK_GBS = 8000.0
 
 
+def job_spectrum(spectrum, workloads, N, L, r, theta_deg, amp):
+    """The job's P_inf: the programme's solution (Sec. II B) for the synthetic C_l scaled by
+    the job's amplitude, on its own cap; beam 1 / l_d with l_d = 0.6 l_max."""
+    lmax = workloads.lmax_for(N, L, r)
+    cl = amp * workloads.synthetic_cl(lmax)
+    k, p, _ = spectrum.invert(cl, r, math.radians(theta_deg), 1.0 / (0.6 * lmax), N=N, L=L)
+    return k, p
+
+
+def active_modes(N, L, k, p):
+    """Half-grid modes (ix, iy, iz <= N/2) whose weight P_box(|f|) is not zero: the modes the
+    noise pass draws (P_inf linear between table nodes, zero beyond the last one)."""
+    import numpy as np
+    f = np.arange(N)
+    f2 = np.minimum(f, N - f) ** 2
+    hist_xy = np.bincount((f2[:, None] + f2[None, :]).ravel())
+    mmax = 3 * (N // 2) ** 2
+    mult = np.zeros(mmax + 1, dtype=np.int64)
+    for fz in range(N // 2 + 1):
+        mult[fz * fz: fz * fz + hist_xy.size] += hist_xy
+    km = (2 * math.pi / L) * np.sqrt(np.arange(mmax + 1, dtype=np.float64))
+    pm = np.interp(km, k, p, left=0.0, right=0.0)
+    pm[km > k[-1]] = 0.0
+    pm[0] = 0.0
+    return int(mult[pm > 0].sum())
+
+
 def build_jobs(torch, cmbx, workloads, n_boxes):
+    from paper_2507_15703_amd import spectrum
     jobs = [j for j in workloads.ensemble_jobs() if j["N"] == 512][:n_boxes]
     out = []
     for j in jobs:
         N, L = j["N"], 1.0
         plan = cmbx.Plan(N, L, "f32", batch=1, interp="tricubic")
-        k, p = workloads.powerlaw_cutoff_table(N, L, kc_modes=N / 4)
-        plan.spectrum_table(k, p * j["amp"])
+        k, p = job_spectrum(spectrum, workloads, N, L, j["r_over_L"] * L, j["theta_deg"], j["amp"])
+        plan.spectrum_table(k, p)
         tuned = plan.autotune(reps=5)
         dirs = torch.tensor(workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"]), device="cuda")
         res = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
         out.append(dict(plan=plan, seed=j["seed"], r=j["r_over_L"] * L, dirs=dirs, out=res,
-                        theta=j["theta_deg"], n_pix=int(dirs.shape[0]), tuned=tuned))
+                        theta=j["theta_deg"], n_pix=int(dirs.shape[0]), tuned=tuned,
+                        active=active_modes(N, L, k, p), k=k, p=p))
     return out
 
 
@@ -60,7 +92,7 @@ def cpu_baseline(jobs_meta, frac_planes=16):
 
     j = jobs_meta[0]
     N, L = 512, 1.0
-    k, p = workloads.powerlaw_cutoff_table(N, L, kc_modes=N / 4)
+    k, p = j["k"], j["p"]
     workers = len(os.sched_getaffinity(0))
     nplanes = N // frac_planes
     t0 = time.perf_counter()
@@ -156,22 +188,24 @@ def main():
     kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
                for n, t, b in zip(names, ms, kbytes)}
     # The dominant kernel is the noise + x pass, bound by the vector ALU: its algorithmic
-    # work per mode is the binary32 Box-Muller sequence (49 floating-point operations with
-    # its four conversions) + the two weight products + half a Philox4x32-10 call (10 rounds
-    # x (2 wide multiplies + 4 xor) / 2 = 30 integer ops) + the x transform (5 log2 N flops
-    # per point); peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s for
-    # unfused, unpacked operations.
-    modes = N**3 // 2
-    ops_per_mode = 49 + 2 + 30 + 5 * math.log2(N)
+    # work is, per drawn mode (weight not zero), the binary32 Box-Muller sequence (49
+    # floating-point operations with its four conversions) + the two weight products +
+    # half a Philox4x32-10 call (10 rounds x (2 wide multiplies + 4 xor) / 2 = 30 integer
+    # ops), and per point of the packed N x N x N/2 grid the x transform (5 log2 N flops);
+    # peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s for unfused,
+    # unpacked operations.
+    drawn = j0["active"]
+    ops_launch = drawn * (49 + 2 + 30) + (N**3 // 2) * 5 * math.log2(N)
     alu_peak = 256 * 4 * 16 * 2.4e9
-    ach_ops = modes * ops_per_mode / (ms[0] * 1e-3)
+    ach_ops = ops_launch / (ms[0] * 1e-3)
     # HBM bytes per launch of this kernel from rocprofv3 FETCH_SIZE (x2.0 calibration against
     # a plain copy) + WRITE_SIZE, by tile width (counters of the current kernel code)
-    traffic_by_tile = {8: (5171.06 * 2.0 + 524288.0) * 1024, 16: (5049.06 * 2.0 + 524288.0) * 1024}
+    traffic_by_tile = {8: (3588.88 * 2.0 + 524288.0) * 1024, 16: (2148.06 * 2.0 + 524288.0) * 1024}
     tile_x = jobs[0]["tuned"]["tile_x"]
     roofline = {"kernel": names[0], "bound": "alu", "achieved": round(ach_ops / 1e12, 2),
                 "peak": round(alu_peak / 1e12, 2), "unit": "Tops/s", "frac": round(ach_ops / alu_peak, 4),
-                "traffic": traffic_by_tile.get(tile_x), "ops_per_launch": int(modes * ops_per_mode)}
+                "traffic": traffic_by_tile.get(tile_x), "ops_per_launch": int(ops_launch),
+                "drawn_modes": drawn, "half_grid_modes": N * N * (N // 2 + 1)}
     # the two transform passes are HBM-bound: fraction of the 8 TB/s peak
     for i in (1, 2):
         kernels[names[i]]["hbm_frac"] = round(kbytes[i] / (ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)

@@ -15,6 +15,8 @@ canonical stream (``philox.mode_words`` then ``normal.box_muller``):
                            conjugate pair; the one with the smaller ix N + iy is drawn as
                            above and the other is its complex conjugate;
 * self-conjugate modes     (ix, iy in {0, N/2} on those planes): T = full[m] g_re, real.
+* a mode whose weight is zero (P_box = 0, e.g. beyond the spectrum's k_max) is exactly
+  +0 (before the conjugation of the planes' partners), whatever its normal pair.
 
 In single precision the normal pair comes from the binary32 transform
 (``normal.box_muller_f32``), the weight is rounded to FP32 and the product is an FP32
@@ -64,8 +66,9 @@ def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32, workers=None)
     try:
         for (_, _, x0, x1, _), (g_re, g_im) in zip(jobs, normals):
             w = half[spectrum.mode_m(N, np.arange(x0, x1))]
-            out[x0:x1].real = w * g_re
-            out[x0:x1].imag = w * g_im
+            zero = rdt.type(0)
+            out[x0:x1].real = np.where(w == 0, zero, w * g_re)
+            out[x0:x1].imag = np.where(w == 0, zero, w * g_im)
     finally:
         if ex is not None:
             ex.shutdown()
@@ -88,7 +91,7 @@ def _hermitian_planes(out, N, seed, full, rdt):
         a, b = philox.mode_words(seed, sx, sy, np.full(sx.shape, iz))
         g_re, _ = _pair(a, b, rdt)
         m = (np.minimum(sx, N - sx) ** 2 + np.minimum(sy, N - sy) ** 2 + iz * iz).astype(np.int64)
-        new[selfc] = full[m] * g_re
+        new[selfc] = np.where(full[m] == 0, rdt.type(0), full[m] * g_re)
         out[:, :, iz] = new
 
 

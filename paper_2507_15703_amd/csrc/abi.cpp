@@ -33,11 +33,11 @@ struct cmbx_plan {
   hipStream_t stream = nullptr;
   void* field = nullptr;   // batch x N^3 reals
   void* tw = nullptr;      // N complex roots of unity
-  void* wtab = nullptr;    // 3 (N/2)^2 + 1 half weights, then 4 full weights
+  void* wtab = nullptr;    // 3 (N/2)^2 + 1 half weights, 4 full weights, the last nonzero |f|^2
   bool has_spectrum = false;
   size_t real_size() const { return dtype == CMBX_F32 ? 4 : 8; }
   size_t field_bytes() const { return (size_t)N * N * N * real_size(); }
-  int64_t wtab_len() const { return 3ll * (N / 2) * (N / 2) + 1 + 4; }
+  int64_t wtab_len() const { return 3ll * (N / 2) * (N / 2) + 1 + 4 + 1; }
 };
 
 struct cmbx_ensemble {
@@ -119,12 +119,13 @@ double interp_p(const double* kt, const double* pt, int64_t n, double k) {
 template <typename T>
 void fill_weights(const cmbx_plan* p, const double* kt, const double* pt, int64_t n, std::vector<T>& out) {
   // P_box = P_inf (2 pi / L)^3 (eq. finalpbox, cubic box); half = sqrt(P_box / 2),
-  // full = sqrt(P_box) at |f|^2 = c (N/2)^2, c = 0..3; P_box(0) = 0.
+  // full = sqrt(P_box) at |f|^2 = c (N/2)^2, c = 0..3; P_box(0) = 0. The last entry is the
+  // largest |f|^2 whose half weight is not zero: the noise pass draws no mode beyond it.
   const int M = p->N / 2;
   const int64_t mmax = 3ll * M * M;
   const double c = 6.283185307179586 / p->L;
   const double c3 = c * c * c;
-  out.assign(mmax + 1 + 4, T(0));
+  out.assign(mmax + 1 + 4 + 1, T(0));
   std::vector<double> pbox(mmax + 1);
   for (int64_t m = 0; m <= mmax; ++m) {
     const double k = c * std::sqrt((double)m);
@@ -133,6 +134,9 @@ void fill_weights(const cmbx_plan* p, const double* kt, const double* pt, int64_
     out[m] = (T)std::sqrt(pbox[m] * 0.5);
   }
   for (int cc = 0; cc < 4; ++cc) out[mmax + 1 + cc] = (T)std::sqrt(pbox[(int64_t)cc * M * M]);
+  int64_t hi = mmax;
+  while (hi > 0 && out[hi] == T(0)) --hi;
+  out[mmax + 5] = (T)hi;  // <= 3 * 512^2 < 2^24: exact in binary32
 }
 
 int check_plan(const cmbx_plan* p) {

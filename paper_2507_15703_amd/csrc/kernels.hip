@@ -98,6 +98,8 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   const int tid = threadIdx.x;
   const int zc0 = zt * TZ;
   const T* wself = wtab + 3 * M * M + 1;
+  // largest |f|^2 whose weight is not zero (stored after the table, exact in T)
+  const int m_hi = (int)wtab[3 * M * M + 5];
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   float* tab = nullptr;
   if constexpr (tab_cpx<T>() > 0) {
@@ -122,9 +124,14 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
     const int ix = s / PAIRS;
     const int zc = zc0 + 2 * pr;
     if (zc == 0) continue;
-    const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
     const int m0 = freq2(ix, N) + fy2 + zc * zc;
+    if (m0 > m_hi) {  // both modes beyond the spectrum's support: +0, no draw, no load
+      tile[ix * TZ + 2 * pr] = {T(0), T(0)};
+      tile[ix * TZ + 2 * pr + 1] = {T(0), T(0)};
+      continue;
+    }
     const int m1 = m0 + 2 * zc + 1;
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
     tile[ix * TZ + 2 * pr] = weighted<T>(wtab[m0], w.x, w.y, tab);
     tile[ix * TZ + 2 * pr + 1] = weighted<T>(wtab[m1], w.z, w.w, tab);
   }

@@ -199,11 +199,13 @@ __device__ __forceinline__ uint2 mode_words(uint32_t k0, uint32_t k1, int ix, in
 
 // A generic mode from its words: weight x (g_re, g_im), the pair from the transform of
 // the working precision T and the product formed in T.
+// A mode of zero weight (P_box = 0) is exactly +0 whatever its normal pair.
 template <typename T>
 __device__ __forceinline__ cpx<T> weighted(T w, uint32_t a, uint32_t b, const float* __restrict__ tab) {
   T gr, gi;
-  normal_pair(a, b, gr, gi, tab);
-  return {w * gr, w * gi};
+  normal_pair(a, b, gr, gi, tab);  // drawn either way: the pair does not wait for the weight
+  const bool zero = w == T(0);
+  return {zero ? T(0) : w * gr, zero ? T(0) : w * gi};
 }
 
 __device__ __forceinline__ int freq2(int i, int N) {
@@ -235,14 +237,15 @@ __device__ __forceinline__ cpx<T> mode_value(int N, int ix, int iy, int iz, uint
       cj = true;
     }
   }
+  const T wv = self ? wself[(ix == M) + (iy == M) + (iz == M)] : wh[m];
+  if (wv == T(0)) {  // zero weight: +0, conjugated like any other value
+    const cpx<T> z = {T(0), T(0)};
+    return cj ? conj(z) : z;
+  }
   const uint2 w = mode_words(k0, k1, sx, sy, iz);
   T gr, gi;
   normal_pair(w.x, w.y, gr, gi, tab);
-  if (self) {
-    const int c = (ix == M) + (iy == M) + (iz == M);
-    return {wself[c] * gr, T(0)};
-  }
-  const T wv = wh[m];
+  if (self) return {wv * gr, T(0)};
   const cpx<T> v = {wv * gr, wv * gi};
   return cj ? conj(v) : v;
 }

@@ -1,7 +1,9 @@
 """A short, fixed launch sequence for rocprofv3 (kernel trace and counter passes).
 
 Runs, on one 512^3 FP32 plan (tricubic, r = 0.45 L, 30 deg cap of 768 x 2048 pixels,
-autotuned tile shapes unless given): one warm-up realisation, then ``--reps`` launches of each kernel of the hot path through
+spectrum from the programme for the synthetic C_l on that cap as in the benchmark, or the
+power-law table with ``--spectrum powerlaw``; autotuned tile shapes unless given): one
+warm-up realisation, then ``--reps`` launches of each kernel of the hot path through
 cmbx_time_passes, and a device-to-device copy of exactly 512 MiB (torch) whose counter
 readings calibrate the HBM byte counters. Usage:
 
@@ -10,6 +12,7 @@ readings calibrate the HBM byte counters. Usage:
 """
 import argparse
 import json
+import math
 import os
 import sys
 
@@ -24,15 +27,20 @@ def main():
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--tile-xy", type=int, default=0)
     ap.add_argument("--lines-z", type=int, default=0)
+    ap.add_argument("--spectrum", default="lp", choices=["lp", "powerlaw"])
     args = ap.parse_args()
 
     import torch
 
-    from paper_2507_15703_amd import cmbx, workloads
+    from paper_2507_15703_amd import cmbx, spectrum, workloads
 
     N = args.N
     plan = cmbx.Plan(N, 1.0, args.dtype, batch=1, interp="tricubic")
-    k, p = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N / 4)
+    if args.spectrum == "lp":
+        lmax = workloads.lmax_for(N, 1.0, 0.45)
+        k, p, _ = spectrum.invert(workloads.synthetic_cl(lmax), 0.45, math.radians(30.0), 1.0 / (0.6 * lmax), N=N)
+    else:
+        k, p = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N / 4)
     plan.spectrum_table(k, p)
     if args.tile_xy or args.lines_z:
         plan.set_tiles(args.tile_xy, args.lines_z)

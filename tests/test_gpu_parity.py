@@ -58,6 +58,24 @@ def test_noise_bit_exact(cmbx, N, dt):
     p.close()
 
 
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N", [16, 48, 64])
+def test_noise_bit_exact_zero_weights(cmbx, N, dt):
+    """A spectrum that ends at the box's isotropic band limit pi N / L (as the programme's
+    solutions do): the modes beyond it have zero weight and are exactly +0, the rest are
+    the oracle's bits."""
+    L = 1.0
+    k, pk = workloads.powerlaw_cutoff_table(N, L, kc_modes=N // 4)
+    keep = k <= np.pi * N / L
+    p, _ = _plan(cmbx, N, L, dt, table=(k[keep], pk[keep]))
+    for seed in (3, 2**40 + 5):
+        gpu = p.debug_noise(seed).cpu().numpy()
+        ref = onoise.halfgrid(N, L, seed, k[keep], pk[keep], dtype=NPDT[dt])
+        assert np.array_equal(_bits(gpu), _bits(ref)), (N, dt, seed)
+        assert np.count_nonzero(_bits(ref)) < 0.75 * _bits(ref).size   # the corners are zero
+    p.close()
+
+
 def test_noise_bit_exact_256(cmbx):
     N, L = 256, 1.0
     p, (k, pk) = _plan(cmbx, N, L, "f32")

@@ -101,3 +101,21 @@ def test_field_variance_is_lattice_xi0():
     xi0 = spectrum.lattice_xi0(N, L, k, p)
     vals = [np.mean(field.field(noise.halfgrid(N, L, s, k, p)) ** 2) for s in range(40)]
     assert np.mean(vals) == pytest.approx(xi0, rel=4 * np.std(vals) / np.sqrt(40) / xi0)
+
+
+def test_zero_weight_modes_are_exactly_zero():
+    # a table that ends below the largest lattice |k|: every mode beyond it is +0 (its
+    # conjugate partner on the planes iz = 0, N/2 is 0 - 0i), every mode inside is drawn
+    N, L = 16, 1.0
+    k = np.linspace(0.0, 2 * np.pi * 6, 40)
+    p = np.exp(-k / 30.0)
+    h = noise.halfgrid(N, L, 7, k, p, dtype=np.float32)
+    m = spectrum.mode_m(N)
+    kk = 2 * np.pi / L * np.sqrt(m)
+    outside = kk > k[-1]
+    assert np.all(h.real[outside] == 0) and np.all(h.imag[outside] == 0)
+    gen = outside.copy()
+    gen[:, :, 0] = gen[:, :, N // 2] = False                       # generic modes: +0 exactly
+    assert not np.any(np.signbit(h.real[gen])) and not np.any(np.signbit(h.imag[gen]))
+    inside = (~outside) & (m > 0)
+    assert np.all(np.abs(h[inside]) > 0)
