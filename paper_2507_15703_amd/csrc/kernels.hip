@@ -100,6 +100,14 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   const T* wself = wtab + 3 * M * M + 1;
   // largest |f|^2 whose weight is not zero (stored after the table, exact in T)
   const int m_hi = (int)wtab[3 * M * M + 5];
+  const int fy2 = freq2(iy, N);
+  if (fy2 + zc0 * zc0 > m_hi) {
+    // every mode of the tile (the packed plane iz = N/2 included) is beyond the spectrum's
+    // support: its transform is zero
+    GlobalColIO<T> zero_out{buf + (size_t)iy * M + zc0, (size_t)N * M};
+    for (int i = tid; i < N * TZ; i += NT) zero_out(i % TZ, i / TZ, cpx<T>{T(0), T(0)});
+    return;
+  }
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   float* tab = nullptr;
   if constexpr (tab_cpx<T>() > 0) {
@@ -107,7 +115,6 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
     for (int i = tid; i < bmf::kTabSize; i += NT) tab[i] = g_bm_tab[i];
     __syncthreads();
   }
-  const int fy2 = freq2(iy, N);
   if (zc0 == 0) {
     // column 0 packs the Hermitian planes iz = 0 and N/2; column 1 is iz = 1
     for (int ix = tid; ix < N; ix += NT) {
