@@ -748,6 +748,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
         if (iy >= 0 && iy < n) {
           cnt[1] = (int64_t)(M / ty) * N;
           a.by = gr.bufs[iy % nbuf];
+          a.wtab_y = gr.items[iy].plan->wtab;
         }
         if (iz >= 0 && iz < n) {
           cnt[2] = (int64_t)N * N / lz;

@@ -151,16 +151,32 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
 // ------------------------------------------------------------------ pass 2: y
 // Workgroup = (z tile zt, one ix): N rows (iy) of TZ columns, read, transformed along y,
 // written back in place.
+// After pass x the element (ix, iy, column zc) is zero wherever fy^2 + zc^2 exceeds the
+// spectrum's last nonzero |f|^2 (every mode of that x-line had zero weight); the reader
+// returns those zeros without loading them.
+template <typename T, int N>
+struct SupportColIO {
+  GlobalColIO<T> g;
+  int zc0, m_hi;
+  __device__ __forceinline__ cpx<T> operator()(int q, int n) const {
+    const int zc = zc0 + q;
+    return freq2(n, N) + zc * zc > m_hi ? cpx<T>{T(0), T(0)} : g(q, n);
+  }
+  __device__ __forceinline__ void done() const { g.done(); }
+};
+
 template <typename T, int N, int TZ, int NT>
 __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __restrict__ buf,
-                                       const cpx<T>* __restrict__ twg) {
+                                       const cpx<T>* __restrict__ twg, const T* __restrict__ wtab) {
   constexpr int M = N / 2;
   cpx<T>* tile = smem;
   cpx<T>* tw = smem + N * TZ;
+  const int m_hi = (int)wtab[3 * M * M + 5];
   for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
   GlobalColIO<T> io{buf + (size_t)ix * N * M + zt * TZ, (size_t)M};
-  fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, io, io);
+  SupportColIO<T, N> first{io, zt * TZ, m_hi};
+  fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, first, io);
 }
 
 // ------------------------------------------------------------------ pass 3: z (c2r)
@@ -193,9 +209,10 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __re
 
 template <typename T, int N, int TZ>
 __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __restrict__ buf,
-                                                                 const cpx<T>* __restrict__ twg) {
+                                                                 const cpx<T>* __restrict__ twg,
+                                                                 const T* __restrict__ wtab) {
   __shared__ cpx<T> smem[N * TZ + N];
-  role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg);
+  role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg, wtab);
 }
 
 template <typename T, int N, int LINES>
@@ -353,6 +370,7 @@ struct PipeArgs {
   const T* wtab_x;     // weights of the item in pass x
   uint32_t k0, k1;     // its seed words
   cpx<T>* by;          // pass y buffer
+  const T* wtab_y;     // weights of the item in pass y (its support bound)
   cpx<T>* bz;          // pass z buffer
   const T* field_g;    // gather input field
   const double* dirs;  // gather directions
@@ -382,7 +400,7 @@ __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict
   if (role == 0) {
     role_x<T, N, TX, kPipeNT>(smem, idx % (M / TX), idx / (M / TX), a.bx, a.wtab_x, a.tw, a.k0, a.k1);
   } else if (role == 1) {
-    role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw);
+    role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw, a.wtab_y);
   } else if (role == 2) {
     role_z<T, N, LZ, kPipeNT>(smem, idx, a.bz, a.tw);
   } else {
@@ -446,7 +464,7 @@ template <typename T, int N, int TZ>
 hipError_t run_y(const FieldArgs& a, hipStream_t s) {
   dim3 grid(N / 2 / TZ, N);
   hipLaunchKernelGGL((k_pass_y<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
-                     (const cpx<T>*)a.tw);
+                     (const cpx<T>*)a.tw, (const T*)a.wtab);
   return hipGetLastError();
 }
 template <typename T, int N, int LINES>
@@ -469,6 +487,7 @@ hipError_t run_pipe(const PipeLaunch& a, hipStream_t s) {
   p.k0 = a.k0;
   p.k1 = a.k1;
   p.by = (cpx<T>*)a.by;
+  p.wtab_y = (const T*)a.wtab_y;
   p.bz = (cpx<T>*)a.bz;
   p.field_g = (const T*)a.field_g;
   p.dirs = a.dirs;

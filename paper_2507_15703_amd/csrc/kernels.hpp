@@ -63,6 +63,7 @@ struct PipeLaunch {
   const void* wtab_x;
   uint32_t k0, k1;
   void* by;
+  const void* wtab_y;
   void* bz;
   const void* field_g;
   const double* dirs;
