@@ -31,18 +31,11 @@ METRIC = "maps/s batched FP32 vs plain at 512³ box+cap sample, px err≤1e-5; H
 HBM_PEAK_GBS = 8000.0
 
 
-def job_spectrum(spectrum, workloads, N, L, r, theta_deg, amp):
-    """The job's P_inf: the programme's solution (Sec. II B) for the synthetic C_l scaled by
-    the job's amplitude, on its own cap; beam 1 / l_d with l_d = 0.6 l_max."""
-    lmax = workloads.lmax_for(N, L, r)
-    cl = amp * workloads.synthetic_cl(lmax)
-    k, p, _ = spectrum.invert(cl, r, math.radians(theta_deg), 1.0 / (0.6 * lmax), N=N, L=L)
-    return k, p
-
-
-def active_modes(N, L, k, p):
-    """Half-grid modes (ix, iy, iz <= N/2) whose weight P_box(|f|) is not zero: the modes the
-    noise pass draws (P_inf linear between table nodes, zero beyond the last one)."""
+def support(N, L, k, p):
+    """(drawn, y_rows): the half-grid modes (ix, iy, iz <= N/2) whose weight P_box(|f|) is
+    not zero -- the modes the noise pass draws (P_inf linear between table nodes, zero
+    beyond the last one) -- and the share of the (iy, packed column) lines that pass y reads
+    (fy^2 + zc^2 up to the last nonzero |f|^2; beyond, pass x leaves zeros)."""
     import numpy as np
     f = np.arange(N)
     f2 = np.minimum(f, N - f) ** 2
@@ -55,7 +48,10 @@ def active_modes(N, L, k, p):
     pm = np.interp(km, k, p, left=0.0, right=0.0)
     pm[km > k[-1]] = 0.0
     pm[0] = 0.0
-    return int(mult[pm > 0].sum())
+    m_hi = int(np.nonzero(pm > 0)[0].max()) if np.any(pm > 0) else 0
+    zc = np.arange(N // 2)
+    rows = (f2[:, None] + zc[None, :] ** 2) <= m_hi
+    return int(mult[pm > 0].sum()), float(rows.mean())
 
 
 def build_jobs(torch, cmbx, workloads, n_boxes):
@@ -65,14 +61,14 @@ def build_jobs(torch, cmbx, workloads, n_boxes):
     for j in jobs:
         N, L = j["N"], 1.0
         plan = cmbx.Plan(N, L, "f32", batch=1, interp="tricubic")
-        k, p = job_spectrum(spectrum, workloads, N, L, j["r_over_L"] * L, j["theta_deg"], j["amp"])
+        k, p = spectrum.synthetic_job_spectrum(N, L, j["r_over_L"] * L, j["theta_deg"], j["amp"])
         plan.spectrum_table(k, p)
         tuned = plan.autotune(reps=5)
         dirs = torch.tensor(workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"]), device="cuda")
         res = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
         out.append(dict(plan=plan, seed=j["seed"], r=j["r_over_L"] * L, dirs=dirs, out=res,
                         theta=j["theta_deg"], n_pix=int(dirs.shape[0]), tuned=tuned,
-                        active=active_modes(N, L, k, p), k=k, p=p))
+                        support=support(N, L, k, p), k=k, p=p))
     return out
 
 
@@ -183,7 +179,9 @@ def main():
     ms = j0["plan"].time_passes(j0["seed"], j0["r"], j0["dirs"], j0["out"], reps=args.kernel_reps)
     N = 512
     field_bytes = 4 * N**3
-    kbytes = [field_bytes, 2 * field_bytes, 2 * field_bytes, 28 * j0["n_pix"]]
+    drawn, y_rows = j0["support"]
+    # pass y reads only the lines pass x can have made nonzero (and writes all of them)
+    kbytes = [field_bytes, int(field_bytes * (1 + y_rows)), 2 * field_bytes, 28 * j0["n_pix"]]
     names = ["pass_x_noise", "pass_y", "pass_z_c2r", "gather_tricubic"]
     kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
                for n, t, b in zip(names, ms, kbytes)}
@@ -194,13 +192,12 @@ def main():
     # ops), and per point of the packed N x N x N/2 grid the x transform (5 log2 N flops);
     # peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s for unfused,
     # unpacked operations.
-    drawn = j0["active"]
     ops_launch = drawn * (49 + 2 + 30) + (N**3 // 2) * 5 * math.log2(N)
     alu_peak = 256 * 4 * 16 * 2.4e9
     ach_ops = ops_launch / (ms[0] * 1e-3)
     # HBM bytes per launch of this kernel from rocprofv3 FETCH_SIZE (x2.0 calibration against
     # a plain copy) + WRITE_SIZE, by tile width (counters of the current kernel code)
-    traffic_by_tile = {8: (3588.88 * 2.0 + 524288.0) * 1024, 16: (2148.06 * 2.0 + 524288.0) * 1024}
+    traffic_by_tile = {8: (3327.69 * 2.0 + 524288.0) * 1024, 16: (2207.31 * 2.0 + 524288.0) * 1024}
     tile_x = jobs[0]["tuned"]["tile_x"]
     roofline = {"kernel": names[0], "bound": "alu", "achieved": round(ach_ops / 1e12, 2),
                 "peak": round(alu_peak / 1e12, 2), "unit": "Tops/s", "frac": round(ach_ops / alu_peak, 4),
@@ -209,7 +206,7 @@ def main():
     # the two transform passes are HBM-bound: fraction of the 8 TB/s peak
     for i in (1, 2):
         kernels[names[i]]["hbm_frac"] = round(kbytes[i] / (ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    map_bytes = 20 * N**3 + sum(28 * j["n_pix"] for j in jobs) / nmaps
+    map_bytes = sum(16 * N**3 + 4 * N**3 * j["support"][1] + 28 * j["n_pix"] for j in jobs) / nmaps
     path_gbs = map_bytes * value / 1e9
 
     result = {

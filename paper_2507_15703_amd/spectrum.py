@@ -104,6 +104,17 @@ def invert(cl, R, theta_max, beam, N=None, L=1.0, k_max=None):
     return pr["k"], x, info
 
 
+def synthetic_job_spectrum(N, L, r, theta_max_deg, amp=1.0):
+    """(k, P_inf) of an ensemble job: the programme's solution for the synthetic C_l family
+    (l_max = floor(0.8 pi r N / L), l_d = 0.6 l_max, beam 1 / l_d) scaled by ``amp``, on a
+    cap of half-angle theta_max_deg, up to the box's band limit pi N / L."""
+    from . import workloads
+    lmax = workloads.lmax_for(N, L, r)
+    cl = amp * workloads.synthetic_cl(lmax)
+    k, p, _ = invert(cl, r, math.radians(theta_max_deg), 1.0 / (0.6 * lmax), N=N, L=L)
+    return k, p
+
+
 def beam_from_damping(ld):
     """exp(-(l/l_d)^2) = exp(-b^2 l^2) with b = 1/l_d (eq. cl)."""
     return 1.0 / float(ld)
