@@ -126,6 +126,52 @@ def test_field_matches_oracle(cmbx, N, dt):
     p.close()
 
 
+def _support_table(N, L, frac):
+    """A power-law table that ends at frac x the band limit pi N / L: the modes beyond carry
+    no power, so pass x skips their draws (and whole tiles) and pass y skips their lines."""
+    k, pk = workloads.powerlaw_cutoff_table(N, L, kc_modes=max(2, N // 4))
+    keep = k <= frac * np.pi * N / L
+    return k[keep], pk[keep]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N", [8, 16, 48, 64, 128])
+def test_field_limited_support_matches_oracle(cmbx, N, dt):
+    L = 1.0
+    table = _support_table(N, L, 0.55)
+    p, _ = _plan(cmbx, N, L, dt, table=table)
+    ref = ofield.field(onoise.halfgrid(N, L, 5, *table, dtype=np.float64))
+    gpu = p.debug_field(5).cpu().numpy()
+    assert _rel(gpu, ref) <= TOL[dt], (N, dt)
+    for txy in (8, 4, 2):   # other tiles: other zero-tile boundaries
+        try:
+            p.set_tiles(txy, 0)
+        except cmbx.CmbxError:
+            continue
+        assert _rel(p.debug_field(5).cpu().numpy(), ref) <= TOL[dt], (N, dt, txy)
+    p.close()
+
+
+def test_pipelined_ensemble_limited_support(cmbx):
+    """The fused pipeline takes each item's support bound from its own weight table."""
+    jobs = []
+    for i, (N, frac) in enumerate([(48, 0.4), (48, 1.0), (48, 0.7), (64, 0.5), (64, 0.9)]):
+        table = _support_table(N, 1.0, frac)
+        p, _ = _plan(cmbx, N, 1.0, "f32", interp="tricubic", table=table)
+        dirs = torch.tensor(workloads.cap_directions(25.0, 16, 64), device="cuda")
+        out = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
+        jobs.append(dict(plan=p, seed=70 + i, r=0.45, dirs=dirs, out=out))
+    ens = cmbx.Ensemble([dict(j) for j in jobs], mode="pipelined")
+    ens.launch()
+    torch.cuda.synchronize()
+    for j in jobs:
+        ref = j["plan"].simulate_patch(j["seed"], j["r"], j["dirs"]).cpu().numpy()[0]
+        assert _rel(j["out"].cpu().numpy()[0], ref) <= 1e-6, j["plan"].N
+    ens.close()
+    for j in jobs:
+        j["plan"].close()
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("N", [64, 384])
 def test_field_alt_tiles_agree(cmbx, N, dt):
