@@ -187,7 +187,9 @@ int cmbx_debug_field(cmbx_plan* plan, uint64_t seed, void* field);
 /* Run the first `npasses` (1..3) kernels of the field computation for realisation `seed`
  * into `buf` (device, N^3 reals of the plan's precision). After pass 1 (x) and pass 2 (y)
  * buf holds complex [N][N][N/2]: the half grid transformed along x (and y), with column
- * iz = 0 carrying Z(iz=0) + i Z(iz=N/2); after pass 3 it is the real field. */
+ * iz = 0 carrying Z(iz=0) + i Z(iz=N/2), except where the spectrum's support makes the
+ * result zero and the next pass does not read it (those entries are left as they were);
+ * after pass 3 it is the real field. */
 int cmbx_debug_passes(cmbx_plan* plan, uint64_t seed, int npasses, void* buf);
 /* Interpolate a caller-given device field [N][N][N] (plan precision, 16-byte aligned) at
  * the pixels. CMBX_EINVAL for a misaligned field. */
@@ -207,12 +209,15 @@ int cmbx_time_passes(cmbx_plan* plan, uint64_t seed, double r, const double* dir
                      void* out, int reps, double* ms);
 
 /*
- * Autotune the plan's workgroup shapes: for each of the three field kernels, every
- * compiled tile choice (cmbx_tile_choices) is launched `reps` times on the plan's stream
- * and timed with HIP events; the fastest is kept as the plan's option. best[0..2]
- * receives (tile_x, tile_y, lines_z) and ms[0..2] their average milliseconds (either may
- * be NULL). Needs a spectrum (CMBX_ESTATE otherwise); overwrites the first workspace slot;
- * synchronises the plan's stream.
+ * Autotune the plan's workgroup shapes by coordinate descent (two sweeps over tile_x,
+ * tile_y, lines_z): each compiled choice (cmbx_tile_choices) of one shape, the other two
+ * held at their best so far, is timed with HIP events over `reps` runs of the whole
+ * x -> y -> z chain on the plan's stream (one pass's write pattern changes the cost of the
+ * next, so a kernel timed alone can mislead); the fastest chain's shapes become the plan's
+ * options. best[0..2] receives (tile_x, tile_y, lines_z) and ms[0..2] the average
+ * milliseconds of each pass alone at those shapes (either may be NULL). Needs a spectrum
+ * (CMBX_ESTATE otherwise); overwrites the first workspace slot; synchronises the plan's
+ * stream.
  */
 int cmbx_plan_autotune(cmbx_plan* plan, int reps, int* best, double* ms);
 /* Compiled tile choices for (dtype, N): which = 0 for the x/y column tiles, 1 for the z

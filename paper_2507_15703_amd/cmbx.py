@@ -209,13 +209,14 @@ class Plan:
         spectrum_table(self.handle, k, p_inf)
 
     def autotune(self, reps=5, cache_path=None, use_cache=True):
-        """Choose the fastest compiled tile shapes of the three field kernels (timed on the
-        device by cmbx_plan_autotune) and remember them in a JSON cache keyed by
-        (arch, N, precision). A cached entry is reused if every value is still a compiled
-        choice; otherwise the plan is re-tuned. Returns dict(tile_x, tile_y, lines_z, ms)."""
+        """Choose the tile shapes of the three field kernels whose x -> y -> z chain runs
+        fastest (timed on the device by cmbx_plan_autotune) and remember them in a JSON
+        cache keyed by (arch, N, precision, tuning rule). A cached entry is reused if every
+        value is still a compiled choice; otherwise the plan is re-tuned. Returns
+        dict(tile_x, tile_y, lines_z, ms) with ms the time of each pass alone."""
         import json
         path = cache_path or TUNE_CACHE
-        key = f"gfx950:N{self.N}:{'f32' if self.dtype == F32 else 'f64'}"
+        key = f"gfx950:N{self.N}:{'f32' if self.dtype == F32 else 'f64'}:chain"
         cache = _load_cache(path) if use_cache else {}
         ent = cache.get(key)
         txy = tile_choices(self.dtype, self.N, 0)
@@ -310,13 +311,14 @@ class Plan:
 
     def debug_passes(self, seed, npasses):
         """Workspace after the first ``npasses`` kernels: complex [N][N][N/2] for 1-2 passes,
-        real [N][N][N] after 3."""
+        real [N][N][N] after 3. The kernels leave entries that the spectrum's support makes
+        zero unwritten; the buffer starts zeroed, so they read as that zero."""
         import torch
         ctype = torch.complex64 if self.dtype == F32 else torch.complex128
         if npasses < 3:
-            b = torch.empty((self.N, self.N, self.N // 2), dtype=ctype, device="cuda")
+            b = torch.zeros((self.N, self.N, self.N // 2), dtype=ctype, device="cuda")
         else:
-            b = torch.empty((self.N, self.N, self.N), dtype=self.torch_dtype, device="cuda")
+            b = torch.zeros((self.N, self.N, self.N), dtype=self.torch_dtype, device="cuda")
         _check(lib().cmbx_debug_passes(self.handle, int(seed), int(npasses), b.data_ptr()))
         return b
 

@@ -33,11 +33,12 @@ struct cmbx_plan {
   hipStream_t stream = nullptr;
   void* field = nullptr;   // batch x N^3 reals
   void* tw = nullptr;      // N complex roots of unity
-  void* wtab = nullptr;    // 3 (N/2)^2 + 1 half weights, 4 full weights, the last nonzero |f|^2
+  void* wtab = nullptr;    // 3 (N/2)^2 + 1 half weights, then 4 full weights
+  int m_hi = 0;            // largest |f|^2 of nonzero half weight in the current table
   bool has_spectrum = false;
   size_t real_size() const { return dtype == CMBX_F32 ? 4 : 8; }
   size_t field_bytes() const { return (size_t)N * N * N * real_size(); }
-  int64_t wtab_len() const { return 3ll * (N / 2) * (N / 2) + 1 + 4 + 1; }
+  int64_t wtab_len() const { return 3ll * (N / 2) * (N / 2) + 1 + 4; }
 };
 
 struct cmbx_ensemble {
@@ -50,6 +51,8 @@ struct cmbx_ensemble {
   hipEvent_t fork = nullptr;
   std::vector<void*> dev;  // rotating workspaces and the schedule
   std::vector<int> modes;  // execution mode chosen per (precision, N) group
+  // support bound each plan had when its kernels were captured (they skip what lies beyond)
+  std::vector<std::pair<const cmbx_plan*, int>> bounds;
   int device = 0;
 };
 
@@ -116,16 +119,16 @@ double interp_p(const double* kt, const double* pt, int64_t n, double k) {
   return pt[i] + prod;
 }
 
+// Returns the largest |f|^2 whose half weight is not zero: the passes skip what lies beyond.
 template <typename T>
-void fill_weights(const cmbx_plan* p, const double* kt, const double* pt, int64_t n, std::vector<T>& out) {
+int fill_weights(const cmbx_plan* p, const double* kt, const double* pt, int64_t n, std::vector<T>& out) {
   // P_box = P_inf (2 pi / L)^3 (eq. finalpbox, cubic box); half = sqrt(P_box / 2),
-  // full = sqrt(P_box) at |f|^2 = c (N/2)^2, c = 0..3; P_box(0) = 0. The last entry is the
-  // largest |f|^2 whose half weight is not zero: the noise pass draws no mode beyond it.
+  // full = sqrt(P_box) at |f|^2 = c (N/2)^2, c = 0..3; P_box(0) = 0.
   const int M = p->N / 2;
   const int64_t mmax = 3ll * M * M;
   const double c = 6.283185307179586 / p->L;
   const double c3 = c * c * c;
-  out.assign(mmax + 1 + 4 + 1, T(0));
+  out.assign(mmax + 1 + 4, T(0));
   std::vector<double> pbox(mmax + 1);
   for (int64_t m = 0; m <= mmax; ++m) {
     const double k = c * std::sqrt((double)m);
@@ -136,7 +139,7 @@ void fill_weights(const cmbx_plan* p, const double* kt, const double* pt, int64_
   for (int cc = 0; cc < 4; ++cc) out[mmax + 1 + cc] = (T)std::sqrt(pbox[(int64_t)cc * M * M]);
   int64_t hi = mmax;
   while (hi > 0 && out[hi] == T(0)) --hi;
-  out[mmax + 5] = (T)hi;  // <= 3 * 512^2 < 2^24: exact in binary32
+  return (int)hi;
 }
 
 int check_plan(const cmbx_plan* p) {
@@ -153,6 +156,7 @@ cmbx::FieldArgs field_args(const cmbx_plan* p, uint64_t seed, void* buf) {
   a.tw = p->tw;
   a.k0 = (uint32_t)(seed & 0xffffffffu);
   a.k1 = (uint32_t)(seed >> 32);
+  a.m_hi = p->m_hi;
   a.tile_x = p->tile_x;
   a.tile_y = p->tile_y;
   a.lines_z = p->lines_z;
@@ -376,19 +380,21 @@ int cmbx_spectrum_table(cmbx_plan* p, const double* k, const double* P, int64_t 
   }
   DeviceGuard g(p->device);
   hipError_t e;
+  int hi = 0;
   // the table is uploaded synchronously with respect to the plan's stream
   e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return fail(CMBX_EHIP, "stream sync: %s", hipGetErrorString(e));
   if (p->dtype == CMBX_F32) {
     std::vector<float> w;
-    fill_weights(p, k, P, n, w);
+    hi = fill_weights(p, k, P, n, w);
     e = hipMemcpy(p->wtab, w.data(), w.size() * 4, hipMemcpyHostToDevice);
   } else {
     std::vector<double> w;
-    fill_weights(p, k, P, n, w);
+    hi = fill_weights(p, k, P, n, w);
     e = hipMemcpy(p->wtab, w.data(), w.size() * 8, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return fail(CMBX_EHIP, "weight table upload: %s", hipGetErrorString(e));
+  p->m_hi = hi;
   p->has_spectrum = true;
   return ok();
 }
@@ -710,6 +716,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
   // workspaces; a plan used by two jobs is fine there (they run in order).
   cmbx_ensemble* en = new cmbx_ensemble;
   en->device = jobs[0].plan->device;
+  for (int j = 0; j < n_jobs; ++j) en->bounds.emplace_back(jobs[j].plan, jobs[j].plan->m_hi);
   auto bail = [&](int code, const std::string& msg) {
     clear_lanes(en);
     for (void* d : en->dev) (void)hipFree(d);
@@ -742,17 +749,19 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
           cnt[0] = (int64_t)(M / tx) * N;
           a.bx = gr.bufs[ix % nbuf];
           a.wtab_x = gr.items[ix].plan->wtab;
+          a.m_hi_x = gr.items[ix].plan->m_hi;
           a.k0 = (uint32_t)(gr.items[ix].seed & 0xffffffffu);
           a.k1 = (uint32_t)(gr.items[ix].seed >> 32);
         }
         if (iy >= 0 && iy < n) {
           cnt[1] = (int64_t)(M / ty) * N;
           a.by = gr.bufs[iy % nbuf];
-          a.wtab_y = gr.items[iy].plan->wtab;
+          a.m_hi_y = gr.items[iy].plan->m_hi;
         }
         if (iz >= 0 && iz < n) {
           cnt[2] = (int64_t)N * N / lz;
           a.bz = gr.bufs[iz % nbuf];
+          a.m_hi_z = gr.items[iz].plan->m_hi;
         }
         if (ig >= 0 && ig < n) {
           const Item& it = gr.items[ig];
@@ -853,6 +862,10 @@ int cmbx_ensemble_lanes(const cmbx_ensemble* en) {
 int cmbx_ensemble_launch(cmbx_ensemble* en, void* stream) {
   if (!en) return fail(CMBX_EINVAL, "ensemble is NULL");
   if (fault("launch")) return fail(CMBX_EHIP, "ensemble launch: injected fault (CMBX_FAULT)");
+  for (const auto& b : en->bounds)
+    if (b.first->m_hi > b.second)
+      return fail(CMBX_ESTATE, "a plan's spectrum now reaches |f|^2 = %d, beyond the %d its kernels were captured with: "
+                  "create the ensemble again", b.first->m_hi, b.second);
   DeviceGuard g(en->device);
   if (int rc = launch_lanes(en, (hipStream_t)stream)) return rc;
   return ok();
@@ -920,35 +933,49 @@ int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   cmbx::FieldArgs a = field_args(p, 0x5eedull, p->field);
-  // time one pass with the current args; returns ms or a negative value on error
-  auto time_pass = [&](int which) -> double {
-    hipError_t e = which == 0 ? cmbx::launch_pass_x(a, p->stream)  // warm-up
-                   : which == 1 ? cmbx::launch_pass_y(a, p->stream)
-                                : cmbx::launch_pass_z(a, p->stream);
+  auto launch = [&](int which) {
+    return which == 0 ? cmbx::launch_pass_x(a, p->stream)
+           : which == 1 ? cmbx::launch_pass_y(a, p->stream)
+                        : cmbx::launch_pass_z(a, p->stream);
+  };
+  // average ms of `reps` launches of the passes first .. last (after one warm-up round),
+  // or a negative value on error
+  auto time_passes = [&](int first, int last) -> double {
+    hipError_t e = hipSuccess;
+    for (int w = first; e == hipSuccess && w <= last; ++w) e = launch(w);
     if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
     for (int i = 0; e == hipSuccess && i < reps; ++i)
-      e = which == 0 ? cmbx::launch_pass_x(a, p->stream)
-          : which == 1 ? cmbx::launch_pass_y(a, p->stream)
-                       : cmbx::launch_pass_z(a, p->stream);
+      for (int w = first; e == hipSuccess && w <= last; ++w) e = launch(w);
     if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
     return e == hipSuccess ? (double)t / reps : -1.0;
   };
-  int pick[3] = {0, 0, 0};
-  double tbest[3] = {1e300, 1e300, 1e300};
+  int* opt[3] = {&a.tile_x, &a.tile_y, &a.lines_z};
+  int pick[3] = {p->tile_x, p->tile_y, p->lines_z};
+  double tbest[3] = {0, 0, 0};
   bool bad = false;
-  for (int which = 0; which < 3 && !bad; ++which) {
-    const int n = which == 2 ? nln : ntz;
-    for (int i = 0; i < n && !bad; ++i) {
-      a.tile_x = which == 0 ? tz[i] : p->tile_x;
-      a.tile_y = which == 1 ? tz[i] : p->tile_y;
-      a.lines_z = which == 2 ? ln[i] : p->lines_z;
-      const double t = time_pass(which);
-      if (t < 0) bad = true;
-      else if (t < tbest[which]) tbest[which] = t, pick[which] = which == 2 ? ln[i] : tz[i];
+  // Each shape is judged by the whole x -> y -> z chain, not by its own kernel alone: a
+  // pass's write pattern changes what the next pass pays (narrow x tiles time as fast as
+  // wide ones in isolation but slow pass y down). Coordinate descent, two sweeps.
+  for (int sweep = 0; sweep < 2 && !bad; ++sweep) {
+    for (int which = 0; which < 3 && !bad; ++which) {
+      const int n = which == 2 ? nln : ntz;
+      double best_t = 1e300;
+      for (int i = 0; i < n && !bad; ++i) {
+        for (int o = 0; o < 3; ++o) *opt[o] = pick[o];
+        *opt[which] = which == 2 ? ln[i] : tz[i];
+        const double t = time_passes(0, 2);
+        if (t < 0) bad = true;
+        else if (t < best_t) best_t = t, pick[which] = *opt[which];
+      }
     }
+  }
+  for (int o = 0; o < 3; ++o) *opt[o] = pick[o];
+  for (int which = 0; which < 3 && !bad; ++which) {
+    tbest[which] = time_passes(which, which);
+    if (tbest[which] < 0) bad = true;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -89,7 +89,7 @@ struct ZShape {
 template <typename T, int N, int TZ, int NT>
 __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __restrict__ buf,
                                        const T* __restrict__ wtab, const cpx<T>* __restrict__ twg, uint32_t k0,
-                                       uint32_t k1) {
+                                       uint32_t k1, int m_hi) {
   constexpr int M = N / 2;
   constexpr int PAIRS = TZ / 2;
   static_assert(M % TZ == 0 && TZ % 2 == 0, "tile must divide N/2 and be even");
@@ -98,16 +98,11 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   const int tid = threadIdx.x;
   const int zc0 = zt * TZ;
   const T* wself = wtab + 3 * M * M + 1;
-  // largest |f|^2 whose weight is not zero (stored after the table, exact in T)
-  const int m_hi = (int)wtab[3 * M * M + 5];
   const int fy2 = freq2(iy, N);
-  if (fy2 + zc0 * zc0 > m_hi) {
-    // every mode of the tile (the packed plane iz = N/2 included) is beyond the spectrum's
-    // support: its transform is zero
-    GlobalColIO<T> zero_out{buf + (size_t)iy * M + zc0, (size_t)N * M};
-    for (int i = tid; i < N * TZ; i += NT) zero_out(i % TZ, i / TZ, cpx<T>{T(0), T(0)});
-    return;
-  }
+  // Every mode of the tile (the packed plane iz = N/2 included) beyond the spectrum's
+  // support: its transform is zero, and pass y does not read those lines (it takes them
+  // as zero), so the tile is left as it is.
+  if (fy2 + zc0 * zc0 > m_hi) return;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   float* tab = nullptr;
   if constexpr (tab_cpx<T>() > 0) {
@@ -153,7 +148,7 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
 // written back in place.
 // After pass x the element (ix, iy, column zc) is zero wherever fy^2 + zc^2 exceeds the
 // spectrum's last nonzero |f|^2 (every mode of that x-line had zero weight); the reader
-// returns those zeros without loading them.
+// returns those zeros without loading them (pass x does not write them).
 template <typename T, int N>
 struct SupportColIO {
   GlobalColIO<T> g;
@@ -167,11 +162,12 @@ struct SupportColIO {
 
 template <typename T, int N, int TZ, int NT>
 __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __restrict__ buf,
-                                       const cpx<T>* __restrict__ twg, const T* __restrict__ wtab) {
+                                       const cpx<T>* __restrict__ twg, int m_hi) {
   constexpr int M = N / 2;
   cpx<T>* tile = smem;
   cpx<T>* tw = smem + N * TZ;
-  const int m_hi = (int)wtab[3 * M * M + 5];
+  // columns wholly beyond the support stay zero through pass y; pass z does not read them
+  if (zt * TZ * zt * TZ > m_hi) return;
   for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
   GlobalColIO<T> io{buf + (size_t)ix * N * M + zt * TZ, (size_t)M};
@@ -181,17 +177,31 @@ __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __r
 
 // ------------------------------------------------------------------ pass 3: z (c2r)
 // Workgroup = LINES consecutive (ix, iy) lines of N/2 complex, starting at line blk LINES;
-// they are contiguous, so the block is loaded and stored with unit stride.
+// they are contiguous, so the block is loaded and stored with unit stride. Columns zc with
+// zc^2 beyond the spectrum's last nonzero |f|^2 are zero after pass y (which does not
+// write them) and are not read.
 template <typename T, int N, int LINES, int NT>
 __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict__ buf,
-                                       const cpx<T>* __restrict__ twg) {
+                                       const cpx<T>* __restrict__ twg, int m_hi) {
   constexpr int M = N / 2;
   cpx<T>* tile = smem;
   cpx<T>* tw = smem + LINES * M;
   const int tid = threadIdx.x;
   cpx<T>* g = buf + (size_t)blk * LINES * M;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
-  for (int i = tid; i < LINES * M; i += NT) tile[i] = g[i];
+  if constexpr (NT % M == 0) {
+    // a thread meets one column only: its test is taken once, and its loads stay batched
+    if ((tid % M) * (tid % M) > m_hi) {
+      for (int i = tid; i < LINES * M; i += NT) tile[i] = {T(0), T(0)};
+    } else {
+      for (int i = tid; i < LINES * M; i += NT) tile[i] = g[i];
+    }
+  } else {
+    for (int i = tid; i < LINES * M; i += NT) {
+      const int zc = i % M;
+      tile[i] = zc * zc > m_hi ? cpx<T>{T(0), T(0)} : g[i];
+    }
+  }
   __syncthreads();
   HalfToComplex<T, M> first{tile, tw};
   GlobalLineIO<T, M> last{g};
@@ -202,24 +212,23 @@ template <typename T, int N, int TZ>
 __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __restrict__ buf,
                                                                  const T* __restrict__ wtab,
                                                                  const cpx<T>* __restrict__ twg,
-                                                                 uint32_t k0, uint32_t k1) {
+                                                                 uint32_t k0, uint32_t k1, int m_hi) {
   __shared__ cpx<T> smem[N * TZ + N + tab_cpx<T>()];
-  role_x<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, wtab, twg, k0, k1);
+  role_x<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, wtab, twg, k0, k1, m_hi);
 }
 
 template <typename T, int N, int TZ>
 __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __restrict__ buf,
-                                                                 const cpx<T>* __restrict__ twg,
-                                                                 const T* __restrict__ wtab) {
+                                                                 const cpx<T>* __restrict__ twg, int m_hi) {
   __shared__ cpx<T> smem[N * TZ + N];
-  role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg, wtab);
+  role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg, m_hi);
 }
 
 template <typename T, int N, int LINES>
 __global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __restrict__ buf,
-                                                                   const cpx<T>* __restrict__ twg) {
+                                                                   const cpx<T>* __restrict__ twg, int m_hi) {
   __shared__ cpx<T> smem[LINES * (N / 2) + N];
-  role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, blockIdx.x, buf, twg);
+  role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, blockIdx.x, buf, twg, m_hi);
 }
 
 // ------------------------------------------------------------------ debug noise
@@ -369,8 +378,8 @@ struct PipeArgs {
   cpx<T>* bx;          // pass x output buffer
   const T* wtab_x;     // weights of the item in pass x
   uint32_t k0, k1;     // its seed words
+  int m_hi_x, m_hi_y, m_hi_z;  // support bound of the items in passes x, y, z
   cpx<T>* by;          // pass y buffer
-  const T* wtab_y;     // weights of the item in pass y (its support bound)
   cpx<T>* bz;          // pass z buffer
   const T* field_g;    // gather input field
   const double* dirs;  // gather directions
@@ -398,11 +407,11 @@ __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict
   const int role = (int)(e >> 30);
   const int idx = (int)(e & 0x3FFFFFFFu);
   if (role == 0) {
-    role_x<T, N, TX, kPipeNT>(smem, idx % (M / TX), idx / (M / TX), a.bx, a.wtab_x, a.tw, a.k0, a.k1);
+    role_x<T, N, TX, kPipeNT>(smem, idx % (M / TX), idx / (M / TX), a.bx, a.wtab_x, a.tw, a.k0, a.k1, a.m_hi_x);
   } else if (role == 1) {
-    role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw, a.wtab_y);
+    role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw, a.m_hi_y);
   } else if (role == 2) {
-    role_z<T, N, LZ, kPipeNT>(smem, idx, a.bz, a.tw);
+    role_z<T, N, LZ, kPipeNT>(smem, idx, a.bz, a.tw, a.m_hi_z);
   } else {
     const int64_t i = (int64_t)idx * kPipeNT + threadIdx.x;
     if (i < a.npix) {
@@ -457,21 +466,21 @@ template <typename T, int N, int TZ>
 hipError_t run_x(const FieldArgs& a, hipStream_t s) {
   dim3 grid(N / 2 / TZ, N);
   hipLaunchKernelGGL((k_pass_x<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
-                     (const T*)a.wtab, (const cpx<T>*)a.tw, a.k0, a.k1);
+                     (const T*)a.wtab, (const cpx<T>*)a.tw, a.k0, a.k1, a.m_hi);
   return hipGetLastError();
 }
 template <typename T, int N, int TZ>
 hipError_t run_y(const FieldArgs& a, hipStream_t s) {
   dim3 grid(N / 2 / TZ, N);
   hipLaunchKernelGGL((k_pass_y<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
-                     (const cpx<T>*)a.tw, (const T*)a.wtab);
+                     (const cpx<T>*)a.tw, a.m_hi);
   return hipGetLastError();
 }
 template <typename T, int N, int LINES>
 hipError_t run_z(const FieldArgs& a, hipStream_t s) {
   dim3 grid(N * N / LINES);
   hipLaunchKernelGGL((k_pass_z<T, N, LINES>), grid, dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf,
-                     (const cpx<T>*)a.tw);
+                     (const cpx<T>*)a.tw, a.m_hi);
   return hipGetLastError();
 }
 
@@ -487,7 +496,9 @@ hipError_t run_pipe(const PipeLaunch& a, hipStream_t s) {
   p.k0 = a.k0;
   p.k1 = a.k1;
   p.by = (cpx<T>*)a.by;
-  p.wtab_y = (const T*)a.wtab_y;
+  p.m_hi_x = a.m_hi_x;
+  p.m_hi_y = a.m_hi_y;
+  p.m_hi_z = a.m_hi_z;
   p.bz = (cpx<T>*)a.bz;
   p.field_g = (const T*)a.field_g;
   p.dirs = a.dirs;

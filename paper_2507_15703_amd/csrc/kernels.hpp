@@ -18,10 +18,10 @@ int lines_z_choices(int dtype, int N, int* out);
 struct FieldArgs {
   int dtype, N;
   void* buf;           // N^3 reals, in place (complex N x N x N/2 during the passes)
-  const void* wtab;    // sqrt(P_box/2) for |f|^2 = 0 .. 3 (N/2)^2, then sqrt(P_box) x 4, then
-                       // the largest |f|^2 of nonzero sqrt(P_box/2) (an integer, exact)
+  const void* wtab;    // sqrt(P_box/2) for |f|^2 = 0 .. 3 (N/2)^2, then sqrt(P_box) x 4
   const void* tw;      // N roots exp(2 pi i m / N), complex, plan precision
   uint32_t k0, k1;     // Philox key (seed words)
+  int m_hi;            // largest |f|^2 of nonzero weight: the passes skip what lies beyond
   int tile_x, tile_y, lines_z;  // 0 = compiled default
 };
 
@@ -62,8 +62,8 @@ struct PipeLaunch {
   void* bx;
   const void* wtab_x;
   uint32_t k0, k1;
+  int m_hi_x, m_hi_y, m_hi_z;
   void* by;
-  const void* wtab_y;
   void* bz;
   const void* field_g;
   const double* dirs;

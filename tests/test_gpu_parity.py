@@ -152,6 +152,48 @@ def test_field_limited_support_matches_oracle(cmbx, N, dt):
     p.close()
 
 
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_support_shrinks_after_wide_run(cmbx, dt):
+    """Parts of the workspace beyond the support are neither written nor read: a narrow
+    spectrum after a full-band run on the same plan still matches the oracle."""
+    N, L = 64, 1.0
+    p, _ = _plan(cmbx, N, L, dt)
+    f = torch.empty((N, N, N), dtype=p.torch_dtype, device="cuda")
+    cmbx.debug_field(p.handle, 9, f.data_ptr())   # leaves a full-band field in f
+    for frac in (0.3, 0.05):
+        table = _support_table(N, L, frac)
+        p.spectrum_table(*table)
+        ref = ofield.field(onoise.halfgrid(N, L, 6, *table, dtype=np.float64))
+        cmbx.debug_field(p.handle, 6, f.data_ptr())
+        assert _rel(f.cpu().numpy(), ref) <= TOL[dt], (dt, frac)
+    p.close()
+
+
+def test_ensemble_rejects_grown_support(cmbx):
+    """An ensemble's kernels skip what lay beyond each plan's support when it was created:
+    a narrower spectrum later is fine, a wider one is refused until the ensemble is made
+    again."""
+    N = 48
+    narrow, wide = _support_table(N, 1.0, 0.5), _support_table(N, 1.0, 1.0)
+    p, _ = _plan(cmbx, N, 1.0, "f32", interp="tricubic", table=narrow)
+    dirs = torch.tensor(workloads.cap_directions(25.0, 16, 64), device="cuda")
+    out = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
+    for mode in ("chained", "pipelined"):
+        p.spectrum_table(*narrow)
+        ens = cmbx.Ensemble([dict(plan=p, seed=3, r=0.45, dirs=dirs, out=out)], mode=mode)
+        p.spectrum_table(*_support_table(N, 1.0, 0.3))
+        ens.launch()
+        torch.cuda.synchronize()
+        ref = p.simulate_patch(3, 0.45, dirs).cpu().numpy()[0]
+        assert _rel(out.cpu().numpy()[0], ref) <= 1e-6, mode
+        p.spectrum_table(*wide)
+        with pytest.raises(cmbx.CmbxError) as e:
+            ens.launch()
+        assert e.value.code == cmbx.ESTATE
+        ens.close()
+    p.close()
+
+
 def test_pipelined_ensemble_limited_support(cmbx):
     """The fused pipeline takes each item's support bound from its own weight table."""
     jobs = []
@@ -192,6 +234,25 @@ def test_field_alt_tiles_agree(cmbx, N, dt):
         err = _rel(p.debug_field(3).cpu().numpy(), base)
         assert err <= (1e-6 if dt == "f32" else 1e-14), (txy, lz, err)
     assert tried >= 2
+    p.close()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_autotune_picks_compiled_shapes(cmbx, dt, tmp_path):
+    """The chain-timed autotuner returns compiled shapes, sets them on the plan (the field
+    still matches the oracle) and caches them."""
+    N = 48
+    p, (k, pk) = _plan(cmbx, N, 1.0, dt)
+    cache = str(tmp_path / "tune.json")
+    t = p.autotune(reps=2, cache_path=cache)
+    assert not t["cached"]
+    assert t["tile_x"] in cmbx.tile_choices(dt, N, 0) and t["tile_y"] in cmbx.tile_choices(dt, N, 0)
+    assert t["lines_z"] in cmbx.tile_choices(dt, N, 1)
+    assert all(m > 0 for m in t["ms"])
+    ref = ofield.field(onoise.halfgrid(N, 1.0, 4, k, pk))
+    assert _rel(p.debug_field(4).cpu().numpy(), ref) <= TOL[dt]
+    again = p.autotune(reps=2, cache_path=cache)
+    assert again["cached"] and again["tile_x"] == t["tile_x"] and again["lines_z"] == t["lines_z"]
     p.close()
 
 
