@@ -29,13 +29,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "maps/s batched FP32 vs plain at 512³ box+cap sample, px err≤1e-5; HBM %peak"
 HBM_PEAK_GBS = 8000.0
+# rocprofv3 FETCH_SIZE, WRITE_SIZE (KiB per dispatch) of the noise + x kernel on the first
+# box (profile_run), by x tile width
+TRAFFIC_X = {8: (2356.22, 274368.0), 16: (1694.6, 279872.0)}
 
 
 def support(N, L, k, p):
-    """(drawn, y_rows): the half-grid modes (ix, iy, iz <= N/2) whose weight P_box(|f|) is
-    not zero -- the modes the noise pass draws (P_inf linear between table nodes, zero
-    beyond the last one) -- and the share of the (iy, packed column) lines that pass y reads
-    (fy^2 + zc^2 up to the last nonzero |f|^2; beyond, pass x leaves zeros)."""
+    """(drawn, y_rows, z_cols): the half-grid modes (ix, iy, iz <= N/2) whose weight
+    P_box(|f|) is not zero -- the modes the noise pass draws (P_inf linear between table
+    nodes, zero beyond the last one) --, the share of the (iy, packed column zc) x-lines
+    that can be nonzero after pass x (fy^2 + zc^2 up to the last nonzero |f|^2: pass x
+    writes them, pass y reads them), and the share of packed columns that can be nonzero
+    after pass y (zc^2 up to it: pass y writes them, pass z reads them)."""
     import numpy as np
     f = np.arange(N)
     f2 = np.minimum(f, N - f) ** 2
@@ -51,7 +56,7 @@ def support(N, L, k, p):
     m_hi = int(np.nonzero(pm > 0)[0].max()) if np.any(pm > 0) else 0
     zc = np.arange(N // 2)
     rows = (f2[:, None] + zc[None, :] ** 2) <= m_hi
-    return int(mult[pm > 0].sum()), float(rows.mean())
+    return int(mult[pm > 0].sum()), float(rows.mean()), float(np.mean(zc**2 <= m_hi))
 
 
 def build_jobs(torch, cmbx, workloads, n_boxes):
@@ -179,9 +184,12 @@ def main():
     ms = j0["plan"].time_passes(j0["seed"], j0["r"], j0["dirs"], j0["out"], reps=args.kernel_reps)
     N = 512
     field_bytes = 4 * N**3
-    drawn, y_rows = j0["support"]
-    # pass y reads only the lines pass x can have made nonzero (and writes all of them)
-    kbytes = [field_bytes, int(field_bytes * (1 + y_rows)), 2 * field_bytes, 28 * j0["n_pix"]]
+    drawn, y_rows, z_cols = j0["support"]
+    # algorithmic bytes: only what the spectrum's support can make nonzero moves -- pass x
+    # writes the x-lines with support, pass y reads them and writes the columns with
+    # support, pass z reads those and writes the real field
+    kbytes = [int(field_bytes * y_rows), int(field_bytes * (y_rows + z_cols)), int(field_bytes * (z_cols + 1)),
+              28 * j0["n_pix"]]
     names = ["pass_x_noise", "pass_y", "pass_z_c2r", "gather_tricubic"]
     kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
                for n, t, b in zip(names, ms, kbytes)}
@@ -196,8 +204,10 @@ def main():
     alu_peak = 256 * 4 * 16 * 2.4e9
     ach_ops = ops_launch / (ms[0] * 1e-3)
     # HBM bytes per launch of this kernel from rocprofv3 FETCH_SIZE (x2.0 calibration against
-    # a plain copy) + WRITE_SIZE, by tile width (counters of the current kernel code)
-    traffic_by_tile = {8: (3327.69 * 2.0 + 524288.0) * 1024, 16: (2207.31 * 2.0 + 524288.0) * 1024}
+    # a plain copy) + WRITE_SIZE (x1.0), by tile width, for this box's spectrum (counters of
+    # the current kernel code)
+    traffic_by_tile = {8: (TRAFFIC_X[8][0] * 2.0 + TRAFFIC_X[8][1]) * 1024,
+                       16: (TRAFFIC_X[16][0] * 2.0 + TRAFFIC_X[16][1]) * 1024}
     tile_x = jobs[0]["tuned"]["tile_x"]
     roofline = {"kernel": names[0], "bound": "alu", "achieved": round(ach_ops / 1e12, 2),
                 "peak": round(alu_peak / 1e12, 2), "unit": "Tops/s", "frac": round(ach_ops / alu_peak, 4),
@@ -206,7 +216,7 @@ def main():
     # the two transform passes are HBM-bound: fraction of the 8 TB/s peak
     for i in (1, 2):
         kernels[names[i]]["hbm_frac"] = round(kbytes[i] / (ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    map_bytes = sum(16 * N**3 + 4 * N**3 * j["support"][1] + 28 * j["n_pix"] for j in jobs) / nmaps
+    map_bytes = sum(4 * N**3 * (2 * j["support"][1] + 2 * j["support"][2] + 1) + 28 * j["n_pix"] for j in jobs) / nmaps
     path_gbs = map_bytes * value / 1e9
 
     result = {

@@ -165,7 +165,10 @@ int cmbx_ensemble_lanes(const cmbx_ensemble* ens);
 int cmbx_ensemble_modes(const cmbx_ensemble* ens, int* modes, int cap);
 /* Launch the captured graphs on `stream` (a hipStream_t; NULL = the default stream): the
  * work is ordered after what `stream` already holds, and what is later enqueued on
- * `stream` runs after all of it. */
+ * `stream` runs after all of it. The captured kernels skip the modes beyond each plan's
+ * spectral support (the largest |f|^2 of nonzero weight) as it was at creation: a plan's
+ * table may change between launches, but CMBX_ESTATE is returned (nothing launched) once
+ * a plan's support reaches beyond that; create the ensemble again then. */
 int cmbx_ensemble_launch(cmbx_ensemble* ens, void* stream);
 /* Release an ensemble (waits for the device first). NULL is accepted. */
 int cmbx_ensemble_destroy(cmbx_ensemble* ens);

@@ -1,8 +1,9 @@
 """A short, fixed launch sequence for rocprofv3 (kernel trace and counter passes).
 
-Runs, on one 512^3 FP32 plan (tricubic, r = 0.45 L, 30 deg cap of 768 x 2048 pixels,
-spectrum from the programme for the synthetic C_l on that cap as in the benchmark, or the
-power-law table with ``--spectrum powerlaw``; autotuned tile shapes unless given): one
+Runs, on one FP32 plan of the benchmark's first 512^3 box (tricubic, r = 0.45 L, its cap
+of 26.9 deg and 687 x 2048 pixels, its spectrum: the programme's solution for the synthetic
+C_l on that cap, ``spectrum.synthetic_job_spectrum``; the power-law table with
+``--spectrum powerlaw``; autotuned tile shapes unless given), with its seed: one
 warm-up realisation, then ``--reps`` launches of each kernel of the hot path through
 cmbx_time_passes, and a device-to-device copy of exactly 512 MiB (torch) whose counter
 readings calibrate the HBM byte counters. Usage:
@@ -12,7 +13,6 @@ readings calibrate the HBM byte counters. Usage:
 """
 import argparse
 import json
-import math
 import os
 import sys
 
@@ -35,10 +35,10 @@ def main():
     from paper_2507_15703_amd import cmbx, spectrum, workloads
 
     N = args.N
+    job = [j for j in workloads.ensemble_jobs() if j["N"] == 512][0]
     plan = cmbx.Plan(N, 1.0, args.dtype, batch=1, interp="tricubic")
     if args.spectrum == "lp":
-        lmax = workloads.lmax_for(N, 1.0, 0.45)
-        k, p, _ = spectrum.invert(workloads.synthetic_cl(lmax), 0.45, math.radians(30.0), 1.0 / (0.6 * lmax), N=N)
+        k, p = spectrum.synthetic_job_spectrum(N, 1.0, job["r_over_L"], job["theta_deg"], job["amp"])
     else:
         k, p = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N / 4)
     plan.spectrum_table(k, p)
@@ -46,11 +46,12 @@ def main():
         plan.set_tiles(args.tile_xy, args.lines_z)
     else:
         plan.autotune(reps=3)  # the tile shapes bench.py uses
-    dirs = torch.tensor(workloads.cap_directions(30.0, 768, 2048), device="cuda")
+    dirs = torch.tensor(workloads.cap_directions(job["theta_deg"], job["n_ring"], job["n_phi"]), device="cuda")
     out = torch.empty((1, dirs.shape[0]), dtype=plan.torch_dtype, device="cuda")
-    plan.simulate_patch(1, 0.45, dirs, out)
+    seed, r = job["seed"], job["r_over_L"]
+    plan.simulate_patch(seed, r, dirs, out)
     torch.cuda.synchronize()
-    ms = plan.time_passes(1, 0.45, dirs, out, reps=args.reps)
+    ms = plan.time_passes(seed, r, dirs, out, reps=args.reps)
     src = torch.ones(512 * 2**20 // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
