@@ -65,6 +65,11 @@ extern "C" {
 #define CMBX_OPT_LINES_Z  4 /* lines per workgroup of the z pass; 0 = default */
 #define CMBX_OPT_TILE_X   5 /* columns per workgroup of the x pass (noise + x transform) */
 #define CMBX_OPT_TILE_Y   6 /* columns per workgroup of the y pass */
+/* 1 (default): maps are made from only the part of the field their pixels' interpolation
+ * stencils read (the map footprint, found on the device from the directions at every
+ * call); 0: from the whole field. The maps are the same either way (Sec. II D 1: the box
+ * is simulated and then sampled; only the samples are the product). */
+#define CMBX_OPT_PRUNE    7
 
 typedef struct cmbx_plan cmbx_plan;
 typedef struct cmbx_ensemble cmbx_ensemble;
@@ -105,7 +110,9 @@ int cmbx_spectrum_table(cmbx_plan* plan, const double* k, const double* P_inf, i
  *   r      shell radius, 0 < r < L/2
  *   dirs   device FP64 [n_pix][3] unit vectors (caller-owned)
  *   out    device array [batch][n_pix] of the plan's precision (caller-owned)
- * The field of realisation b is left in the plan's workspace (cmbx_plan_info).
+ * The field of realisation b is left in the plan's workspace (cmbx_plan_info): the whole
+ * field with CMBX_OPT_PRUNE 0, otherwise only the z-lines in 8-row blocks of x-planes
+ * that the pixels' stencils read (the rest of the workspace is left as it was).
  * Errors: CMBX_ESTATE (no spectrum yet), CMBX_EINVAL (r out of range, n_pix < 1, NULL
  * pointer), CMBX_EHIP (launch failure).
  */
@@ -153,7 +160,8 @@ typedef struct cmbx_job {
  * ordered (one launch stream, or synchronised).
  * Buffers passed in stay caller-owned and must outlive the ensemble, and so must the
  * plans, whose weight and twiddle tables and workspaces are used when the graph runs
- * (interpolant, r and pixel counts are fixed at creation). Errors: as cmbx_simulate_patch
+ * (interpolant, prune option, r and pixel counts are fixed at creation; a pruning plan's
+ * footprint is made from the directions at every launch). Errors: as cmbx_simulate_patch
  * for each job, CMBX_EINVAL for n_jobs < 1, an unknown mode or both lane flags,
  * CMBX_ENOMEM.
  */
@@ -204,9 +212,10 @@ int cmbx_debug_gather(cmbx_plan* plan, const void* field, double r, const double
  * slot): every kernel is launched `reps` times in a row on the plan's stream between two
  * HIP events, and ms[i] receives the average duration in milliseconds of kernel i:
  * ms[0] pass x (noise + x transform), ms[1] pass y, ms[2] pass z (complex-to-real),
- * ms[3] gather into out[0 .. n_pix). Synchronises the plan's stream; the workspace and
- * out hold one realisation afterwards. Errors: as cmbx_simulate_patch, CMBX_EINVAL for
- * reps < 1 or ms == NULL.
+ * ms[3] gather into out[0 .. n_pix). The passes run as in cmbx_simulate_patch: if the
+ * plan prunes, the map footprint is made first (not timed). Synchronises the plan's
+ * stream; the workspace and out hold one realisation afterwards. Errors: as
+ * cmbx_simulate_patch, CMBX_EINVAL for reps < 1 or ms == NULL.
  */
 int cmbx_time_passes(cmbx_plan* plan, uint64_t seed, double r, const double* dirs, int64_t n_pix,
                      void* out, int reps, double* ms);
@@ -233,7 +242,8 @@ int cmbx_tile_choices(int dtype, int N, int which, int* out);
  * streams restricted to different compute units). stage 0: noise + x pass into buf;
  * 1: y pass on buf; 2: z pass on buf; 3: gather from buf (r, dirs, n_pix, out as in
  * cmbx_simulate_patch; ignored by stages 0-2). buf: device, N^3 reals of the plan's
- * precision, 16-byte aligned. Tile shapes are the plan's. Errors: CMBX_ESTATE (no
+ * precision, 16-byte aligned. Tile shapes are the plan's; stages 0-2 make the whole field
+ * (no map footprint). Errors: CMBX_ESTATE (no
  * spectrum), CMBX_EINVAL, CMBX_EHIP.
  */
 int cmbx_enqueue_stage(cmbx_plan* plan, int stage, uint64_t seed, void* buf, double r, const double* dirs,

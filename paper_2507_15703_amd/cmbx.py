@@ -20,7 +20,7 @@ F32, F64 = 1, 2
 TRILINEAR, TRICUBIC = 1, 2
 ENS_AUTO, ENS_CHAINED, ENS_PIPELINED = 0, 1, 2
 ENS_ONE_LANE, ENS_TWO_LANES = 0x100, 0x200
-OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y = 1, 2, 3, 4, 5, 6
+OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y, OPT_PRUNE = 1, 2, 3, 4, 5, 6, 7
 
 _DTYPES = {"f32": F32, "float32": F32, F32: F32, "f64": F64, "float64": F64, F64: F64}
 _INTERPS = {"trilinear": TRILINEAR, "tricubic": TRICUBIC, TRILINEAR: TRILINEAR, TRICUBIC: TRICUBIC}
@@ -163,9 +163,11 @@ class Plan:
 
     ``stream``: a torch.cuda.Stream, a raw hipStream_t integer, or None for torch's
     current stream (so the plan's work is ordered with torch's allocations).
+    ``prune``: maps are made from only the part of the field their stencils read (the
+    same maps; the workspace then holds only that part of the field).
     """
 
-    def __init__(self, N, L=1.0, dtype="f32", batch=1, interp="trilinear", stream=None):
+    def __init__(self, N, L=1.0, dtype="f32", batch=1, interp="trilinear", stream=None, prune=True):
         import torch
         self.N, self.L, self.batch = int(N), float(L), int(batch)
         self.dtype = _DTYPES[dtype]
@@ -173,6 +175,7 @@ class Plan:
         self.handle = plan_box(N, L, self.dtype, batch)
         try:
             self.set_interp(interp)
+            self.set_prune(prune)
             if stream is None:
                 stream = torch.cuda.current_stream()
             self.stream = stream
@@ -191,6 +194,10 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_prune(self, prune):
+        self.prune = bool(prune)
+        plan_set(self.handle, OPT_PRUNE, int(self.prune))
 
     def set_interp(self, interp):
         self.interp = _INTERPS[interp]
@@ -251,7 +258,8 @@ class Plan:
         return f.value + b * self.N**3 * self.real_size
 
     def field(self, b=0):
-        """A copy of realisation b's field from the plan's workspace, [N][N][N] tensor."""
+        """A copy of realisation b's field from the plan's workspace, [N][N][N] tensor (after
+        simulate_patch on a pruning plan only the part the map's stencils read is valid)."""
         import torch
         out = torch.empty((self.N, self.N, self.N), dtype=self.torch_dtype, device="cuda")
         _memcpy_d2d(out.data_ptr(), self.field_ptr(b), self.N**3 * self.real_size, self.stream)

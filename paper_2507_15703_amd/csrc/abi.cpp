@@ -35,6 +35,8 @@ struct cmbx_plan {
   void* tw = nullptr;      // N complex roots of unity
   void* wtab = nullptr;    // 3 (N/2)^2 + 1 half weights, then 4 full weights
   int m_hi = 0;            // largest |f|^2 of nonzero half weight in the current table
+  void* fp = nullptr;      // map footprint of the last simulate_patch call
+  bool prune = true;       // maps make only the part of the field their stencils read
   bool has_spectrum = false;
   size_t real_size() const { return dtype == CMBX_F32 ? 4 : 8; }
   size_t field_bytes() const { return (size_t)N * N * N * real_size(); }
@@ -50,6 +52,7 @@ struct cmbx_ensemble {
   std::vector<hipEvent_t> done;
   hipEvent_t fork = nullptr;
   std::vector<void*> dev;  // rotating workspaces and the schedule
+  std::vector<void*> fps;  // one map footprint per realisation whose plan prunes
   std::vector<int> modes;  // execution mode chosen per (precision, N) group
   // support bound each plan had when its kernels were captured (they skip what lies beyond)
   std::vector<std::pair<const cmbx_plan*, int>> bounds;
@@ -148,7 +151,7 @@ int check_plan(const cmbx_plan* p) {
 }
 
 cmbx::FieldArgs field_args(const cmbx_plan* p, uint64_t seed, void* buf) {
-  cmbx::FieldArgs a;
+  cmbx::FieldArgs a{};  // value-initialised: every pointer not set below is NULL (fp: the whole field)
   a.dtype = p->dtype;
   a.N = p->N;
   a.buf = buf;
@@ -163,8 +166,11 @@ cmbx::FieldArgs field_args(const cmbx_plan* p, uint64_t seed, void* buf) {
   return a;
 }
 
-int enqueue_field(const cmbx_plan* p, uint64_t seed, void* buf, hipStream_t s) {
-  const cmbx::FieldArgs a = field_args(p, seed, buf);
+// The field of one realisation in buf: the whole field, or with a map footprint `fp` only
+// the part that footprint marks (what the map's stencils read).
+int enqueue_field(const cmbx_plan* p, uint64_t seed, void* buf, hipStream_t s, const void* fp = nullptr) {
+  cmbx::FieldArgs a = field_args(p, seed, buf);
+  a.fp = fp;
   HIP_TRY(cmbx::launch_pass_x(a, s));
   HIP_TRY(cmbx::launch_pass_y(a, s));
   HIP_TRY(cmbx::launch_pass_z(a, s));
@@ -173,7 +179,7 @@ int enqueue_field(const cmbx_plan* p, uint64_t seed, void* buf, hipStream_t s) {
 
 int enqueue_gather(const cmbx_plan* p, const void* field, double r, const double* dirs, int64_t n_pix, void* out,
                    hipStream_t s) {
-  cmbx::GatherArgs g;
+  cmbx::GatherArgs g{};
   g.dtype = p->dtype;
   g.interp = p->interp;
   g.N = p->N;
@@ -185,6 +191,20 @@ int enqueue_gather(const cmbx_plan* p, const void* field, double r, const double
   g.n_pix = n_pix;
   g.out = out;
   HIP_TRY(cmbx::launch_gather(g, s));
+  return CMBX_OK;
+}
+
+int enqueue_footprint(const cmbx_plan* p, void* fp, double r, const double* dirs, int64_t n_pix, hipStream_t s) {
+  cmbx::FootprintArgs f{};
+  f.interp = p->interp;
+  f.N = p->N;
+  f.fp = fp;
+  f.scale = (double)p->N / p->L;
+  f.half = 0.5 * p->L;
+  f.r = r;
+  f.dirs = dirs;
+  f.n_pix = n_pix;
+  HIP_TRY(cmbx::launch_footprint(f, s));
   return CMBX_OK;
 }
 
@@ -200,9 +220,12 @@ int check_patch_args(const cmbx_plan* p, double r, const double* dirs, int64_t n
 // Launch the whole hot path for every realisation of the plan on stream s.
 int enqueue_patch(cmbx_plan* p, uint64_t seed, double r, const double* dirs, int64_t n_pix, void* out,
                   hipStream_t s) {
+  // the realisations share their pixels, hence one footprint
+  if (p->prune)
+    if (int rc = enqueue_footprint(p, p->fp, r, dirs, n_pix, s)) return rc;
   for (int b = 0; b < p->batch; ++b) {
     char* buf = (char*)p->field + (size_t)b * p->field_bytes();
-    int rc = enqueue_field(p, seed + (uint64_t)b, buf, s);
+    int rc = enqueue_field(p, seed + (uint64_t)b, buf, s, p->prune ? p->fp : nullptr);
     if (rc) return rc;
     rc = enqueue_gather(p, buf, r, dirs, n_pix, (char*)out + (size_t)b * n_pix * p->real_size(), s);
     if (rc) return rc;
@@ -287,6 +310,7 @@ int cmbx_plan_box(int N, double L, int dtype, int batch, cmbx_plan** out) {
   if (e == hipSuccess) e = hipMalloc(&p->field, p->field_bytes() * batch);
   if (e == hipSuccess) e = hipMalloc(&p->tw, (size_t)N * 2 * p->real_size());
   if (e == hipSuccess) e = hipMalloc(&p->wtab, (size_t)p->wtab_len() * p->real_size());
+  if (e == hipSuccess) e = hipMalloc(&p->fp, cmbx::footprint_bytes(N));
   if (e == hipSuccess && dtype == CMBX_F32) e = ensure_noise_tables(p->device);
   if (e != hipSuccess) {
     const int code = (e == hipErrorOutOfMemory) ? CMBX_ENOMEM : CMBX_EHIP;
@@ -321,6 +345,7 @@ int cmbx_plan_destroy(cmbx_plan* p) {
   if (p->field) (void)hipFree(p->field);
   if (p->tw) (void)hipFree(p->tw);
   if (p->wtab) (void)hipFree(p->wtab);
+  if (p->fp) (void)hipFree(p->fp);
   if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
   delete p;
   return ok();
@@ -333,6 +358,10 @@ int cmbx_plan_set(cmbx_plan* p, int key, int64_t value) {
     case CMBX_OPT_INTERP:
       if (value != CMBX_TRILINEAR && value != CMBX_TRICUBIC) return fail(CMBX_EINVAL, "unknown interpolant %lld", (long long)value);
       p->interp = (int)value;
+      return ok();
+    case CMBX_OPT_PRUNE:
+      if (value != 0 && value != 1) return fail(CMBX_EINVAL, "prune = %lld must be 0 or 1", (long long)value);
+      p->prune = value == 1;
       return ok();
     case CMBX_OPT_STREAM:
       p->stream = value == -1 ? p->own_stream : (hipStream_t)(intptr_t)value;
@@ -463,6 +492,7 @@ struct Item {
   int64_t n_pix;
   void* out;
   int lane = 0;  // chained mode: the graph (and stream) the item runs in
+  void* fp = nullptr;  // its map footprint if its plan prunes
 };
 
 // Interleave the roles' workgroups in proportion to their counts (largest-deficit
@@ -498,12 +528,17 @@ int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t
     for (const Item& it : gr.items) {
       if (lane >= 0 && it.lane != lane) continue;
       char* buf = (char*)it.plan->field + (size_t)it.slot * it.plan->field_bytes();
-      if (int rc = enqueue_field(it.plan, it.seed, buf, s)) return rc;
+      if (it.fp)
+        if (int rc = enqueue_footprint(it.plan, it.fp, it.r, it.dirs, it.n_pix, s)) return rc;
+      if (int rc = enqueue_field(it.plan, it.seed, buf, s, it.fp)) return rc;
       if (int rc = enqueue_gather(it.plan, buf, it.r, it.dirs, it.n_pix, it.out, s)) return rc;
     }
     return CMBX_OK;
   }
   if (lane > 0) return CMBX_OK;  // pipelined groups run in lane 0
+  for (const Item& it : gr.items)
+    if (it.fp)
+      if (int rc = enqueue_footprint(it.plan, it.fp, it.r, it.dirs, it.n_pix, s)) return rc;
   for (size_t i = 0; i < gr.pipe.size(); ++i) {
     cmbx::PipeLaunch a = gr.pipe[i];
     a.sched = dsched + gr.sched_off[i];
@@ -720,9 +755,21 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
   auto bail = [&](int code, const std::string& msg) {
     clear_lanes(en);
     for (void* d : en->dev) (void)hipFree(d);
+    for (void* d : en->fps) (void)hipFree(d);
     delete en;
     return code == CMBX_OK ? CMBX_OK : fail(code, "%s", msg.c_str());
   };
+  // a footprint per realisation of a pruning plan, made inside the graph at every launch
+  // (from the pixel directions as they are then)
+  for (Group& gr : groups)
+    for (Item& it : gr.items) {
+      if (!it.plan->prune) continue;
+      void* f = nullptr;
+      const hipError_t e = hipMalloc(&f, cmbx::footprint_bytes(it.plan->N));
+      if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "ensemble footprints");
+      en->fps.push_back(f);
+      it.fp = f;
+    }
   std::vector<uint32_t> sched;
   if (mode != CMBX_ENS_CHAINED) {
     for (Group& gr : groups) {
@@ -750,6 +797,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
           a.bx = gr.bufs[ix % nbuf];
           a.wtab_x = gr.items[ix].plan->wtab;
           a.m_hi_x = gr.items[ix].plan->m_hi;
+          a.fp_x = gr.items[ix].fp;
           a.k0 = (uint32_t)(gr.items[ix].seed & 0xffffffffu);
           a.k1 = (uint32_t)(gr.items[ix].seed >> 32);
         }
@@ -757,11 +805,13 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
           cnt[1] = (int64_t)(M / ty) * N;
           a.by = gr.bufs[iy % nbuf];
           a.m_hi_y = gr.items[iy].plan->m_hi;
+          a.fp_y = gr.items[iy].fp;
         }
         if (iz >= 0 && iz < n) {
           cnt[2] = (int64_t)N * N / lz;
           a.bz = gr.bufs[iz % nbuf];
           a.m_hi_z = gr.items[iz].plan->m_hi;
+          a.fp_z = gr.items[iz].fp;
         }
         if (ig >= 0 && ig < n) {
           const Item& it = gr.items[ig];
@@ -877,6 +927,7 @@ int cmbx_ensemble_destroy(cmbx_ensemble* en) {
   (void)hipDeviceSynchronize();
   clear_lanes(en);
   for (void* d : en->dev) (void)hipFree(d);
+  for (void* d : en->fps) (void)hipFree(d);
   delete en;
   return ok();
 }
@@ -887,9 +938,15 @@ int cmbx_time_passes(cmbx_plan* p, uint64_t seed, double r, const double* dirs, 
   if (int rc = check_patch_args(p, r, dirs, n_pix, out)) return rc;
   if (reps < 1 || !ms) return fail(CMBX_EINVAL, "reps must be >= 1 and ms non-NULL");
   DeviceGuard g(p->device);
+  cmbx::FieldArgs a = field_args(p, seed, p->field);
+  // the passes as cmbx_simulate_patch runs them: with the map's footprint if the plan
+  // prunes (made once, before the timed launches)
+  if (p->prune) {
+    if (int rc = enqueue_footprint(p, p->fp, r, dirs, n_pix, p->stream)) return rc;
+    a.fp = p->fp;
+  }
   hipEvent_t ev[5] = {};
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-  const cmbx::FieldArgs a = field_args(p, seed, p->field);
   int rc = CMBX_OK;
   hipError_t e = hipEventRecord(ev[0], p->stream);
   for (int i = 0; e == hipSuccess && i < reps; ++i) e = cmbx::launch_pass_x(a, p->stream);

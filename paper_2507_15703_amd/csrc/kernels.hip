@@ -27,11 +27,35 @@ struct GlobalColIO {
   __device__ __forceinline__ void done() const { __syncthreads(); }
 };
 
+// Map footprint (layout in kernels.hpp): a column tile whose writes skip the rows n that
+// no pixel stencil reads. `keep` is an LDS copy of the footprint's bytes for these rows,
+// one byte per `1 << SHIFT` rows; NULL keeps every row.
+template <typename T, int SHIFT>
+struct KeptRowsColIO {
+  GlobalColIO<T> g;
+  const uint8_t* keep;
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const {
+    if (!keep || keep[n >> SHIFT]) g(q, n, v);
+  }
+  __device__ __forceinline__ void done() const { g.done(); }
+};
+
 // Contiguous lines of length L: element n of line q at p[q * L + n].
 template <typename T, int L>
 struct GlobalLineIO {
   cpx<T>* p;
   __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const { p[(size_t)q * L + n] = v; }
+  __device__ __forceinline__ void done() const {}
+};
+
+// The same, writing only the lines q with keep[q] != 0 (an LDS array; NULL keeps all).
+template <typename T, int L>
+struct KeptLinesIO {
+  cpx<T>* p;
+  const uint8_t* keep;
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const {
+    if (!keep || keep[q]) p[(size_t)q * L + n] = v;
+  }
   __device__ __forceinline__ void done() const {}
 };
 
@@ -85,11 +109,12 @@ struct ZShape {
 // weighted modes in LDS (one Philox call per pair of neighbouring iz), then runs the
 // length-N inverse transform along x and writes the tile's N rows of TZ columns (128 B for
 // FP32 TZ = 16) to the strided x axis. smem: N TZ + N complex (tile, then twiddles), then
-// for binary32 the Box-Muller tables.
+// for binary32 the Box-Muller tables. With a map footprint `fp`, only the rows ix of the
+// x-planes that the map's stencils read are written (the transform itself is whole).
 template <typename T, int N, int TZ, int NT>
 __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __restrict__ buf,
                                        const T* __restrict__ wtab, const cpx<T>* __restrict__ twg, uint32_t k0,
-                                       uint32_t k1, int m_hi) {
+                                       uint32_t k1, int m_hi, const uint8_t* __restrict__ fp) {
   constexpr int M = N / 2;
   constexpr int PAIRS = TZ / 2;
   static_assert(M % TZ == 0 && TZ % 2 == 0, "tile must divide N/2 and be even");
@@ -103,6 +128,9 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   // support: its transform is zero, and pass y does not read those lines (it takes them
   // as zero), so the tile is left as it is.
   if (fy2 + zc0 * zc0 > m_hi) return;
+  __shared__ uint8_t planes[N];
+  if (fp)
+    for (int i = tid; i < N; i += NT) planes[i] = fp[i];
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   float* tab = nullptr;
   if constexpr (tab_cpx<T>() > 0) {
@@ -139,7 +167,7 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   }
   __syncthreads();
   LdsIO<T, N, TZ, true> first{tile};
-  GlobalColIO<T> last{buf + (size_t)iy * M + zc0, (size_t)N * M};
+  KeptRowsColIO<T, 0> last{{buf + (size_t)iy * M + zc0, (size_t)N * M}, fp ? planes : nullptr};
   fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, first, last);
 }
 
@@ -160,19 +188,27 @@ struct SupportColIO {
   __device__ __forceinline__ void done() const { g.done(); }
 };
 
+// With a map footprint `fp`, x-planes that no stencil reads are skipped, and of the
+// others only the 8-row blocks that some stencil reads are written.
 template <typename T, int N, int TZ, int NT>
 __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __restrict__ buf,
-                                       const cpx<T>* __restrict__ twg, int m_hi) {
+                                       const cpx<T>* __restrict__ twg, int m_hi, const uint8_t* __restrict__ fp) {
   constexpr int M = N / 2;
+  constexpr int NB = footprint_blocks(N);
   cpx<T>* tile = smem;
   cpx<T>* tw = smem + N * TZ;
   // columns wholly beyond the support stay zero through pass y; pass z does not read them
   if (zt * TZ * zt * TZ > m_hi) return;
+  if (fp && !fp[ix]) return;
+  __shared__ uint8_t rows[NB];
+  if (fp)
+    for (int i = threadIdx.x; i < NB; i += NT) rows[i] = fp[N + ix * NB + i];
   for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
   GlobalColIO<T> io{buf + (size_t)ix * N * M + zt * TZ, (size_t)M};
   SupportColIO<T, N> first{io, zt * TZ, m_hi};
-  fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, first, io);
+  KeptRowsColIO<T, 3> last{io, fp ? rows : nullptr};
+  fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, first, last);
 }
 
 // ------------------------------------------------------------------ pass 3: z (c2r)
@@ -180,13 +216,27 @@ __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __r
 // they are contiguous, so the block is loaded and stored with unit stride. Columns zc with
 // zc^2 beyond the spectrum's last nonzero |f|^2 are zero after pass y (which does not
 // write them) and are not read.
+// With a map footprint `fp`, a block none of whose lines a stencil reads is skipped, and
+// only the lines in 8-row blocks that some stencil reads are written (the others of a kept
+// block are transformed from whatever pass y left there, and dropped).
 template <typename T, int N, int LINES, int NT>
 __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict__ buf,
-                                       const cpx<T>* __restrict__ twg, int m_hi) {
+                                       const cpx<T>* __restrict__ twg, int m_hi, const uint8_t* __restrict__ fp) {
   constexpr int M = N / 2;
+  constexpr int NB = footprint_blocks(N);
   cpx<T>* tile = smem;
   cpx<T>* tw = smem + LINES * M;
   const int tid = threadIdx.x;
+  __shared__ uint8_t keep[LINES];
+  if (fp) {
+    int any = 0;
+    for (int q = tid; q < LINES; q += NT) {
+      const int l = blk * LINES + q;
+      keep[q] = fp[N + (l / N) * NB + ((l % N) >> 3)];
+      any |= keep[q];
+    }
+    if (!__syncthreads_or(any)) return;
+  }
   cpx<T>* g = buf + (size_t)blk * LINES * M;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   if constexpr (NT % M == 0) {
@@ -204,7 +254,7 @@ __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict
   }
   __syncthreads();
   HalfToComplex<T, M> first{tile, tw};
-  GlobalLineIO<T, M> last{g};
+  KeptLinesIO<T, M> last{g, fp ? keep : nullptr};
   fft_run<T, M, LINES, NT, false, 2, 0>(tw, tile, first, last);
 }
 
@@ -212,23 +262,26 @@ template <typename T, int N, int TZ>
 __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __restrict__ buf,
                                                                  const T* __restrict__ wtab,
                                                                  const cpx<T>* __restrict__ twg,
-                                                                 uint32_t k0, uint32_t k1, int m_hi) {
+                                                                 uint32_t k0, uint32_t k1, int m_hi,
+                                                                 const uint8_t* __restrict__ fp) {
   __shared__ cpx<T> smem[N * TZ + N + tab_cpx<T>()];
-  role_x<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, wtab, twg, k0, k1, m_hi);
+  role_x<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, wtab, twg, k0, k1, m_hi, fp);
 }
 
 template <typename T, int N, int TZ>
 __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __restrict__ buf,
-                                                                 const cpx<T>* __restrict__ twg, int m_hi) {
+                                                                 const cpx<T>* __restrict__ twg, int m_hi,
+                                                                 const uint8_t* __restrict__ fp) {
   __shared__ cpx<T> smem[N * TZ + N];
-  role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg, m_hi);
+  role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg, m_hi, fp);
 }
 
 template <typename T, int N, int LINES>
 __global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __restrict__ buf,
-                                                                   const cpx<T>* __restrict__ twg, int m_hi) {
+                                                                   const cpx<T>* __restrict__ twg, int m_hi,
+                                                                   const uint8_t* __restrict__ fp) {
   __shared__ cpx<T> smem[LINES * (N / 2) + N];
-  role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, blockIdx.x, buf, twg, m_hi);
+  role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, blockIdx.x, buf, twg, m_hi, fp);
 }
 
 // ------------------------------------------------------------------ debug noise
@@ -266,6 +319,27 @@ __device__ __forceinline__ void weights1d(T f, T* w, int interp) {
 
 __device__ __forceinline__ int wrap(int i, int N) { return i < 0 ? i + N : (i >= N ? i - N : i); }
 
+// First stencil node i0 (before wrapping: -1 .. N-1) and fraction along each axis of the
+// K-point stencil of pixel i. The gather and the map footprint both take their integer
+// decisions here.
+template <int K>
+__device__ __forceinline__ void stencil_origin(int N, double scale, double half, double r,
+                                               const double* __restrict__ dirs, int64_t i, int i0[3],
+                                               double frac[3]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double p = (r * dirs[3 * i + d] + half) * scale;
+    // any finite position is reduced modulo N; non-finite input samples node 0
+    if (!(p > -1.0e9 && p < 1.0e9)) p = 0.0;
+    const double fl = floor(p);
+    int base = (int)fl % N;
+    base = base < 0 ? base + N : base;
+    i0[d] = base - (K == 4 ? 1 : 0);
+    frac[d] = p - fl;
+  }
+}
+
 template <typename T, int K>
 __device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N, double scale, double half,
                                              double r, const double* __restrict__ dirs, int64_t i,
@@ -273,18 +347,10 @@ __device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N,
   int i0[3];
   T w[3][4];
   {
-#pragma clang fp contract(off)
+    double frac[3];
+    stencil_origin<K>(N, scale, half, r, dirs, i, i0, frac);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double p = (r * dirs[3 * i + d] + half) * scale;
-      // any finite position is reduced modulo N; non-finite input samples node 0
-      if (!(p > -1.0e9 && p < 1.0e9)) p = 0.0;
-      const double fl = floor(p);
-      int base = (int)fl % N;
-      base = base < 0 ? base + N : base;
-      i0[d] = base - (K == 4 ? 1 : 0);
-      weights1d<T>((T)(p - fl), w[d], K == 4 ? kTricubic : kTrilinear);
-    }
+    for (int d = 0; d < 3; ++d) weights1d<T>((T)frac[d], w[d], K == 4 ? kTricubic : kTrilinear);
   }
   // Tricubic fast path: the four z taps of a line are read with aligned 16-byte vector
   // loads (two for FP32, three for FP64) covering them, and the z weights are shifted to
@@ -367,6 +433,37 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int
   gather_pixel<T, K>(field, N, scale, half, r, dirs, i, out);
 }
 
+// ------------------------------------------------------------------ map footprint
+// Mark what the K-point stencils of the pixels read: x-plane ix, and the 8-row block of
+// line (ix, iy). Many threads store the same byte 1; nothing else writes it.
+template <int K>
+__global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int N, double scale, double half,
+                                                   double r, const double* __restrict__ dirs, int64_t npix) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  int i0[3];
+  double frac[3];
+  stencil_origin<K>(N, scale, half, r, dirs, i, i0, frac);
+  const int nb = footprint_blocks(N);
+#pragma unroll
+  for (int a = 0; a < K; ++a) {
+    const int ix = wrap(i0[0] + a, N);
+    fp[ix] = 1;
+    int prev = -1;
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+      const int blk = wrap(i0[1] + b, N) >> 3;
+      if (blk != prev) fp[N + ix * nb + blk] = 1;
+      prev = blk;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 // ------------------------------------------------------------------ pipelined passes
 // One launch runs the four stages of the hot path on four different realisations at once:
 // pass x of item t, pass y of item t-1, pass z of item t-2 and the gather of item t-3.
@@ -379,6 +476,7 @@ struct PipeArgs {
   const T* wtab_x;     // weights of the item in pass x
   uint32_t k0, k1;     // its seed words
   int m_hi_x, m_hi_y, m_hi_z;  // support bound of the items in passes x, y, z
+  const uint8_t *fp_x, *fp_y, *fp_z;  // their map footprints (NULL: whole field)
   cpx<T>* by;          // pass y buffer
   cpx<T>* bz;          // pass z buffer
   const T* field_g;    // gather input field
@@ -407,11 +505,11 @@ __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict
   const int role = (int)(e >> 30);
   const int idx = (int)(e & 0x3FFFFFFFu);
   if (role == 0) {
-    role_x<T, N, TX, kPipeNT>(smem, idx % (M / TX), idx / (M / TX), a.bx, a.wtab_x, a.tw, a.k0, a.k1, a.m_hi_x);
+    role_x<T, N, TX, kPipeNT>(smem, idx % (M / TX), idx / (M / TX), a.bx, a.wtab_x, a.tw, a.k0, a.k1, a.m_hi_x, a.fp_x);
   } else if (role == 1) {
-    role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw, a.m_hi_y);
+    role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw, a.m_hi_y, a.fp_y);
   } else if (role == 2) {
-    role_z<T, N, LZ, kPipeNT>(smem, idx, a.bz, a.tw, a.m_hi_z);
+    role_z<T, N, LZ, kPipeNT>(smem, idx, a.bz, a.tw, a.m_hi_z, a.fp_z);
   } else {
     const int64_t i = (int64_t)idx * kPipeNT + threadIdx.x;
     if (i < a.npix) {
@@ -466,21 +564,21 @@ template <typename T, int N, int TZ>
 hipError_t run_x(const FieldArgs& a, hipStream_t s) {
   dim3 grid(N / 2 / TZ, N);
   hipLaunchKernelGGL((k_pass_x<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
-                     (const T*)a.wtab, (const cpx<T>*)a.tw, a.k0, a.k1, a.m_hi);
+                     (const T*)a.wtab, (const cpx<T>*)a.tw, a.k0, a.k1, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
 }
 template <typename T, int N, int TZ>
 hipError_t run_y(const FieldArgs& a, hipStream_t s) {
   dim3 grid(N / 2 / TZ, N);
   hipLaunchKernelGGL((k_pass_y<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
-                     (const cpx<T>*)a.tw, a.m_hi);
+                     (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
 }
 template <typename T, int N, int LINES>
 hipError_t run_z(const FieldArgs& a, hipStream_t s) {
   dim3 grid(N * N / LINES);
   hipLaunchKernelGGL((k_pass_z<T, N, LINES>), grid, dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf,
-                     (const cpx<T>*)a.tw, a.m_hi);
+                     (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
 }
 
@@ -490,7 +588,7 @@ using PipeFn = hipError_t (*)(const PipeLaunch&, hipStream_t);
 
 template <typename T, int N, int TX, int TY, int LZ>
 hipError_t run_pipe(const PipeLaunch& a, hipStream_t s) {
-  PipeArgs<T> p;
+  PipeArgs<T> p{};
   p.bx = (cpx<T>*)a.bx;
   p.wtab_x = (const T*)a.wtab_x;
   p.k0 = a.k0;
@@ -499,6 +597,9 @@ hipError_t run_pipe(const PipeLaunch& a, hipStream_t s) {
   p.m_hi_x = a.m_hi_x;
   p.m_hi_y = a.m_hi_y;
   p.m_hi_z = a.m_hi_z;
+  p.fp_x = (const uint8_t*)a.fp_x;
+  p.fp_y = (const uint8_t*)a.fp_y;
+  p.fp_z = (const uint8_t*)a.fp_z;
   p.bz = (cpx<T>*)a.bz;
   p.field_g = (const T*)a.field_g;
   p.dirs = a.dirs;
@@ -641,6 +742,19 @@ hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uin
   else
     hipLaunchKernelGGL(k_noise_debug<double>, grid, dim3(256), 0, s, (cpx<double>*)out, N, (const double*)wtab, k0,
                        k1);
+  return hipGetLastError();
+}
+
+hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s) {
+  const int64_t words = (int64_t)(footprint_bytes(a.N) / 4);
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)a.fp, words);
+  const dim3 grid((unsigned)((a.n_pix + 255) / 256));
+  if (a.interp == kTricubic)
+    hipLaunchKernelGGL(k_footprint<4>, grid, dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.scale, a.half, a.r, a.dirs,
+                       a.n_pix);
+  else
+    hipLaunchKernelGGL(k_footprint<2>, grid, dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.scale, a.half, a.r, a.dirs,
+                       a.n_pix);
   return hipGetLastError();
 }
 

@@ -15,6 +15,23 @@ bool size_compiled(int N);
 int tile_xy_choices(int dtype, int N, int* out);
 int lines_z_choices(int dtype, int N, int* out);
 
+// Map footprint: what the interpolation stencils of one map's pixels read. Bytes [0, N):
+// x-plane ix is read; then for each ix the footprint_blocks(N) bytes of its 8-row blocks:
+// some line (ix, iy) with iy / 8 = block is read. 1 = read, 0 = not; padded to 4 bytes.
+constexpr int footprint_blocks(int N) { return (N + 7) / 8; }
+constexpr size_t footprint_bytes(int N) { return ((size_t)N * (1 + footprint_blocks(N)) + 3) & ~(size_t)3; }
+
+struct FootprintArgs {
+  int interp, N;
+  void* fp;            // footprint_bytes(N), cleared and filled by the launch
+  double scale, half;  // N / L and L / 2
+  double r;
+  const double* dirs;  // [n_pix][3]
+  int64_t n_pix;
+};
+// Two kernels: clear the footprint, then mark every pixel's stencil.
+hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s);
+
 struct FieldArgs {
   int dtype, N;
   void* buf;           // N^3 reals, in place (complex N x N x N/2 during the passes)
@@ -22,6 +39,7 @@ struct FieldArgs {
   const void* tw;      // N roots exp(2 pi i m / N), complex, plan precision
   uint32_t k0, k1;     // Philox key (seed words)
   int m_hi;            // largest |f|^2 of nonzero weight: the passes skip what lies beyond
+  const void* fp;      // map footprint: only what it marks is made (NULL = the whole field)
   int tile_x, tile_y, lines_z;  // 0 = compiled default
 };
 
@@ -63,6 +81,7 @@ struct PipeLaunch {
   const void* wtab_x;
   uint32_t k0, k1;
   int m_hi_x, m_hi_y, m_hi_z;
+  const void *fp_x, *fp_y, *fp_z;
   void* by;
   void* bz;
   const void* field_g;

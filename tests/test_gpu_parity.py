@@ -194,6 +194,70 @@ def test_ensemble_rejects_grown_support(cmbx):
     p.close()
 
 
+def _turned(dirs, k):
+    """The cap turned to another axis: a cyclic shift of the coordinates and, for odd k, a
+    reflection (caps at -z, +x, -y, ...), so the stencils cross the periodic boundary
+    along every axis when r is close to L/2."""
+    d = np.roll(dirs, k // 2, axis=1)
+    return -d if k % 2 else d
+
+
+@pytest.mark.parametrize("interp", ["trilinear", "tricubic"])
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N", [12, 48, 64, 128])
+def test_pruned_maps_equal_whole_field_maps(cmbx, N, dt, interp):
+    """Maps made from the part of the field the stencils read are bit-identical to maps of
+    the whole field: every value the gather reads is made by the same arithmetic. Caps on
+    all six half-axes near the box faces (r = 0.49 L) wrap the stencils; the pruning plan
+    keeps whatever an earlier call left outside the new footprint."""
+    L = 1.0
+    k, pk = workloads.powerlaw_cutoff_table(N, L, kc_modes=max(2, N // 4))
+    whole = cmbx.Plan(N, L, dt, batch=2, interp=interp, prune=False)
+    pruned = cmbx.Plan(N, L, dt, batch=2, interp=interp)
+    for p in (whole, pruned):
+        p.spectrum_table(k, pk)
+    base = workloads.cap_directions(20.0, 24, 96)
+    for turn in range(6):
+        for r in (0.49, 0.3):
+            dirs = torch.tensor(_turned(base, turn), device="cuda")
+            a = whole.simulate_patch(11 + turn, r, dirs).cpu().numpy()
+            b = pruned.simulate_patch(11 + turn, r, dirs).cpu().numpy()
+            assert np.array_equal(_bits(a), _bits(b)), (N, dt, interp, turn, r)
+    whole.close()
+    pruned.close()
+
+
+@pytest.mark.parametrize("mode", ["chained", "pipelined"])
+def test_pruned_ensemble_matches_whole_field(cmbx, mode):
+    """Ensembles of pruning plans (footprints made inside the graph at every launch) against
+    whole-field maps; new directions between launches are picked up."""
+    jobs, whole = [], []
+    for i, (N, theta) in enumerate([(48, 12.0), (48, 35.0), (64, 25.0), (64, 8.0)]):
+        k, pk = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N // 4)
+        p = cmbx.Plan(N, 1.0, "f32", interp="tricubic")
+        p.spectrum_table(k, pk)
+        w = cmbx.Plan(N, 1.0, "f32", interp="tricubic", prune=False)
+        w.spectrum_table(k, pk)
+        dirs = torch.tensor(_turned(workloads.cap_directions(theta, 16, 64), i), device="cuda")
+        out = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
+        jobs.append(dict(plan=p, seed=40 + i, r=0.45, dirs=dirs, out=out))
+        whole.append(w)
+    ens = cmbx.Ensemble([dict(j) for j in jobs], mode=mode)
+    for launch in range(2):
+        if launch:
+            for i, j in enumerate(jobs):   # same buffers, other directions
+                j["dirs"].copy_(torch.tensor(_turned(workloads.cap_directions(20.0, 16, 64), i + 3), device="cuda"))
+        ens.launch()
+        torch.cuda.synchronize()
+        for j, w in zip(jobs, whole):
+            ref = w.simulate_patch(j["seed"], j["r"], j["dirs"]).cpu().numpy()[0]
+            assert _rel(j["out"].cpu().numpy()[0], ref) <= 1e-6, (mode, launch, j["plan"].N)
+    ens.close()
+    for j, w in zip(jobs, whole):
+        j["plan"].close()
+        w.close()
+
+
 def test_pipelined_ensemble_limited_support(cmbx):
     """The fused pipeline takes each item's support bound from its own weight table."""
     jobs = []
@@ -218,7 +282,10 @@ def test_pipelined_ensemble_limited_support(cmbx):
 @pytest.mark.parametrize("N", [64, 384])
 def test_field_alt_tiles_agree(cmbx, N, dt):
     """Every compiled tile shape gives the same field up to rounding (the compiler may
-    contract multiply-adds differently per instantiation)."""
+    contract multiply-adds differently per instantiation). Bar for FP32: the three passes'
+    rounding gives each point a relative spread of about eps sqrt(3 log2 N) (3e-7 at
+    N = 384, eps = 6e-8), whose maximum over N^3 points is about 5.5 sigma = 1.6e-6: 2e-6.
+    FP64: the same reasoning at eps = 1.1e-16, 1e-14."""
     p, (k, pk) = _plan(cmbx, N, 1.0, dt)
     base = p.debug_field(3).cpu().numpy()
     if N <= 64:
@@ -232,7 +299,7 @@ def test_field_alt_tiles_agree(cmbx, N, dt):
             continue
         tried += 1
         err = _rel(p.debug_field(3).cpu().numpy(), base)
-        assert err <= (1e-6 if dt == "f32" else 1e-14), (txy, lz, err)
+        assert err <= (2e-6 if dt == "f32" else 1e-14), (txy, lz, err)
     assert tried >= 2
     p.close()
 
