@@ -64,6 +64,8 @@ def lib():
             "cmbx_debug_noise": (I, [P, U64, P]),
             "cmbx_debug_field": (I, [P, U64, P]),
             "cmbx_debug_gather": (I, [P, P, D, P, I64, P]),
+            "cmbx_footprint_bytes": (I64, [I]),
+            "cmbx_debug_footprint": (I, [P, D, P, I64, P]),
             "cmbx_debug_passes": (I, [P, U64, I, P]),
             "cmbx_time_passes": (I, [P, U64, D, P, I64, P, I, ctypes.POINTER(D)]),
             "cmbx_plan_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
@@ -329,6 +331,25 @@ class Plan:
             b = torch.zeros((self.N, self.N, self.N), dtype=self.torch_dtype, device="cuda")
         _check(lib().cmbx_debug_passes(self.handle, int(seed), int(npasses), b.data_ptr()))
         return b
+
+    def debug_footprint(self, r, dirs, out=None):
+        """The map footprint of (r, dirs) as simulate_patch makes it on a pruning plan:
+        (planes [N] uint8, blocks [N][ceil(N/8)] uint8, lines, sorted z-block list) as numpy
+        arrays; the raw device buffer goes to `out` if given (uint8 tensor)."""
+        import numpy as np
+        import torch
+        nbytes = int(lib().cmbx_footprint_bytes(self.N))
+        if nbytes < 0:
+            _check(nbytes)
+        if out is None:
+            out = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+        _check(lib().cmbx_debug_footprint(self.handle, float(r), dirs.data_ptr(), int(dirs.shape[0]), out.data_ptr()))
+        raw = out.cpu().numpy()
+        N, nb = self.N, (self.N + 7) // 8
+        off = (N * (1 + nb) + 3) // 4 * 4
+        hdr = raw[off:off + 8].view(np.uint32)
+        lst = raw[off + 8: off + 8 + 4 * int(hdr[1])].view(np.uint32)
+        return raw[:N].copy(), raw[N:N + N * nb].reshape(N, nb).copy(), int(hdr[0]), np.sort(lst)
 
     def debug_gather(self, field, r, dirs, out=None):
         import torch

@@ -194,10 +194,14 @@ int enqueue_gather(const cmbx_plan* p, const void* field, double r, const double
   return CMBX_OK;
 }
 
-int enqueue_footprint(const cmbx_plan* p, void* fp, double r, const double* dirs, int64_t n_pix, hipStream_t s) {
+// The map footprint of (r, dirs) in fp, with the z-pass work list for blocks of `lines`
+// lines (0: the plan's own z tile).
+int enqueue_footprint(const cmbx_plan* p, void* fp, double r, const double* dirs, int64_t n_pix, hipStream_t s,
+                      int lines = 0) {
   cmbx::FootprintArgs f{};
   f.interp = p->interp;
   f.N = p->N;
+  f.lines = lines > 0 ? lines : cmbx::resolve_lines_z(p->dtype, p->N, p->lines_z);
   f.fp = fp;
   f.scale = (double)p->N / p->L;
   f.half = 0.5 * p->L;
@@ -480,6 +484,22 @@ int cmbx_debug_gather(cmbx_plan* p, const void* field, double r, const double* d
   return ok();
 }
 
+int64_t cmbx_footprint_bytes(int N) {
+  if (N < 8 || N > 1024) return fail(CMBX_EINVAL, "N = %d must be in [8, 1024]", N);
+  return (int64_t)cmbx::footprint_bytes(N);
+}
+
+int cmbx_debug_footprint(cmbx_plan* p, double r, const double* dirs, int64_t n_pix, void* fp) {
+  if (int rc = check_plan(p)) return rc;
+  if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2", r);
+  if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "bad n_pix %lld", (long long)n_pix);
+  if (!dirs || !fp) return fail(CMBX_EINVAL, "dirs and fp must be non-NULL");
+  if ((uintptr_t)fp % 4 != 0) return fail(CMBX_EINVAL, "fp must be 4-byte aligned");
+  DeviceGuard g(p->device);
+  if (int rc = enqueue_footprint(p, fp, r, dirs, n_pix, p->stream)) return rc;
+  return ok();
+}
+
 namespace {
 
 // One realisation to simulate inside an ensemble.
@@ -536,9 +556,11 @@ int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t
     return CMBX_OK;
   }
   if (lane > 0) return CMBX_OK;  // pipelined groups run in lane 0
+  int tx = 0, ty = 0, lz = 0;
+  if (!cmbx::pipeline_shape(gr.dtype, gr.N, &tx, &ty, &lz)) return fail(CMBX_EUNSUPPORTED, "no pipelined kernel");
   for (const Item& it : gr.items)
     if (it.fp)
-      if (int rc = enqueue_footprint(it.plan, it.fp, it.r, it.dirs, it.n_pix, s)) return rc;
+      if (int rc = enqueue_footprint(it.plan, it.fp, it.r, it.dirs, it.n_pix, s, lz)) return rc;
   for (size_t i = 0; i < gr.pipe.size(); ++i) {
     cmbx::PipeLaunch a = gr.pipe[i];
     a.sched = dsched + gr.sched_off[i];

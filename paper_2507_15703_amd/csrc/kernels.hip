@@ -276,12 +276,26 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __re
   role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg, m_hi, fp);
 }
 
+// Without a footprint one workgroup per block of LINES lines. With one, a grid of at most
+// kZGrid workgroups walks the footprint's list of blocks that hold a read line (if the
+// list was made for another block size, every block, each checked line by line).
+constexpr int kZGrid = 1024;
+
 template <typename T, int N, int LINES>
 __global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __restrict__ buf,
                                                                    const cpx<T>* __restrict__ twg, int m_hi,
                                                                    const uint8_t* __restrict__ fp) {
   __shared__ cpx<T> smem[LINES * (N / 2) + N];
-  role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, blockIdx.x, buf, twg, m_hi, fp);
+  constexpr int NBLK = N * N / LINES;
+  const uint32_t* hdr = fp ? reinterpret_cast<const uint32_t*>(fp + footprint_list_offset(N)) : nullptr;
+  const bool listed = hdr && hdr[0] == (uint32_t)LINES;
+  // whole field: one pass of the loop, on this workgroup's own block (one call site of
+  // the transform, so both cases run the same instructions)
+  const int count = !fp ? (int)blockIdx.x + 1 : listed ? (int)hdr[1] : NBLK;
+  for (int e = blockIdx.x; e < count; e += gridDim.x) {
+    role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, listed ? (int)hdr[2 + e] : e, buf, twg, m_hi, fp);
+    __syncthreads();  // the tile and the line flags are reused by the next block
+  }
 }
 
 // ------------------------------------------------------------------ debug noise
@@ -459,6 +473,32 @@ __global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int
   }
 }
 
+// The z-pass work list: one thread per block of `lines` consecutive (ix, iy) lines; a
+// block that holds a line of a marked 8-row block is appended (one atomic per wave).
+__global__ __launch_bounds__(256) void k_zlist(uint8_t* __restrict__ fp, int N, int lines) {
+  const int nb = footprint_blocks(N);
+  const int nblk = N * N / lines;
+  uint32_t* hdr = reinterpret_cast<uint32_t*>(fp + footprint_list_offset(N));
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) hdr[0] = (uint32_t)lines;
+  bool need = false;
+  if (b < nblk) {
+    for (int l = b * lines; l < (b + 1) * lines && !need;) {
+      const int iy = l % N;
+      need = fp[N + (l / N) * nb + (iy >> 3)] != 0;
+      l += min(8 - (iy & 7), N - iy);  // the next 8-row block, or the next plane's first
+    }
+  }
+  const uint64_t m = __ballot(need);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(&hdr[1], (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  if (need) hdr[2 + base + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)b;
+}
+
 __global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -509,7 +549,16 @@ __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict
   } else if (role == 1) {
     role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw, a.m_hi_y, a.fp_y);
   } else if (role == 2) {
-    role_z<T, N, LZ, kPipeNT>(smem, idx, a.bz, a.tw, a.m_hi_z, a.fp_z);
+    int blk = idx;
+    if (a.fp_z) {
+      // with the item's z list (made for LZ) the index runs over the listed blocks
+      const uint32_t* hdr = reinterpret_cast<const uint32_t*>(a.fp_z + footprint_list_offset(N));
+      if (hdr[0] == (uint32_t)LZ) {
+        if (idx >= (int)hdr[1]) return;
+        blk = (int)hdr[2 + idx];
+      }
+    }
+    role_z<T, N, LZ, kPipeNT>(smem, blk, a.bz, a.tw, a.m_hi_z, a.fp_z);
   } else {
     const int64_t i = (int64_t)idx * kPipeNT + threadIdx.x;
     if (i < a.npix) {
@@ -576,7 +625,8 @@ hipError_t run_y(const FieldArgs& a, hipStream_t s) {
 }
 template <typename T, int N, int LINES>
 hipError_t run_z(const FieldArgs& a, hipStream_t s) {
-  dim3 grid(N * N / LINES);
+  constexpr int NBLK = N * N / LINES;
+  dim3 grid(a.fp && NBLK > kZGrid ? kZGrid : NBLK);
   hipLaunchKernelGGL((k_pass_z<T, N, LINES>), grid, dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf,
                      (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
@@ -746,7 +796,8 @@ hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uin
 }
 
 hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s) {
-  const int64_t words = (int64_t)(footprint_bytes(a.N) / 4);
+  if (a.lines < 1 || (a.N * a.N) % a.lines) return hipErrorInvalidValue;
+  const int64_t words = (int64_t)(footprint_list_offset(a.N) / 4) + 2;  // marks + list header
   hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)a.fp, words);
   const dim3 grid((unsigned)((a.n_pix + 255) / 256));
   if (a.interp == kTricubic)
@@ -755,7 +806,15 @@ hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_footprint<2>, grid, dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.scale, a.half, a.r, a.dirs,
                        a.n_pix);
+  const int nblk = a.N * a.N / a.lines;
+  hipLaunchKernelGGL(k_zlist, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.lines);
   return hipGetLastError();
+}
+
+int resolve_lines_z(int dtype, int N, int lines_z) {
+  const Entry* e = find(dtype, N);
+  const int i = e ? pick(e->lines, lines_z) : -1;
+  return i < 0 ? 0 : e->lines[i];
 }
 
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {

@@ -17,20 +17,29 @@ int lines_z_choices(int dtype, int N, int* out);
 
 // Map footprint: what the interpolation stencils of one map's pixels read. Bytes [0, N):
 // x-plane ix is read; then for each ix the footprint_blocks(N) bytes of its 8-row blocks:
-// some line (ix, iy) with iy / 8 = block is read. 1 = read, 0 = not; padded to 4 bytes.
+// some line (ix, iy) with iy / 8 = block is read. 1 = read, 0 = not. Then, 4-byte
+// aligned at footprint_list_offset(N), the z-pass work list: the block size `lines` it
+// was made for, the count, and the indices (in no particular order) of the blocks of
+// `lines` consecutive (ix, iy) lines that hold a read line (at most N^2 of them).
 constexpr int footprint_blocks(int N) { return (N + 7) / 8; }
-constexpr size_t footprint_bytes(int N) { return ((size_t)N * (1 + footprint_blocks(N)) + 3) & ~(size_t)3; }
+constexpr size_t footprint_list_offset(int N) { return ((size_t)N * (1 + footprint_blocks(N)) + 3) & ~(size_t)3; }
+constexpr size_t footprint_bytes(int N) { return footprint_list_offset(N) + 8 + 4 * (size_t)N * N; }
 
 struct FootprintArgs {
   int interp, N;
+  int lines;           // z block (lines per z workgroup) the work list is for
   void* fp;            // footprint_bytes(N), cleared and filled by the launch
   double scale, half;  // N / L and L / 2
   double r;
   const double* dirs;  // [n_pix][3]
   int64_t n_pix;
 };
-// Two kernels: clear the footprint, then mark every pixel's stencil.
+// Three kernels: clear the marks and the list header, mark every pixel's stencil, list
+// the z blocks.
 hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s);
+// Lines per z workgroup that launch_pass_z uses for (dtype, N) and a lines_z option
+// (0 = default); 0 if not compiled.
+int resolve_lines_z(int dtype, int N, int lines_z);
 
 struct FieldArgs {
   int dtype, N;

@@ -69,6 +69,7 @@ def test_null_arguments(L):
     assert L.cmbx_debug_noise(None, 0, None) == cmbx.EINVAL
     assert L.cmbx_debug_field(None, 0, None) == cmbx.EINVAL
     assert L.cmbx_debug_gather(None, None, 0.1, None, 1, None) == cmbx.EINVAL
+    assert L.cmbx_debug_footprint(None, 0.1, None, 1, None) == cmbx.EINVAL
     assert L.cmbx_plan_set(None, cmbx.OPT_INTERP, 1) == cmbx.EINVAL
     assert L.cmbx_ensemble_create(None, 0, 0, None) == cmbx.EINVAL
     assert L.cmbx_ensemble_launch(None, None) == cmbx.EINVAL
@@ -99,3 +100,13 @@ def test_noise_tables_match_oracle(L):
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
     assert L.cmbx_noise_tables(buf, 100) == cmbx.EINVAL
     assert L.cmbx_noise_tables(None, 768) == cmbx.EINVAL
+
+
+def test_footprint_bytes(L):
+    """Marks (N planes + N ceil(N/8) row blocks, padded to 4 bytes), the list header and
+    room for one list entry per (ix, iy) line."""
+    for N in (8, 12, 48, 512, 1024):
+        nb = (N + 7) // 8
+        assert L.cmbx_footprint_bytes(N) == (N * (1 + nb) + 3) // 4 * 4 + 8 + 4 * N * N
+    assert L.cmbx_footprint_bytes(4) == cmbx.EINVAL
+    assert L.cmbx_footprint_bytes(2048) == cmbx.EINVAL

@@ -227,6 +227,42 @@ def test_pruned_maps_equal_whole_field_maps(cmbx, N, dt, interp):
     pruned.close()
 
 
+def _footprint_ref(N, L, r, dirs, K):
+    """What the K-point stencils read, from the definition: node i0 + a (mod N) on each
+    axis, i0 = floor(p) mod N - (1 if K = 4), p = (r n + L/2) N / L in FP64 as the gather
+    forms it (no fused multiply-add)."""
+    p = (r * dirs + 0.5 * L) * (N / L)
+    base = np.floor(p).astype(np.int64) % N - (1 if K == 4 else 0)
+    nb = (N + 7) // 8
+    planes = np.zeros(N, np.uint8)
+    blocks = np.zeros((N, nb), np.uint8)
+    for a in range(K):
+        ix = (base[:, 0] + a) % N
+        planes[ix] = 1
+        for b in range(K):
+            blocks[ix, ((base[:, 1] + b) % N) // 8] = 1
+    return planes, blocks
+
+
+@pytest.mark.parametrize("interp", ["trilinear", "tricubic"])
+@pytest.mark.parametrize("N", [12, 64, 512])
+def test_footprint_matches_definition(cmbx, N, interp):
+    """Marks bit-exact against the definition; the z list holds each block of `lines`
+    lines with a marked line exactly once."""
+    L, K = 1.0, (4 if interp == "tricubic" else 2)
+    p = cmbx.Plan(N, L, "f32", interp=interp)
+    for turn, (theta, r) in enumerate([(20.0, 0.49), (35.0, 0.3), (5.0, 0.45)]):
+        dn = _turned(workloads.cap_directions(theta, 48, 192), turn)
+        planes, blocks, lines, lst = p.debug_footprint(r, torch.tensor(dn, device="cuda"))
+        rp, rb = _footprint_ref(N, L, r, dn, K)
+        assert np.array_equal(planes, rp) and np.array_equal(blocks, rb), (N, interp, turn)
+        assert lines in cmbx.tile_choices("f32", N, 1)
+        line_marked = rb[np.arange(N * N) // N, (np.arange(N * N) % N) // 8].astype(bool)
+        want = np.nonzero(line_marked.reshape(-1, lines).any(axis=1))[0]
+        assert np.array_equal(lst, want.astype(np.uint32)), (N, interp, turn)
+    p.close()
+
+
 @pytest.mark.parametrize("mode", ["chained", "pipelined"])
 def test_pruned_ensemble_matches_whole_field(cmbx, mode):
     """Ensembles of pruning plans (footprints made inside the graph at every launch) against
