@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--mode", default="auto", choices=["auto", "chained", "pipelined"],
                     help="ensemble execution mode of the batched path")
+    ap.add_argument("--lanes", type=int, default=None, choices=[1, 2],
+                    help="graphs the chained items are split over (default: auto mode times both)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): independent realisations "
@@ -146,7 +148,7 @@ def main():
     jobs = build_jobs(torch, cmbx, workloads, args.boxes)
     nmaps = len(jobs)
     ens = cmbx.Ensemble([dict(plan=j["plan"], seed=j["seed"], r=j["r"], dirs=j["dirs"], out=j["out"]) for j in jobs],
-                        mode=args.mode)
+                        mode=args.mode, lanes=args.lanes)
 
     def step_batched():
         ens.launch()

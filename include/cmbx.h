@@ -131,7 +131,7 @@ typedef struct cmbx_job {
 } cmbx_job;
 
 /* ensemble execution modes */
-#define CMBX_ENS_AUTO      0 /* time both modes per (precision, N) group at creation, keep the faster */
+#define CMBX_ENS_AUTO      0 /* time the modes and lanes at creation, keep the fastest */
 #define CMBX_ENS_CHAINED   1 /* each realisation's four kernels in turn, in its plan's workspace */
 #define CMBX_ENS_PIPELINED 2 /* software pipeline of fused launches (see below) */
 /* lane flags, OR-ed into the mode */
@@ -155,8 +155,10 @@ typedef struct cmbx_job {
  * into two graphs. Lane 0 (with every pipelined group) runs on the launch stream, lane 1
  * on a stream the ensemble owns, forked from and joined back into the launch stream, so
  * the chains of different plans can overlap on the device. With fewer than two chained
- * plans there is one lane. Without a lane flag, CMBX_ENS_AUTO times one and two lanes and
- * keeps the faster, and the explicit modes use one lane. Launches of one ensemble must be
+ * plans there is one lane. Without a lane flag, CMBX_ENS_AUTO times the whole ensemble
+ * with the per-group choice on one lane and on two, and with every group chained on two
+ * lanes, and keeps the fastest (so it may report a group chained that was faster
+ * pipelined alone); the explicit modes use one lane. Launches of one ensemble must be
  * ordered (one launch stream, or synchronised).
  * Buffers passed in stay caller-owned and must outlive the ensemble, and so must the
  * plans, whose weight and twiddle tables and workspaces are used when the graph runs

@@ -882,21 +882,41 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
   }
   // Lanes: with two, the chained items are split by plan (items of one plan share its
   // workspace and stay in one lane) into two graphs that run on two streams.
-  const bool two_possible = assign_lanes(groups);
-  int lanes = 1;
-  if (two_possible && (lanes_flag == CMBX_ENS_TWO_LANES || (lanes_flag == 0 && mode == CMBX_ENS_AUTO))) lanes = 2;
-  if (int rc = build_lanes(en, groups, dsched, lanes)) return bail(rc, g_err);
-  if (lanes == 2 && lanes_flag == 0) {
-    // AUTO: keep two lanes only if they are faster than one
-    const double t2 = time_ensemble(en);
-    clear_lanes(en);
-    if (int rc = build_lanes(en, groups, dsched, 1)) return bail(rc, g_err);
-    const double t1 = time_ensemble(en);
-    if (t1 < 0 || t2 < 0) return bail(CMBX_EHIP, "ensemble lane timing failed");
-    if (t2 < t1) {
+  std::vector<int> chosen;
+  for (const Group& gr : groups) chosen.push_back(gr.mode);
+  auto set_modes = [&](const std::vector<int>& m) {
+    for (size_t gi = 0; gi < groups.size(); ++gi) groups[gi].mode = m[gi];
+    return assign_lanes(groups);  // true if two lanes are possible
+  };
+  if (mode != CMBX_ENS_AUTO || lanes_flag != 0) {
+    const bool two_possible = set_modes(chosen);
+    const int lanes = two_possible && lanes_flag == CMBX_ENS_TWO_LANES ? 2 : 1;
+    if (int rc = build_lanes(en, groups, dsched, lanes)) return bail(rc, g_err);
+  } else {
+    // AUTO: time the whole ensemble in each candidate -- the modes chosen per group on one
+    // and on two lanes, and every group chained on two lanes (the chains of different
+    // plans then overlap, which a group timed alone does not show) -- and keep the fastest
+    struct Cand {
+      std::vector<int> modes;
+      int lanes;
+    };
+    std::vector<Cand> cands{{chosen, 1}};
+    if (set_modes(chosen)) cands.push_back({chosen, 2});
+    const std::vector<int> all_chained(groups.size(), CMBX_ENS_CHAINED);
+    if (all_chained != chosen && set_modes(all_chained)) cands.push_back({all_chained, 2});
+    double best_t = 1e300;
+    size_t best = 0;
+    for (size_t c = 0; c < cands.size() && cands.size() > 1; ++c) {
+      set_modes(cands[c].modes);
       clear_lanes(en);
-      if (int rc = build_lanes(en, groups, dsched, 2)) return bail(rc, g_err);
+      if (int rc = build_lanes(en, groups, dsched, cands[c].lanes)) return bail(rc, g_err);
+      const double t = time_ensemble(en);
+      if (t < 0) return bail(CMBX_EHIP, "ensemble timing failed");
+      if (t < best_t) best_t = t, best = c;
     }
+    set_modes(cands[best].modes);
+    clear_lanes(en);
+    if (int rc = build_lanes(en, groups, dsched, cands[best].lanes)) return bail(rc, g_err);
   }
   bool any_pipe = false;
   for (const Group& gr : groups) {
