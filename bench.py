@@ -31,7 +31,7 @@ METRIC = "maps/s batched FP32 vs plain at 512³ box+cap sample, px err≤1e-5; H
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE, WRITE_SIZE (KiB per dispatch) of the noise + x kernel on the first
 # box (profile_run), by x tile width
-TRAFFIC_X = {8: (2356.22, 274368.0), 16: (1694.6, 279872.0)}
+TRAFFIC_X = {8: (1440.31, 114141.0), 16: (1171.03, 116431.0)}
 
 
 def support(N, L, k, p):
@@ -59,6 +59,19 @@ def support(N, L, k, p):
     return int(mult[pm > 0].sum()), float(rows.mean()), float(np.mean(zc**2 <= m_hi))
 
 
+def footprint(N, L, r, dirs, K=4):
+    """(planes, lines): the shares of x-planes and of (ix, iy) lines that the K-point
+    interpolation stencils of the pixels read -- the only part of the field a map needs.
+    Node i0 + a (mod N) per axis, i0 = floor((r n + L/2) N / L) - 1 for K = 4."""
+    import numpy as np
+    base = np.floor((r * dirs + 0.5 * L) * (N / L)).astype(np.int64) - (1 if K == 4 else 0)
+    read = np.zeros((N, N), bool)
+    for a in range(K):
+        for b in range(K):
+            read[(base[:, 0] + a) % N, (base[:, 1] + b) % N] = True
+    return float(read.any(axis=1).mean()), float(read.mean())
+
+
 def build_jobs(torch, cmbx, workloads, n_boxes):
     from paper_2507_15703_amd import spectrum
     jobs = [j for j in workloads.ensemble_jobs() if j["N"] == 512][:n_boxes]
@@ -73,7 +86,8 @@ def build_jobs(torch, cmbx, workloads, n_boxes):
         res = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
         out.append(dict(plan=plan, seed=j["seed"], r=j["r_over_L"] * L, dirs=dirs, out=res,
                         theta=j["theta_deg"], n_pix=int(dirs.shape[0]), tuned=tuned,
-                        support=support(N, L, k, p), k=k, p=p))
+                        support=support(N, L, k, p), k=k, p=p,
+                        footprint=footprint(N, L, j["r_over_L"] * L, dirs.cpu().numpy())))
     return out
 
 
@@ -187,22 +201,44 @@ def main():
     N = 512
     field_bytes = 4 * N**3
     drawn, y_rows, z_cols = j0["support"]
-    # algorithmic bytes: only what the spectrum's support can make nonzero moves -- pass x
-    # writes the x-lines with support, pass y reads them and writes the columns with
-    # support, pass z reads those and writes the real field
-    kbytes = [int(field_bytes * y_rows), int(field_bytes * (y_rows + z_cols)), int(field_bytes * (z_cols + 1)),
-              28 * j0["n_pix"]]
+    planes, lines = j0["footprint"]
+    # algorithmic bytes: only what can be nonzero (the spectrum's support) and what the
+    # map reads (the stencils' footprint) moves -- pass x writes the x-lines within the
+    # support, rows of the planes read; pass y reads those and writes the columns within
+    # the support of the lines read; pass z reads those and writes the lines read; the
+    # gather reads the directions (24 B) and writes the map (4 B) per pixel
+    kbytes = [int(field_bytes * y_rows * planes), int(field_bytes * (y_rows * planes + z_cols * lines)),
+              int(field_bytes * (z_cols + 1) * lines), 28 * j0["n_pix"]]
     names = ["pass_x_noise", "pass_y", "pass_z_c2r", "gather_tricubic"]
     kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
                for n, t, b in zip(names, ms, kbytes)}
+    # the footprint (clear, mark the stencils, list the z blocks), timed on the plan's
+    # stream: it reads the directions (24 B per pixel)
+    import ctypes
+    plan0 = j0["plan"]
+    fbuf = torch.zeros(int(cmbx.lib().cmbx_footprint_bytes(N)), dtype=torch.uint8, device="cuda")
+    def make_fp():
+        cmbx._check(cmbx.lib().cmbx_debug_footprint(plan0.handle, ctypes.c_double(j0["r"]), j0["dirs"].data_ptr(),
+                                                    j0["n_pix"], fbuf.data_ptr()))
+    make_fp()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.kernel_reps):
+        make_fp()
+    e1.record()
+    torch.cuda.synchronize()
+    t_fp = e0.elapsed_time(e1) / args.kernel_reps
+    kernels["footprint"] = {"ms": round(t_fp, 4), "alg_bytes": 24 * j0["n_pix"],
+                            "GBps": round(24 * j0["n_pix"] / (t_fp * 1e-3) / 1e9, 1)}
     # The dominant kernel is the noise + x pass, bound by the vector ALU: its algorithmic
     # work is, per drawn mode (weight not zero), the binary32 Box-Muller sequence (49
     # floating-point operations with its four conversions) + the two weight products +
     # half a Philox4x32-10 call (10 rounds x (2 wide multiplies + 4 xor) / 2 = 30 integer
-    # ops), and per point of the packed N x N x N/2 grid the x transform (5 log2 N flops);
-    # peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s for unfused,
-    # unpacked operations.
-    ops_launch = drawn * (49 + 2 + 30) + (N**3 // 2) * 5 * math.log2(N)
+    # ops), and per point of the x-lines within the spectrum's support the x transform
+    # (5 log2 N flops; the other lines are zero and need none); peak = 256 CUs x 4 SIMDs
+    # x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s for unfused, unpacked operations.
+    ops_launch = drawn * (49 + 2 + 30) + (N**3 // 2) * y_rows * 5 * math.log2(N)
     alu_peak = 256 * 4 * 16 * 2.4e9
     ach_ops = ops_launch / (ms[0] * 1e-3)
     # HBM bytes per launch of this kernel from rocprofv3 FETCH_SIZE (x2.0 calibration against
@@ -218,7 +254,8 @@ def main():
     # the two transform passes are HBM-bound: fraction of the 8 TB/s peak
     for i in (1, 2):
         kernels[names[i]]["hbm_frac"] = round(kbytes[i] / (ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    map_bytes = sum(4 * N**3 * (2 * j["support"][1] + 2 * j["support"][2] + 1) + 28 * j["n_pix"] for j in jobs) / nmaps
+    map_bytes = sum(4 * N**3 * (2 * j["support"][1] * j["footprint"][0] + (2 * j["support"][2] + 1) * j["footprint"][1])
+                    + 52 * j["n_pix"] for j in jobs) / nmaps
     path_gbs = map_bytes * value / 1e9
 
     result = {
