@@ -245,6 +245,12 @@ int cmbx_time_passes(cmbx_plan* plan, uint64_t seed, double r, const double* dir
  * stream.
  */
 int cmbx_plan_autotune(cmbx_plan* plan, int reps, int* best, double* ms);
+/* As cmbx_plan_autotune, but on a pruning plan the chains are timed as maps of these pixels
+ * (r, dirs, n_pix as in cmbx_simulate_patch) are made: from their footprint, whose z list
+ * is rebuilt for each z tile tried (not timed). Which shapes win depends on how much of
+ * the field the map reads. Leaves the footprint in the plan. */
+int cmbx_plan_autotune_patch(cmbx_plan* plan, int reps, double r, const double* dirs, int64_t n_pix,
+                             int* best, double* ms);
 /* Compiled tile choices for (dtype, N): which = 0 for the x/y column tiles, 1 for the z
  * lines. Writes up to 4 values to out and returns their count (0 if none). */
 int cmbx_tile_choices(int dtype, int N, int which, int* out);

@@ -65,6 +65,7 @@ def lib():
             "cmbx_debug_field": (I, [P, U64, P]),
             "cmbx_debug_gather": (I, [P, P, D, P, I64, P]),
             "cmbx_footprint_bytes": (I64, [I]),
+            "cmbx_plan_autotune_patch": (I, [P, I, D, P, I64, P, P]),
             "cmbx_debug_footprint": (I, [P, D, P, I64, P]),
             "cmbx_debug_passes": (I, [P, U64, I, P]),
             "cmbx_time_passes": (I, [P, U64, D, P, I64, P, I, ctypes.POINTER(D)]),
@@ -217,15 +218,26 @@ class Plan:
     def spectrum_table(self, k, p_inf):
         spectrum_table(self.handle, k, p_inf)
 
-    def autotune(self, reps=5, cache_path=None, use_cache=True):
+    def autotune(self, reps=5, cache_path=None, use_cache=True, r=None, dirs=None):
         """Choose the tile shapes of the three field kernels whose x -> y -> z chain runs
         fastest (timed on the device by cmbx_plan_autotune) and remember them in a JSON
         cache keyed by (arch, N, precision, tuning rule). A cached entry is reused if every
         value is still a compiled choice; otherwise the plan is re-tuned. Returns
-        dict(tile_x, tile_y, lines_z, ms) with ms the time of each pass alone."""
+        dict(tile_x, tile_y, lines_z, ms) with ms the time of each pass alone.
+
+        With ``r`` and ``dirs`` (a map's pixels) a pruning plan is tuned on the passes as
+        that map makes them (cmbx_plan_autotune_patch); the choice depends on the map's
+        footprint, so it is not cached."""
         import json
         path = cache_path or TUNE_CACHE
         key = f"gfx950:N{self.N}:{'f32' if self.dtype == F32 else 'f64'}:chain"
+        patch = dirs is not None and self.prune
+        if patch:
+            if r is None:
+                raise ValueError("autotune with dirs needs r")
+            import torch
+            use_cache = False
+            d = _ptr(dirs, dirs.shape[0] * 24, torch.float64, "dirs")
         cache = _load_cache(path) if use_cache else {}
         ent = cache.get(key)
         txy = tile_choices(self.dtype, self.N, 0)
@@ -236,7 +248,10 @@ class Plan:
             return dict(ent, cached=True)
         best = (ctypes.c_int * 3)()
         ms = (ctypes.c_double * 3)()
-        _check(lib().cmbx_plan_autotune(self.handle, int(reps), best, ms))
+        if patch:
+            _check(lib().cmbx_plan_autotune_patch(self.handle, int(reps), float(r), d, int(dirs.shape[0]), best, ms))
+        else:
+            _check(lib().cmbx_plan_autotune(self.handle, int(reps), best, ms))
         ent = {"tile_x": best[0], "tile_y": best[1], "lines_z": best[2], "ms": list(ms)}
         if use_cache:
             cache[key] = ent

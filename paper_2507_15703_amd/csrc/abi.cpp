@@ -1020,11 +1020,16 @@ int cmbx_tile_choices(int dtype, int N, int which, int* out) {
   return n;
 }
 
-int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
+namespace {
+
+// The autotuner; with dirs (and a pruning plan) it times the passes as a map of those
+// pixels makes them: from the footprint, its z list rebuilt for each z tile tried.
+int autotune(cmbx_plan* p, int reps, int* best, double* ms, double r, const double* dirs, int64_t n_pix) {
   if (int rc = check_plan(p)) return rc;
   if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set");
   if (reps < 1) return fail(CMBX_EINVAL, "reps = %d must be >= 1", reps);
   DeviceGuard g(p->device);
+  const bool pruned = dirs != nullptr && p->prune;
   int tz[4], ln[4];
   const int ntz = cmbx::tile_xy_choices(p->dtype, p->N, tz);
   const int nln = cmbx::lines_z_choices(p->dtype, p->N, ln);
@@ -1032,6 +1037,17 @@ int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   cmbx::FieldArgs a = field_args(p, 0x5eedull, p->field);
+  if (pruned) a.fp = p->fp;
+  int fp_lines = -1;
+  // the footprint with the z list for the z tile in `a` (made before the timed launches)
+  auto prepare = [&]() -> int {
+    if (!pruned) return CMBX_OK;
+    const int lines = cmbx::resolve_lines_z(p->dtype, p->N, a.lines_z);
+    if (lines == fp_lines) return CMBX_OK;
+    if (int rc = enqueue_footprint(p, p->fp, r, dirs, n_pix, p->stream, lines)) return rc;
+    fp_lines = lines;
+    return CMBX_OK;
+  };
   auto launch = [&](int which) {
     return which == 0 ? cmbx::launch_pass_x(a, p->stream)
            : which == 1 ? cmbx::launch_pass_y(a, p->stream)
@@ -1065,6 +1081,10 @@ int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
       for (int i = 0; i < n && !bad; ++i) {
         for (int o = 0; o < 3; ++o) *opt[o] = pick[o];
         *opt[which] = which == 2 ? ln[i] : tz[i];
+        if (prepare() != CMBX_OK) {
+          bad = true;
+          break;
+        }
         const double t = time_passes(0, 2);
         if (t < 0) bad = true;
         else if (t < best_t) best_t = t, pick[which] = *opt[which];
@@ -1072,6 +1092,7 @@ int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
     }
   }
   for (int o = 0; o < 3; ++o) *opt[o] = pick[o];
+  if (!bad && prepare() != CMBX_OK) bad = true;
   for (int which = 0; which < 3 && !bad; ++which) {
     tbest[which] = time_passes(which, which);
     if (tbest[which] < 0) bad = true;
@@ -1087,6 +1108,21 @@ int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
     if (ms) ms[i] = tbest[i];
   }
   return ok();
+}
+
+}  // namespace
+
+int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
+  return autotune(p, reps, best, ms, 0.0, nullptr, 0);
+}
+
+int cmbx_plan_autotune_patch(cmbx_plan* p, int reps, double r, const double* dirs, int64_t n_pix, int* best,
+                             double* ms) {
+  if (int rc = check_plan(p)) return rc;
+  if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2", r);
+  if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "bad n_pix %lld", (long long)n_pix);
+  if (!dirs) return fail(CMBX_EINVAL, "dirs must be a non-NULL device pointer");
+  return autotune(p, reps, best, ms, r, dirs, n_pix);
 }
 
 int cmbx_enqueue_stage(cmbx_plan* p, int stage, uint64_t seed, void* buf, double r, const double* dirs,

@@ -9,7 +9,8 @@ the programme's solution for the synthetic C_l family on its cap (host inversion
 ``spectrum.synthetic_job_spectrum``; ``--spectrum powerlaw`` takes the power-law table).
 One step maps every box once. The batched path is one ``cmbx.Ensemble`` (auto mode: per size group the
 faster of chained and pipelined, one or two lanes); the unbatched path calls
-``simulate_patch`` job after job on one stream. Tile shapes are autotuned per size.
+``simulate_patch`` job after job on one stream. Tile shapes are autotuned per box on its
+own pixels.
 Prints one JSON line.
 """
 import argparse
@@ -34,8 +35,8 @@ def build(torch, cmbx, workloads, dtype, kind="lp"):
             k, p = workloads.powerlaw_cutoff_table(N, L, kc_modes=N / 4)
             p = p * j["amp"]
         plan.spectrum_table(k, p)
-        plan.autotune(reps=3)
         dirs = torch.tensor(workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"]), device="cuda")
+        plan.autotune(reps=3, r=j["r_over_L"] * L, dirs=dirs)
         out = torch.empty((1, dirs.shape[0]), dtype=plan.torch_dtype, device="cuda")
         jobs.append(dict(plan=plan, seed=j["seed"], r=j["r_over_L"] * L, dirs=dirs, out=out, N=N))
     return jobs

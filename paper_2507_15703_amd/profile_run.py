@@ -42,11 +42,11 @@ def main():
     else:
         k, p = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N / 4)
     plan.spectrum_table(k, p)
+    dirs = torch.tensor(workloads.cap_directions(job["theta_deg"], job["n_ring"], job["n_phi"]), device="cuda")
     if args.tile_xy or args.lines_z:
         plan.set_tiles(args.tile_xy, args.lines_z)
     else:
-        plan.autotune(reps=3)  # the tile shapes bench.py uses
-    dirs = torch.tensor(workloads.cap_directions(job["theta_deg"], job["n_ring"], job["n_phi"]), device="cuda")
+        plan.autotune(reps=3, r=job["r_over_L"], dirs=dirs)  # the tile shapes bench.py uses
     out = torch.empty((1, dirs.shape[0]), dtype=plan.torch_dtype, device="cuda")
     seed, r = job["seed"], job["r_over_L"]
     plan.simulate_patch(seed, r, dirs, out)

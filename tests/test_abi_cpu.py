@@ -70,6 +70,7 @@ def test_null_arguments(L):
     assert L.cmbx_debug_field(None, 0, None) == cmbx.EINVAL
     assert L.cmbx_debug_gather(None, None, 0.1, None, 1, None) == cmbx.EINVAL
     assert L.cmbx_debug_footprint(None, 0.1, None, 1, None) == cmbx.EINVAL
+    assert L.cmbx_plan_autotune_patch(None, 1, 0.1, None, 1, None, None) == cmbx.EINVAL
     assert L.cmbx_plan_set(None, cmbx.OPT_INTERP, 1) == cmbx.EINVAL
     assert L.cmbx_ensemble_create(None, 0, 0, None) == cmbx.EINVAL
     assert L.cmbx_ensemble_launch(None, None) == cmbx.EINVAL

@@ -359,6 +359,27 @@ def test_autotune_picks_compiled_shapes(cmbx, dt, tmp_path):
     p.close()
 
 
+def test_autotune_on_a_maps_pixels(cmbx):
+    """Tuning on a map's pixels (pruned chains) returns compiled shapes, caches nothing,
+    and the map afterwards still equals the whole-field map."""
+    N = 64
+    k, pk = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N // 4)
+    p = cmbx.Plan(N, 1.0, "f32", interp="tricubic")
+    w = cmbx.Plan(N, 1.0, "f32", interp="tricubic", prune=False)
+    for q in (p, w):
+        q.spectrum_table(k, pk)
+    dirs = torch.tensor(workloads.cap_directions(20.0, 32, 128), device="cuda")
+    t = p.autotune(reps=2, r=0.45, dirs=dirs)
+    assert not t["cached"] and t["tile_x"] in cmbx.tile_choices("f32", N, 0)
+    assert t["lines_z"] in cmbx.tile_choices("f32", N, 1) and all(m > 0 for m in t["ms"])
+    w.set_tiles(0, t["lines_z"], tile_x=t["tile_x"], tile_y=t["tile_y"])
+    a = p.simulate_patch(8, 0.45, dirs).cpu().numpy()
+    b = w.simulate_patch(8, 0.45, dirs).cpu().numpy()
+    assert np.array_equal(_bits(a), _bits(b))
+    p.close()
+    w.close()
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_field_256(cmbx, dt):
     N, L = 256, 1.0
