@@ -60,16 +60,19 @@ def support(N, L, k, p):
 
 
 def footprint(N, L, r, dirs, K=4):
-    """(planes, lines): the shares of x-planes and of (ix, iy) lines that the K-point
-    interpolation stencils of the pixels read -- the only part of the field a map needs.
-    Node i0 + a (mod N) per axis, i0 = floor((r n + L/2) N / L) - 1 for K = 4."""
+    """(planes, lines, zband): the shares of x-planes, of (ix, iy) lines and of z nodes
+    that the K-point interpolation stencils of the pixels read -- the only part of the
+    field a map needs. Node i0 + a (mod N) per axis, i0 = floor((r n + L/2) N / L) - 1
+    for K = 4."""
     import numpy as np
     base = np.floor((r * dirs + 0.5 * L) * (N / L)).astype(np.int64) - (1 if K == 4 else 0)
     read = np.zeros((N, N), bool)
+    zread = np.zeros(N, bool)
     for a in range(K):
+        zread[(base[:, 2] + a) % N] = True
         for b in range(K):
             read[(base[:, 0] + a) % N, (base[:, 1] + b) % N] = True
-    return float(read.any(axis=1).mean()), float(read.mean())
+    return float(read.any(axis=1).mean()), float(read.mean()), float(zread.mean())
 
 
 def build_jobs(torch, cmbx, workloads, n_boxes):
@@ -201,14 +204,14 @@ def main():
     N = 512
     field_bytes = 4 * N**3
     drawn, y_rows, z_cols = j0["support"]
-    planes, lines = j0["footprint"]
+    planes, lines, zband = j0["footprint"]
     # algorithmic bytes: only what can be nonzero (the spectrum's support) and what the
     # map reads (the stencils' footprint) moves -- pass x writes the x-lines within the
     # support, rows of the planes read; pass y reads those and writes the columns within
-    # the support of the lines read; pass z reads those and writes the lines read; the
-    # gather reads the directions (24 B) and writes the map (4 B) per pixel
+    # the support of the lines read; pass z reads those and writes the z nodes read of the
+    # lines read; the gather reads the directions (24 B) and writes the map (4 B) per pixel
     kbytes = [int(field_bytes * y_rows * planes), int(field_bytes * (y_rows * planes + z_cols * lines)),
-              int(field_bytes * (z_cols + 1) * lines), 28 * j0["n_pix"]]
+              int(field_bytes * (z_cols + zband) * lines), 28 * j0["n_pix"]]
     names = ["pass_x_noise", "pass_y", "pass_z_c2r", "gather_tricubic"]
     kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
                for n, t, b in zip(names, ms, kbytes)}
@@ -254,7 +257,8 @@ def main():
     # the two transform passes are HBM-bound: fraction of the 8 TB/s peak
     for i in (1, 2):
         kernels[names[i]]["hbm_frac"] = round(kbytes[i] / (ms[i] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    map_bytes = sum(4 * N**3 * (2 * j["support"][1] * j["footprint"][0] + (2 * j["support"][2] + 1) * j["footprint"][1])
+    map_bytes = sum(4 * N**3 * (2 * j["support"][1] * j["footprint"][0]
+                                + (2 * j["support"][2] + j["footprint"][2]) * j["footprint"][1])
                     + 52 * j["n_pix"] for j in jobs) / nmaps
     path_gbs = map_bytes * value / 1e9
 

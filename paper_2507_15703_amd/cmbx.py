@@ -349,8 +349,9 @@ class Plan:
 
     def debug_footprint(self, r, dirs, out=None):
         """The map footprint of (r, dirs) as simulate_patch makes it on a pruning plan:
-        (planes [N] uint8, blocks [N][ceil(N/8)] uint8, lines, sorted z-block list) as numpy
-        arrays; the raw device buffer goes to `out` if given (uint8 tensor)."""
+        (planes [N] uint8, blocks [N][ceil(N/8)] uint8, zblocks [ceil(N/32)] uint8, lines,
+        sorted z-block list) as numpy arrays; the raw device buffer goes to `out` if given
+        (uint8 tensor)."""
         import numpy as np
         import torch
         nbytes = int(lib().cmbx_footprint_bytes(self.N))
@@ -360,11 +361,13 @@ class Plan:
             out = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
         _check(lib().cmbx_debug_footprint(self.handle, float(r), dirs.data_ptr(), int(dirs.shape[0]), out.data_ptr()))
         raw = out.cpu().numpy()
-        N, nb = self.N, (self.N + 7) // 8
-        off = (N * (1 + nb) + 3) // 4 * 4
+        N, nb, nzb = self.N, (self.N + 7) // 8, (self.N + 31) // 32
+        zoff = N * (1 + nb)
+        off = (zoff + nzb + 3) // 4 * 4
         hdr = raw[off:off + 8].view(np.uint32)
         lst = raw[off + 8: off + 8 + 4 * int(hdr[1])].view(np.uint32)
-        return raw[:N].copy(), raw[N:N + N * nb].reshape(N, nb).copy(), int(hdr[0]), np.sort(lst)
+        return (raw[:N].copy(), raw[N:zoff].reshape(N, nb).copy(), raw[zoff:zoff + nzb].copy(), int(hdr[0]),
+                np.sort(lst))
 
     def debug_gather(self, field, r, dirs, out=None):
         import torch

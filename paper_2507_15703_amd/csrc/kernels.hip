@@ -48,13 +48,19 @@ struct GlobalLineIO {
   __device__ __forceinline__ void done() const {}
 };
 
-// The same, writing only the lines q with keep[q] != 0 (an LDS array; NULL keeps all).
-template <typename T, int L>
+// The same, writing only the lines q that `keep` flags (a bit mask, or with more than 64
+// lines per block an LDS byte array, NULL = every line), and of those only the elements n
+// whose bit n / 16 is set in `zmask`. Element n holds the real outputs 2n and 2n + 1, so zmask flags
+// blocks of 32 real outputs (whole 128-byte lines in FP32: partial-line writes cost more than they save).
+template <typename T, int L, int LINES>
 struct KeptLinesIO {
   cpx<T>* p;
-  const uint8_t* keep;
+  uint64_t keep;
+  const uint8_t* keep_lds;
+  uint64_t zmask;
   __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const {
-    if (!keep || keep[q]) p[(size_t)q * L + n] = v;
+    const bool line = LINES <= 64 ? ((keep >> q) & 1) != 0 : (!keep_lds || keep_lds[q] != 0);
+    if (line && ((zmask >> (n >> 4)) & 1)) p[(size_t)q * L + n] = v;
   }
   __device__ __forceinline__ void done() const {}
 };
@@ -218,7 +224,8 @@ __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __r
 // write them) and are not read.
 // With a map footprint `fp`, a block none of whose lines a stencil reads is skipped, and
 // only the lines in 8-row blocks that some stencil reads are written (the others of a kept
-// block are transformed from whatever pass y left there, and dropped).
+// block are transformed from whatever pass y left there, and dropped), and of those only
+// the 32-node z blocks that some stencil reads.
 template <typename T, int N, int LINES, int NT>
 __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict__ buf,
                                        const cpx<T>* __restrict__ twg, int m_hi, const uint8_t* __restrict__ fp) {
@@ -227,15 +234,28 @@ __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict
   cpx<T>* tile = smem;
   cpx<T>* tw = smem + LINES * M;
   const int tid = threadIdx.x;
-  __shared__ uint8_t keep[LINES];
+  static_assert(footprint_zblocks(N) <= 64, "one bit per z block");
+  // flags of the block's lines and of the z blocks as bit masks, built by every wave
+  // from the footprint (identical in all waves, so the early return is uniform); blocks
+  // of more than 64 lines keep their line flags in LDS
+  uint64_t keep = ~0ull, zmask = ~0ull;
+  __shared__ uint8_t keep_lds[LINES > 64 ? LINES : 1];
   if (fp) {
-    int any = 0;
-    for (int q = tid; q < LINES; q += NT) {
-      const int l = blk * LINES + q;
-      keep[q] = fp[N + (l / N) * NB + ((l % N) >> 3)];
-      any |= keep[q];
+    const int lane = tid & 63;
+    zmask = __ballot(lane < footprint_zblocks(N) && fp[footprint_z_offset(N) + lane] != 0);
+    if constexpr (LINES <= 64) {
+      const int l = blk * LINES + lane;
+      keep = __ballot(lane < LINES && fp[N + (l / N) * NB + ((l % N) >> 3)] != 0);
+      if (keep == 0) return;
+    } else {
+      int any = 0;
+      for (int q = tid; q < LINES; q += NT) {
+        const int l = blk * LINES + q;
+        keep_lds[q] = fp[N + (l / N) * NB + ((l % N) >> 3)];
+        any |= keep_lds[q];
+      }
+      if (!__syncthreads_or(any)) return;
     }
-    if (!__syncthreads_or(any)) return;
   }
   cpx<T>* g = buf + (size_t)blk * LINES * M;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
@@ -254,7 +274,7 @@ __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict
   }
   __syncthreads();
   HalfToComplex<T, M> first{tile, tw};
-  KeptLinesIO<T, M> last{g, fp ? keep : nullptr};
+  KeptLinesIO<T, M, LINES> last{g, keep, fp ? keep_lds : nullptr, zmask};
   fft_run<T, M, LINES, NT, false, 2, 0>(tw, tile, first, last);
 }
 
@@ -448,8 +468,9 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int
 }
 
 // ------------------------------------------------------------------ map footprint
-// Mark what the K-point stencils of the pixels read: x-plane ix, and the 8-row block of
-// line (ix, iy). Many threads store the same byte 1; nothing else writes it.
+// Mark what the K-point stencils of the pixels read: x-plane ix, the 8-row block of line
+// (ix, iy) and the 32-node z block. Many threads store the same byte 1; nothing else
+// writes it.
 template <int K>
 __global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int N, double scale, double half,
                                                    double r, const double* __restrict__ dirs, int64_t npix) {
@@ -459,6 +480,16 @@ __global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int
   double frac[3];
   stencil_origin<K>(N, scale, half, r, dirs, i, i0, frac);
   const int nb = footprint_blocks(N);
+  // z blocks: every pixel's few bytes are the same handful for the whole map, so a byte
+  // already set is only read (stores from every thread to one cache line would queue)
+  uint8_t* zb = fp + footprint_z_offset(N);
+  int prevz = -1;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const int b = wrap(i0[2] + c, N) >> 5;
+    if (b != prevz && !zb[b]) zb[b] = 1;
+    prevz = b;
+  }
 #pragma unroll
   for (int a = 0; a < K; ++a) {
     const int ix = wrap(i0[0] + a, N);

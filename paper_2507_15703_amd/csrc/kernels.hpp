@@ -17,12 +17,16 @@ int lines_z_choices(int dtype, int N, int* out);
 
 // Map footprint: what the interpolation stencils of one map's pixels read. Bytes [0, N):
 // x-plane ix is read; then for each ix the footprint_blocks(N) bytes of its 8-row blocks:
-// some line (ix, iy) with iy / 8 = block is read. 1 = read, 0 = not. Then, 4-byte
-// aligned at footprint_list_offset(N), the z-pass work list: the block size `lines` it
-// was made for, the count, and the indices (in no particular order) of the blocks of
-// `lines` consecutive (ix, iy) lines that hold a read line (at most N^2 of them).
+// some line (ix, iy) with iy / 8 = block is read; then at footprint_z_offset(N) the
+// footprint_zblocks(N) bytes of the 32-node z blocks: some node iz with iz / 32 = block
+// is read. 1 = read, 0 = not. Then, 4-byte aligned at footprint_list_offset(N), the
+// z-pass work list: the block size `lines` it was made for, the count, and the indices
+// (in no particular order) of the blocks of `lines` consecutive (ix, iy) lines that hold
+// a read line (at most N^2 of them).
 constexpr int footprint_blocks(int N) { return (N + 7) / 8; }
-constexpr size_t footprint_list_offset(int N) { return ((size_t)N * (1 + footprint_blocks(N)) + 3) & ~(size_t)3; }
+constexpr int footprint_zblocks(int N) { return (N + 31) / 32; }
+constexpr size_t footprint_z_offset(int N) { return (size_t)N * (1 + footprint_blocks(N)); }
+constexpr size_t footprint_list_offset(int N) { return (footprint_z_offset(N) + footprint_zblocks(N) + 3) & ~(size_t)3; }
 constexpr size_t footprint_bytes(int N) { return footprint_list_offset(N) + 8 + 4 * (size_t)N * N; }
 
 struct FootprintArgs {

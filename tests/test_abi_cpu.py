@@ -104,10 +104,10 @@ def test_noise_tables_match_oracle(L):
 
 
 def test_footprint_bytes(L):
-    """Marks (N planes + N ceil(N/8) row blocks, padded to 4 bytes), the list header and
-    room for one list entry per (ix, iy) line."""
+    """Marks (N planes + N ceil(N/8) row blocks + ceil(N/32) z blocks, padded to 4
+    bytes), the list header and room for one list entry per (ix, iy) line."""
     for N in (8, 12, 48, 512, 1024):
-        nb = (N + 7) // 8
-        assert L.cmbx_footprint_bytes(N) == (N * (1 + nb) + 3) // 4 * 4 + 8 + 4 * N * N
+        nb, nzb = (N + 7) // 8, (N + 31) // 32
+        assert L.cmbx_footprint_bytes(N) == (N * (1 + nb) + nzb + 3) // 4 * 4 + 8 + 4 * N * N
     assert L.cmbx_footprint_bytes(4) == cmbx.EINVAL
     assert L.cmbx_footprint_bytes(2048) == cmbx.EINVAL

@@ -236,26 +236,29 @@ def _footprint_ref(N, L, r, dirs, K):
     nb = (N + 7) // 8
     planes = np.zeros(N, np.uint8)
     blocks = np.zeros((N, nb), np.uint8)
+    zblocks = np.zeros((N + 31) // 32, np.uint8)
     for a in range(K):
         ix = (base[:, 0] + a) % N
         planes[ix] = 1
+        zblocks[((base[:, 2] + a) % N) // 32] = 1
         for b in range(K):
             blocks[ix, ((base[:, 1] + b) % N) // 8] = 1
-    return planes, blocks
+    return planes, blocks, zblocks
 
 
 @pytest.mark.parametrize("interp", ["trilinear", "tricubic"])
 @pytest.mark.parametrize("N", [12, 64, 512])
 def test_footprint_matches_definition(cmbx, N, interp):
-    """Marks bit-exact against the definition; the z list holds each block of `lines`
-    lines with a marked line exactly once."""
+    """Marks (planes, row blocks, z blocks) bit-exact against the definition; the z list
+    holds each block of `lines` lines with a marked line exactly once."""
     L, K = 1.0, (4 if interp == "tricubic" else 2)
     p = cmbx.Plan(N, L, "f32", interp=interp)
     for turn, (theta, r) in enumerate([(20.0, 0.49), (35.0, 0.3), (5.0, 0.45)]):
         dn = _turned(workloads.cap_directions(theta, 48, 192), turn)
-        planes, blocks, lines, lst = p.debug_footprint(r, torch.tensor(dn, device="cuda"))
-        rp, rb = _footprint_ref(N, L, r, dn, K)
+        planes, blocks, zblocks, lines, lst = p.debug_footprint(r, torch.tensor(dn, device="cuda"))
+        rp, rb, rz = _footprint_ref(N, L, r, dn, K)
         assert np.array_equal(planes, rp) and np.array_equal(blocks, rb), (N, interp, turn)
+        assert np.array_equal(zblocks, rz), (N, interp, turn)
         assert lines in cmbx.tile_choices("f32", N, 1)
         line_marked = rb[np.arange(N * N) // N, (np.arange(N * N) % N) // 8].astype(bool)
         want = np.nonzero(line_marked.reshape(-1, lines).any(axis=1))[0]
