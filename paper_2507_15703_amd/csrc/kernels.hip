@@ -374,63 +374,14 @@ __device__ __forceinline__ void stencil_origin(int N, double scale, double half,
   }
 }
 
+// K taps of z, K times K lines: sum of w[0][a] w[1][b] w[2][c] f(i0 + (a, b, c)).
 template <typename T, int K>
-__device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N, double scale, double half,
-                                             double r, const double* __restrict__ dirs, int64_t i,
-                                             T* __restrict__ out) {
-  int i0[3];
-  T w[3][4];
-  {
-    double frac[3];
-    stencil_origin<K>(N, scale, half, r, dirs, i, i0, frac);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) weights1d<T>((T)frac[d], w[d], K == 4 ? kTricubic : kTrilinear);
-  }
-  // Tricubic fast path: the four z taps of a line are read with aligned 16-byte vector
-  // loads (two for FP32, three for FP64) covering them, and the z weights are shifted to
-  // the taps' offset inside that window, so a line costs 2-3 load instructions instead of
-  // four. Taken when the window stays inside the line (no z wrap); otherwise the
-  // per-tap path below.
-  if constexpr (K == 4) {
-    constexpr int VEC = 16 / (int)sizeof(T);        // values per 16-byte load
-    constexpr int NV = sizeof(T) == 4 ? 2 : 3;       // loads per line
-    const int a0 = i0[2] - (((i0[2] % VEC) + VEC) % VEC);
-    const int sh = i0[2] - a0;                        // 0 .. VEC-1
-    if (i0[2] >= 0 && a0 + NV * VEC <= N) {
-      T wz[NV * VEC];
-#pragma unroll
-      for (int k = 0; k < NV * VEC; ++k) {
-        const int c = k - sh;
-        wz[k] = (c == 0) ? w[2][0] : (c == 1) ? w[2][1] : (c == 2) ? w[2][2] : (c == 3) ? w[2][3] : T(0);
-      }
-      T acc = 0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int ix = wrap(i0[0] + a, N);
-        T accb = 0;
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-          const int iy = wrap(i0[1] + bb, N);
-          const T* line = field + ((size_t)ix * N + iy) * N + a0;
-          T sum = 0;
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            if constexpr (sizeof(T) == 4) {
-              const float4 q = *reinterpret_cast<const float4*>(line + 4 * v);
-              sum += wz[4 * v] * q.x + wz[4 * v + 1] * q.y + wz[4 * v + 2] * q.z + wz[4 * v + 3] * q.w;
-            } else {
-              const double2 q = *reinterpret_cast<const double2*>(line + 2 * v);
-              sum += wz[2 * v] * q.x + wz[2 * v + 1] * q.y;
-            }
-          }
-          accb += w[1][bb] * sum;
-        }
-        acc += w[0][a] * accb;
-      }
-      out[i] = acc;
-      return;
-    }
-  }
+struct Taps {
+  typedef T vec __attribute__((ext_vector_type(K), aligned(sizeof(T))));
+};
+
+template <typename T, int K, bool CONTIGUOUS>
+__device__ __forceinline__ T stencil_sum(const T* __restrict__ field, int N, const int i0[3], const T (*w)[4]) {
   int iz[K];
 #pragma unroll
   for (int c = 0; c < K; ++c) iz[c] = wrap(i0[2] + c, N);
@@ -443,14 +394,46 @@ __device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N,
     for (int bb = 0; bb < K; ++bb) {
       const int iy = wrap(i0[1] + bb, N);
       const T* line = field + ((size_t)ix * N + iy) * N;
+      T q[K];
+      if constexpr (CONTIGUOUS) {
+        const typename Taps<T, K>::vec v = *reinterpret_cast<const typename Taps<T, K>::vec*>(line + i0[2]);
+#pragma unroll
+        for (int c = 0; c < K; ++c) q[c] = v[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < K; ++c) q[c] = line[iz[c]];
+      }
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < K; ++c) s += w[2][c] * line[iz[c]];
+      for (int c = 0; c < K; ++c) s += w[2][c] * q[c];
       accb += w[1][bb] * s;
     }
     acc += w[0][a] * accb;
   }
-  out[i] = acc;
+  return acc;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N, double scale, double half,
+                                             double r, const double* __restrict__ dirs, int64_t i,
+                                             T* __restrict__ out) {
+  int i0[3];
+  T w[3][4];
+  {
+    double frac[3];
+    stencil_origin<K>(N, scale, half, r, dirs, i, i0, frac);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) weights1d<T>((T)frac[d], w[d], K == 4 ? kTricubic : kTrilinear);
+  }
+  // The K z taps of a line are contiguous unless the stencil wraps in z: then they are
+  // read with vector loads of the taps alone (16 bytes for FP32 tricubic; the target
+  // allows them at 4-byte alignment), else one by one. Both ways sum in the same order, and
+  // no value outside the stencil is read (with a map footprint, cells beyond it are not
+  // made).
+  if (i0[2] >= 0 && i0[2] + K <= N)
+    out[i] = stencil_sum<T, K, true>(field, N, i0, w);
+  else
+    out[i] = stencil_sum<T, K, false>(field, N, i0, w);
 }
 
 // Blocks are assigned so that each XCD's L2 serves a contiguous pixel range.
