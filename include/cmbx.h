@@ -212,9 +212,10 @@ int64_t cmbx_footprint_bytes(int N);
  * stencil reads; then, per ix, ceil(N/8) bytes flag the 8-row blocks iy/8 of its lines
  * (ix, iy) that some stencil reads; then ceil(N/32) bytes flag the 32-node blocks iz/32
  * of z that some stencil reads (1 read, 0 not); then, at the next multiple of 4 bytes,
- * uint32 [lines, count, block indices ...]: the blocks of `lines` consecutive (ix, iy)
- * lines (lines = the plan's z tile) holding a flagged line, each once, in no particular
- * order. Errors: CMBX_EINVAL (r out of range, n_pix, NULL or misaligned). */
+ * uint32 [lines, z count, plane count, 0], then N^2 slots of which the first z count hold
+ * the blocks of `lines` consecutive (ix, iy) lines (lines = the plan's z tile) with a
+ * flagged line, then N slots of which the first plane count hold the flagged planes; each
+ * entry once, in no particular order. Errors: CMBX_EINVAL (r out of range, n_pix, NULL or misaligned). */
 int cmbx_debug_footprint(cmbx_plan* plan, double r, const double* dirs, int64_t n_pix, void* fp);
 /* Interpolate a caller-given device field [N][N][N] (plan precision, 16-byte aligned) at
  * the pixels. CMBX_EINVAL for a misaligned field. */

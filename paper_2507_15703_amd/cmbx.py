@@ -350,8 +350,8 @@ class Plan:
     def debug_footprint(self, r, dirs, out=None):
         """The map footprint of (r, dirs) as simulate_patch makes it on a pruning plan:
         (planes [N] uint8, blocks [N][ceil(N/8)] uint8, zblocks [ceil(N/32)] uint8, lines,
-        sorted z-block list) as numpy arrays; the raw device buffer goes to `out` if given
-        (uint8 tensor)."""
+        sorted z-block list, sorted plane list) as numpy arrays; the raw device buffer goes
+        to `out` if given (uint8 tensor)."""
         import numpy as np
         import torch
         nbytes = int(lib().cmbx_footprint_bytes(self.N))
@@ -364,10 +364,13 @@ class Plan:
         N, nb, nzb = self.N, (self.N + 7) // 8, (self.N + 31) // 32
         zoff = N * (1 + nb)
         off = (zoff + nzb + 3) // 4 * 4
-        hdr = raw[off:off + 8].view(np.uint32)
-        lst = raw[off + 8: off + 8 + 4 * int(hdr[1])].view(np.uint32)
+        hdr = raw[off:off + 16].view(np.uint32)
+        zl = off + 16
+        pl = zl + 4 * N * N
+        zlist = raw[zl:zl + 4 * int(hdr[1])].view(np.uint32)
+        plist = raw[pl:pl + 4 * int(hdr[2])].view(np.uint32)
         return (raw[:N].copy(), raw[N:zoff].reshape(N, nb).copy(), raw[zoff:zoff + nzb].copy(), int(hdr[0]),
-                np.sort(lst))
+                np.sort(zlist), np.sort(plist))
 
     def debug_gather(self, field, r, dirs, out=None):
         import torch

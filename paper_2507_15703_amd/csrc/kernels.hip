@@ -293,7 +293,30 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __re
                                                                  const cpx<T>* __restrict__ twg, int m_hi,
                                                                  const uint8_t* __restrict__ fp) {
   __shared__ cpx<T> smem[N * TZ + N];
-  role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, twg, m_hi, fp);
+  constexpr int T_ = N / 2 / TZ;  // column tiles per plane
+  // whole field: the grid is (tile, plane), one pass of the loop; with a footprint a grid
+  // of at most kZGrid workgroups walks (listed plane, tile) pairs, tiles beyond the
+  // spectrum's support left out. One call site of the transform either way.
+  int tiles = T_, count, e0, step;
+  const uint32_t* plist = nullptr;
+  if (fp) {
+    const uint32_t* hdr = reinterpret_cast<const uint32_t*>(fp + footprint_list_offset(N));
+    plist = hdr + kFootprintHeader + N * N;
+    tiles = 0;
+    while (tiles < T_ && tiles * TZ * tiles * TZ <= m_hi) ++tiles;
+    count = (int)hdr[2] * tiles;
+    e0 = blockIdx.x;
+    step = gridDim.x;
+  } else {
+    e0 = blockIdx.y * T_ + blockIdx.x;
+    count = e0 + 1;
+    step = 1;
+  }
+  for (int e = e0; e < count; e += step) {
+    const int zt = e % tiles, ix = plist ? (int)plist[e / tiles] : e / tiles;
+    role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, zt, ix, buf, twg, m_hi, fp);
+    __syncthreads();  // the tile is reused by the next pair
+  }
 }
 
 // Without a footprint one workgroup per block of LINES lines. With one, a grid of at most
@@ -313,7 +336,8 @@ __global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __
   // the transform, so both cases run the same instructions)
   const int count = !fp ? (int)blockIdx.x + 1 : listed ? (int)hdr[1] : NBLK;
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
-    role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, listed ? (int)hdr[2 + e] : e, buf, twg, m_hi, fp);
+    const int blk = listed ? (int)hdr[kFootprintHeader + e] : e;
+    role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, blk, buf, twg, m_hi, fp);
     __syncthreads();  // the tile and the line flags are reused by the next block
   }
 }
@@ -487,8 +511,22 @@ __global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int
   }
 }
 
-// The z-pass work list: one thread per block of `lines` consecutive (ix, iy) lines; a
-// block that holds a line of a marked 8-row block is appended (one atomic per wave).
+// Append `v` for the lanes with `need` to the list whose count is *count (one atomic per
+// wave; the order among waves is not fixed).
+__device__ __forceinline__ void wave_append(bool need, uint32_t v, uint32_t* count, uint32_t* list) {
+  const uint64_t m = __ballot(need);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  if (need) list[base + __popcll(m & ((1ull << lane) - 1))] = v;
+}
+
+// The work lists: one thread per block of `lines` consecutive (ix, iy) lines -- a block
+// that holds a line of a marked 8-row block goes to the z list -- and one per x-plane --
+// a marked plane goes to the plane list.
 __global__ __launch_bounds__(256) void k_zlist(uint8_t* __restrict__ fp, int N, int lines) {
   const int nb = footprint_blocks(N);
   const int nblk = N * N / lines;
@@ -503,14 +541,8 @@ __global__ __launch_bounds__(256) void k_zlist(uint8_t* __restrict__ fp, int N, 
       l += min(8 - (iy & 7), N - iy);  // the next 8-row block, or the next plane's first
     }
   }
-  const uint64_t m = __ballot(need);
-  if (m == 0) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(&hdr[1], (uint32_t)__popcll(m));
-  base = __shfl(base, leader);
-  if (need) hdr[2 + base + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)b;
+  wave_append(need, (uint32_t)b, &hdr[1], hdr + kFootprintHeader);
+  wave_append(b < N && fp[b] != 0, (uint32_t)b, &hdr[2], hdr + kFootprintHeader + N * N);
 }
 
 __global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
@@ -561,7 +593,15 @@ __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict
   if (role == 0) {
     role_x<T, N, TX, kPipeNT>(smem, idx % (M / TX), idx / (M / TX), a.bx, a.wtab_x, a.tw, a.k0, a.k1, a.m_hi_x, a.fp_x);
   } else if (role == 1) {
-    role_y<T, N, TY, kPipeNT>(smem, idx % (M / TY), idx / (M / TY), a.by, a.tw, a.m_hi_y, a.fp_y);
+    const int zt = idx % (M / TY);
+    int ix = idx / (M / TY);
+    if (a.fp_y) {
+      // with the item's plane list the index runs over (listed plane, tile)
+      const uint32_t* hdr = reinterpret_cast<const uint32_t*>(a.fp_y + footprint_list_offset(N));
+      if (ix >= (int)hdr[2]) return;
+      ix = (int)hdr[kFootprintHeader + N * N + ix];
+    }
+    role_y<T, N, TY, kPipeNT>(smem, zt, ix, a.by, a.tw, a.m_hi_y, a.fp_y);
   } else if (role == 2) {
     int blk = idx;
     if (a.fp_z) {
@@ -569,7 +609,7 @@ __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict
       const uint32_t* hdr = reinterpret_cast<const uint32_t*>(a.fp_z + footprint_list_offset(N));
       if (hdr[0] == (uint32_t)LZ) {
         if (idx >= (int)hdr[1]) return;
-        blk = (int)hdr[2 + idx];
+        blk = (int)hdr[kFootprintHeader + idx];
       }
     }
     role_z<T, N, LZ, kPipeNT>(smem, blk, a.bz, a.tw, a.m_hi_z, a.fp_z);
@@ -632,7 +672,8 @@ hipError_t run_x(const FieldArgs& a, hipStream_t s) {
 }
 template <typename T, int N, int TZ>
 hipError_t run_y(const FieldArgs& a, hipStream_t s) {
-  dim3 grid(N / 2 / TZ, N);
+  constexpr int NWG = N / 2 / TZ * N;
+  const dim3 grid = a.fp ? dim3(NWG > kZGrid ? kZGrid : NWG) : dim3(N / 2 / TZ, N);
   hipLaunchKernelGGL((k_pass_y<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
                      (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
@@ -811,7 +852,7 @@ hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uin
 
 hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s) {
   if (a.lines < 1 || (a.N * a.N) % a.lines) return hipErrorInvalidValue;
-  const int64_t words = (int64_t)(footprint_list_offset(a.N) / 4) + 2;  // marks + list header
+  const int64_t words = (int64_t)(footprint_list_offset(a.N) / 4) + kFootprintHeader;  // marks + header
   hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)a.fp, words);
   const dim3 grid((unsigned)((a.n_pix + 255) / 256));
   if (a.interp == kTricubic)
@@ -820,8 +861,9 @@ hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_footprint<2>, grid, dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.scale, a.half, a.r, a.dirs,
                        a.n_pix);
-  const int nblk = a.N * a.N / a.lines;
-  hipLaunchKernelGGL(k_zlist, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.lines);
+  const int threads = a.N * a.N / a.lines > a.N ? a.N * a.N / a.lines : a.N;  // per z block, and per plane
+  hipLaunchKernelGGL(k_zlist, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, (uint8_t*)a.fp, a.N,
+                     a.lines);
   return hipGetLastError();
 }
 

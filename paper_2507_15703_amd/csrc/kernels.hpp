@@ -19,15 +19,19 @@ int lines_z_choices(int dtype, int N, int* out);
 // x-plane ix is read; then for each ix the footprint_blocks(N) bytes of its 8-row blocks:
 // some line (ix, iy) with iy / 8 = block is read; then at footprint_z_offset(N) the
 // footprint_zblocks(N) bytes of the 32-node z blocks: some node iz with iz / 32 = block
-// is read. 1 = read, 0 = not. Then, 4-byte aligned at footprint_list_offset(N), the
-// z-pass work list: the block size `lines` it was made for, the count, and the indices
-// (in no particular order) of the blocks of `lines` consecutive (ix, iy) lines that hold
-// a read line (at most N^2 of them).
+// is read. 1 = read, 0 = not. Then, 4-byte aligned at footprint_list_offset(N), the work
+// lists: a header of four words (the z block size `lines` the z list was made for, the z
+// list's count, the plane list's count, 0), the z list -- the indices of the blocks of
+// `lines` consecutive (ix, iy) lines that hold a read line, room for N^2 -- and the plane
+// list -- the x-planes read, room for N; both in no particular order.
 constexpr int footprint_blocks(int N) { return (N + 7) / 8; }
 constexpr int footprint_zblocks(int N) { return (N + 31) / 32; }
 constexpr size_t footprint_z_offset(int N) { return (size_t)N * (1 + footprint_blocks(N)); }
 constexpr size_t footprint_list_offset(int N) { return (footprint_z_offset(N) + footprint_zblocks(N) + 3) & ~(size_t)3; }
-constexpr size_t footprint_bytes(int N) { return footprint_list_offset(N) + 8 + 4 * (size_t)N * N; }
+constexpr int kFootprintHeader = 4;  // words before the z list
+constexpr size_t footprint_bytes(int N) {
+  return footprint_list_offset(N) + 4 * (kFootprintHeader + (size_t)N * N + (size_t)N);
+}
 
 struct FootprintArgs {
   int interp, N;
@@ -39,7 +43,7 @@ struct FootprintArgs {
   int64_t n_pix;
 };
 // Three kernels: clear the marks and the list header, mark every pixel's stencil, list
-// the z blocks.
+// the z blocks and the planes.
 hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s);
 // Lines per z workgroup that launch_pass_z uses for (dtype, N) and a lines_z option
 // (0 = default); 0 if not compiled.

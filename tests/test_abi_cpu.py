@@ -105,9 +105,10 @@ def test_noise_tables_match_oracle(L):
 
 def test_footprint_bytes(L):
     """Marks (N planes + N ceil(N/8) row blocks + ceil(N/32) z blocks, padded to 4
-    bytes), the list header and room for one list entry per (ix, iy) line."""
+    bytes), the lists' header (4 words) and room for one z-list entry per (ix, iy) line
+    and one plane-list entry per plane."""
     for N in (8, 12, 48, 512, 1024):
         nb, nzb = (N + 7) // 8, (N + 31) // 32
-        assert L.cmbx_footprint_bytes(N) == (N * (1 + nb) + nzb + 3) // 4 * 4 + 8 + 4 * N * N
+        assert L.cmbx_footprint_bytes(N) == (N * (1 + nb) + nzb + 3) // 4 * 4 + 16 + 4 * N * N + 4 * N
     assert L.cmbx_footprint_bytes(4) == cmbx.EINVAL
     assert L.cmbx_footprint_bytes(2048) == cmbx.EINVAL

@@ -250,12 +250,13 @@ def _footprint_ref(N, L, r, dirs, K):
 @pytest.mark.parametrize("N", [12, 64, 512])
 def test_footprint_matches_definition(cmbx, N, interp):
     """Marks (planes, row blocks, z blocks) bit-exact against the definition; the z list
-    holds each block of `lines` lines with a marked line exactly once."""
+    holds each block of `lines` lines with a marked line exactly once, the plane list each
+    marked plane once."""
     L, K = 1.0, (4 if interp == "tricubic" else 2)
     p = cmbx.Plan(N, L, "f32", interp=interp)
     for turn, (theta, r) in enumerate([(20.0, 0.49), (35.0, 0.3), (5.0, 0.45)]):
         dn = _turned(workloads.cap_directions(theta, 48, 192), turn)
-        planes, blocks, zblocks, lines, lst = p.debug_footprint(r, torch.tensor(dn, device="cuda"))
+        planes, blocks, zblocks, lines, lst, plist = p.debug_footprint(r, torch.tensor(dn, device="cuda"))
         rp, rb, rz = _footprint_ref(N, L, r, dn, K)
         assert np.array_equal(planes, rp) and np.array_equal(blocks, rb), (N, interp, turn)
         assert np.array_equal(zblocks, rz), (N, interp, turn)
@@ -263,6 +264,7 @@ def test_footprint_matches_definition(cmbx, N, interp):
         line_marked = rb[np.arange(N * N) // N, (np.arange(N * N) % N) // 8].astype(bool)
         want = np.nonzero(line_marked.reshape(-1, lines).any(axis=1))[0]
         assert np.array_equal(lst, want.astype(np.uint32)), (N, interp, turn)
+        assert np.array_equal(plist, np.nonzero(rp)[0].astype(np.uint32)), (N, interp, turn)
     p.close()
 
 
