@@ -31,7 +31,7 @@ METRIC = "maps/s batched FP32 vs plain at 512³ box+cap sample, px err≤1e-5; H
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE, WRITE_SIZE (KiB per dispatch) of the noise + x kernel on the first
 # box (profile_run), by x tile width
-TRAFFIC_X = {8: (1440.31, 114141.0), 16: (1171.03, 116431.0)}
+TRAFFIC_X = {8: (1442.0, 114141.0), 16: (1170.81, 116431.0)}
 
 
 def support(N, L, k, p):
