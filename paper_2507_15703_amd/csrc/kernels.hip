@@ -475,9 +475,10 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int
 }
 
 // ------------------------------------------------------------------ map footprint
-// Mark what the K-point stencils of the pixels read: x-plane ix, the 8-row block of line
-// (ix, iy) and the 32-node z block. Many threads store the same byte 1; nothing else
-// writes it.
+// Mark what the K-point stencils of the pixels read: the 8-row block of line (ix, iy)
+// and the 32-node z block (the x-planes are flagged from the row blocks afterwards, by
+// k_zlist: every pixel would store into the same few bytes). Many threads store the same
+// byte 1; nothing else writes it.
 template <int K>
 __global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int N, double scale, double half,
                                                    double r, const double* __restrict__ dirs, int64_t npix) {
@@ -500,7 +501,6 @@ __global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int
 #pragma unroll
   for (int a = 0; a < K; ++a) {
     const int ix = wrap(i0[0] + a, N);
-    fp[ix] = 1;
     int prev = -1;
 #pragma unroll
     for (int b = 0; b < K; ++b) {
@@ -524,9 +524,10 @@ __device__ __forceinline__ void wave_append(bool need, uint32_t v, uint32_t* cou
   if (need) list[base + __popcll(m & ((1ull << lane) - 1))] = v;
 }
 
-// The work lists: one thread per block of `lines` consecutive (ix, iy) lines -- a block
-// that holds a line of a marked 8-row block goes to the z list -- and one per x-plane --
-// a marked plane goes to the plane list.
+// The plane flags and the work lists: one thread per block of `lines` consecutive
+// (ix, iy) lines -- a block that holds a line of a marked 8-row block goes to the z list
+// -- and one per x-plane -- a plane with a marked row block is flagged and goes to the
+// plane list.
 __global__ __launch_bounds__(256) void k_zlist(uint8_t* __restrict__ fp, int N, int lines) {
   const int nb = footprint_blocks(N);
   const int nblk = N * N / lines;
@@ -542,7 +543,17 @@ __global__ __launch_bounds__(256) void k_zlist(uint8_t* __restrict__ fp, int N, 
     }
   }
   wave_append(need, (uint32_t)b, &hdr[1], hdr + kFootprintHeader);
-  wave_append(b < N && fp[b] != 0, (uint32_t)b, &hdr[2], hdr + kFootprintHeader + N * N);
+  bool plane = false;
+  if (b < N) {
+    // OR of the plane's row-block flags, all loads in flight together
+    const uint8_t* row = fp + N + (size_t)b * nb;
+    uint32_t any = 0;
+#pragma unroll 16
+    for (int k = 0; k < nb; ++k) any |= row[k];
+    plane = any != 0;
+    if (plane) fp[b] = 1;
+  }
+  wave_append(plane, (uint32_t)b, &hdr[2], hdr + kFootprintHeader + N * N);
 }
 
 __global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
