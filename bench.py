@@ -149,8 +149,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--mode", default="auto", choices=["auto", "chained", "pipelined"],
                     help="ensemble execution mode of the batched path")
-    ap.add_argument("--lanes", type=int, default=None, choices=[1, 2],
-                    help="graphs the chained items are split over (default: auto mode times both)")
+    ap.add_argument("--lanes", type=int, default=None, choices=[1, 2, 3, 4],
+                    help="graphs the chained items are split over (default: auto mode times 1 .. 4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): independent realisations "

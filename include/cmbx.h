@@ -135,8 +135,10 @@ typedef struct cmbx_job {
 #define CMBX_ENS_CHAINED   1 /* each realisation's four kernels in turn, in its plan's workspace */
 #define CMBX_ENS_PIPELINED 2 /* software pipeline of fused launches (see below) */
 /* lane flags, OR-ed into the mode */
-#define CMBX_ENS_ONE_LANE  0x100 /* one graph on the launch stream */
-#define CMBX_ENS_TWO_LANES 0x200 /* chained items split by plan over two graphs on two streams */
+#define CMBX_ENS_LANES(n)  ((n) << 8) /* chained items split by plan over n graphs (1 <= n <= 4) */
+#define CMBX_ENS_ONE_LANE  CMBX_ENS_LANES(1) /* one graph on the launch stream */
+#define CMBX_ENS_TWO_LANES CMBX_ENS_LANES(2) /* two graphs on two streams */
+#define CMBX_ENS_MAX_LANES 4
 
 /*
  * Capture the jobs into one HIP graph. Every realisation of every job (job j's plan has
@@ -150,25 +152,27 @@ typedef struct cmbx_job {
  *   the ensemble.
  * - CMBX_ENS_AUTO: both are captured for each group and timed (the outputs are written
  *   meanwhile); the faster is kept (cmbx_ensemble_modes reports the choice).
- * Lanes: with CMBX_ENS_TWO_LANES the chained items are split by plan (all items of one plan
- * in one lane, since they share its workspace; heaviest plans first into the lighter lane)
- * into two graphs. Lane 0 (with every pipelined group) runs on the launch stream, lane 1
- * on a stream the ensemble owns, forked from and joined back into the launch stream, so
- * the chains of different plans can overlap on the device. With fewer than two chained
- * plans there is one lane. Without a lane flag, CMBX_ENS_AUTO times the whole ensemble
- * with the per-group choice on one lane and on two, and with every group chained on two
- * lanes, and keeps the fastest (so it may report a group chained that was faster
- * pipelined alone); the explicit modes use one lane. Launches of one ensemble must be
+ * Lanes: with CMBX_ENS_LANES(n) the chained items are split by plan (all items of one plan
+ * in one lane, since they share its workspace; heaviest plans first into the lightest
+ * lane) into n graphs. Lane 0 (with every pipelined group) runs on the launch stream,
+ * lanes 1 .. n-1 on streams the ensemble owns, forked from and joined back into the launch
+ * stream, so the chains of different plans can overlap on the device. There are never
+ * more lanes than chained plans. Without a lane flag, CMBX_ENS_AUTO times the whole
+ * ensemble with the per-group choice and with every group chained, on each possible
+ * number of lanes up to CMBX_ENS_MAX_LANES, and keeps the fastest (so it may report a
+ * group chained that was faster pipelined alone); the explicit modes use one lane. Launches of one ensemble must be
  * ordered (one launch stream, or synchronised).
  * Buffers passed in stay caller-owned and must outlive the ensemble, and so must the
  * plans, whose weight and twiddle tables and workspaces are used when the graph runs
  * (interpolant, prune option, r and pixel counts are fixed at creation; a pruning plan's
  * footprint is made from the directions at every launch). Errors: as cmbx_simulate_patch
- * for each job, CMBX_EINVAL for n_jobs < 1, an unknown mode or both lane flags,
+ * for each job, CMBX_EINVAL for n_jobs < 1, an unknown mode or more than
+ * CMBX_ENS_MAX_LANES lanes,
  * CMBX_ENOMEM.
  */
 int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemble** out);
-/* Number of lanes (1 or 2) the ensemble runs in, or CMBX_EINVAL for a NULL ensemble. */
+/* Number of lanes (1 .. CMBX_ENS_MAX_LANES) the ensemble runs in, or CMBX_EINVAL for a
+ * NULL ensemble. */
 int cmbx_ensemble_lanes(const cmbx_ensemble* ens);
 /* Mode chosen for each group (in order of first appearance) written to modes[0 .. cap);
  * returns the number of groups, or CMBX_EINVAL for a NULL ensemble. */

@@ -19,7 +19,7 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 F32, F64 = 1, 2
 TRILINEAR, TRICUBIC = 1, 2
 ENS_AUTO, ENS_CHAINED, ENS_PIPELINED = 0, 1, 2
-ENS_ONE_LANE, ENS_TWO_LANES = 0x100, 0x200
+ENS_ONE_LANE, ENS_TWO_LANES, ENS_MAX_LANES = 0x100, 0x200, 4
 OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y, OPT_PRUNE = 1, 2, 3, 4, 5, 6, 7
 
 _DTYPES = {"f32": F32, "float32": F32, F32: F32, "f64": F64, "float64": F64, F64: F64}
@@ -430,7 +430,7 @@ class Ensemble:
 
     def __init__(self, jobs, mode="auto", lanes=None):
         """jobs: list of dict(plan=Plan, seed, r, dirs=tensor, out=tensor). lanes: None
-        (auto mode times one and two lanes; explicit modes use one), 1 or 2."""
+        (auto mode times 1 .. 4 lanes; explicit modes use one) or 1 .. 4."""
         arr = (_Job * len(jobs))()
         self._keep = []
         for i, j in enumerate(jobs):
@@ -439,7 +439,9 @@ class Ensemble:
             arr[i] = _Job(p.handle, int(j["seed"]), float(j["r"]), d, n_pix, o)
             self._keep.append(j)
         h = ctypes.c_void_p()
-        flags = {None: 0, 1: ENS_ONE_LANE, 2: ENS_TWO_LANES}[lanes]
+        if lanes is not None and not 1 <= int(lanes) <= ENS_MAX_LANES:
+            raise ValueError(f"lanes must be 1 .. {ENS_MAX_LANES}")
+        flags = 0 if lanes is None else int(lanes) << 8
         _check(lib().cmbx_ensemble_create(arr, len(jobs), self._MODES.get(mode, mode) | flags, ctypes.byref(h)))
         self.handle = h.value
 

@@ -596,9 +596,10 @@ int capture(const std::vector<Group>& groups, const uint32_t* dsched, int only, 
   return CMBX_OK;
 }
 
-// Split the chained items over two lanes by plan, largest work first into the lighter
-// lane. Returns false (everything in lane 0) when fewer than two plans are chained.
-bool assign_lanes(std::vector<Group>& groups) {
+// Split the chained items over up to `want` lanes by plan, largest work first into the
+// lightest lane. Returns the number of lanes used: at most the number of chained plans
+// (1: everything in lane 0).
+int assign_lanes(std::vector<Group>& groups, int want) {
   std::vector<const cmbx_plan*> plans;
   std::vector<double> cost;
   for (Group& gr : groups) {
@@ -611,14 +612,15 @@ bool assign_lanes(std::vector<Group>& groups) {
       cost[k] += (double)it.plan->N * it.plan->N * it.plan->N + (double)it.n_pix;
     }
   }
-  if (plans.size() < 2) return false;
+  const int nl = std::min<int>(want, (int)plans.size());
+  if (nl < 2) return 1;
   std::vector<size_t> order(plans.size());
   for (size_t k = 0; k < order.size(); ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-  double load[2] = {0.0, 0.0};
+  std::vector<double> load(nl, 0.0);
   std::vector<int> lane_of(plans.size(), 0);
   for (size_t k : order) {
-    const int l = load[1] < load[0] ? 1 : 0;
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     lane_of[k] = l;
     load[l] += cost[k];
   }
@@ -629,7 +631,7 @@ bool assign_lanes(std::vector<Group>& groups) {
       while (plans[k] != it.plan) ++k;
       it.lane = lane_of[k];
     }
-  return true;
+  return nl;
 }
 
 void clear_lanes(cmbx_ensemble* en) {
@@ -736,13 +738,13 @@ double time_graph(hipGraphExec_t exec) {
 int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemble** out) {
   if (!out) return fail(CMBX_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!jobs || n_jobs < 1) return fail(CMBX_EINVAL, "need at least one job");
-  const int lanes_flag = mode & (CMBX_ENS_ONE_LANE | CMBX_ENS_TWO_LANES);
-  mode &= ~(CMBX_ENS_ONE_LANE | CMBX_ENS_TWO_LANES);
+  const int lanes_flag = (mode >> 8) & 7;  // lanes asked for, 0 = auto
+  mode &= ~0x700;
   if (mode != CMBX_ENS_AUTO && mode != CMBX_ENS_CHAINED && mode != CMBX_ENS_PIPELINED)
     return fail(CMBX_EINVAL, "unknown ensemble mode %d", mode);
-  if (lanes_flag == (CMBX_ENS_ONE_LANE | CMBX_ENS_TWO_LANES))
-    return fail(CMBX_EINVAL, "CMBX_ENS_ONE_LANE and CMBX_ENS_TWO_LANES exclude each other");
+  if (lanes_flag > CMBX_ENS_MAX_LANES)
+    return fail(CMBX_EINVAL, "%d lanes asked for; at most %d", lanes_flag, CMBX_ENS_MAX_LANES);
+  if (!jobs || n_jobs < 1) return fail(CMBX_EINVAL, "need at least one job");
   for (int j = 0; j < n_jobs; ++j) {
     if (!jobs[j].plan) return fail(CMBX_EINVAL, "job %d has no plan", j);
     if (int rc = check_patch_args(jobs[j].plan, jobs[j].r, jobs[j].dirs, jobs[j].n_pix, jobs[j].out)) {
@@ -880,41 +882,45 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
       groups[gi].mode = t[1] < t[0] ? CMBX_ENS_PIPELINED : CMBX_ENS_CHAINED;
     }
   }
-  // Lanes: with two, the chained items are split by plan (items of one plan share its
-  // workspace and stay in one lane) into two graphs that run on two streams.
+  // Lanes: the chained items are split by plan (items of one plan share its workspace and
+  // stay in one lane) into up to CMBX_ENS_MAX_LANES graphs that run on as many streams.
   std::vector<int> chosen;
   for (const Group& gr : groups) chosen.push_back(gr.mode);
-  auto set_modes = [&](const std::vector<int>& m) {
+  auto set_modes = [&](const std::vector<int>& m, int want) {
     for (size_t gi = 0; gi < groups.size(); ++gi) groups[gi].mode = m[gi];
-    return assign_lanes(groups);  // true if two lanes are possible
+    return assign_lanes(groups, want);  // lanes usable
   };
   if (mode != CMBX_ENS_AUTO || lanes_flag != 0) {
-    const bool two_possible = set_modes(chosen);
-    const int lanes = two_possible && lanes_flag == CMBX_ENS_TWO_LANES ? 2 : 1;
+    const int lanes = set_modes(chosen, lanes_flag > 0 ? lanes_flag : 1);
     if (int rc = build_lanes(en, groups, dsched, lanes)) return bail(rc, g_err);
   } else {
-    // AUTO: time the whole ensemble in each candidate -- the modes chosen per group on one
-    // and on two lanes, and every group chained on two lanes (the chains of different
-    // plans then overlap, which a group timed alone does not show) -- and keep the fastest
+    // AUTO: time the whole ensemble in each candidate -- the modes chosen per group, and
+    // every group chained (the chains of different plans then overlap, which a group
+    // timed alone does not show), on 1 .. CMBX_ENS_MAX_LANES lanes -- keep the fastest
     struct Cand {
       std::vector<int> modes;
       int lanes;
     };
-    std::vector<Cand> cands{{chosen, 1}};
-    if (set_modes(chosen)) cands.push_back({chosen, 2});
+    std::vector<Cand> cands;
     const std::vector<int> all_chained(groups.size(), CMBX_ENS_CHAINED);
-    if (all_chained != chosen && set_modes(all_chained)) cands.push_back({all_chained, 2});
+    for (const std::vector<int>* m : {(const std::vector<int>*)&chosen, &all_chained}) {
+      if (m == &all_chained && all_chained == chosen) break;
+      for (int want = 1; want <= CMBX_ENS_MAX_LANES; ++want) {
+        const int got = set_modes(*m, want);
+        if (got == want && !(m == &all_chained && want == 1)) cands.push_back({*m, want});
+      }
+    }
     double best_t = 1e300;
     size_t best = 0;
     for (size_t c = 0; c < cands.size() && cands.size() > 1; ++c) {
-      set_modes(cands[c].modes);
+      set_modes(cands[c].modes, cands[c].lanes);
       clear_lanes(en);
       if (int rc = build_lanes(en, groups, dsched, cands[c].lanes)) return bail(rc, g_err);
       const double t = time_ensemble(en);
       if (t < 0) return bail(CMBX_EHIP, "ensemble timing failed");
       if (t < best_t) best_t = t, best = c;
     }
-    set_modes(cands[best].modes);
+    set_modes(cands[best].modes, cands[best].lanes);
     clear_lanes(en);
     if (int rc = build_lanes(en, groups, dsched, cands[best].lanes)) return bail(rc, g_err);
   }

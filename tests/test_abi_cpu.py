@@ -112,3 +112,13 @@ def test_footprint_bytes(L):
         assert L.cmbx_footprint_bytes(N) == (N * (1 + nb) + nzb + 3) // 4 * 4 + 16 + 4 * N * N + 4 * N
     assert L.cmbx_footprint_bytes(4) == cmbx.EINVAL
     assert L.cmbx_footprint_bytes(2048) == cmbx.EINVAL
+
+
+def test_ensemble_rejects_too_many_lanes(L):
+    """More than four lanes is refused before anything touches the device (the flags are
+    checked before the job list)."""
+    h = ctypes.c_void_p()
+    rc = L.cmbx_ensemble_create(None, 0, (cmbx.ENS_MAX_LANES + 1) << 8, ctypes.byref(h))
+    assert rc == cmbx.EINVAL and "lanes" in cmbx.last_error()
+    rc = L.cmbx_ensemble_create(None, 0, cmbx.ENS_MAX_LANES << 8, ctypes.byref(h))
+    assert rc == cmbx.EINVAL and "job" in cmbx.last_error()

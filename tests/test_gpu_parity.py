@@ -511,10 +511,10 @@ def test_fault_injection_leaves_library_usable(cmbx, monkeypatch):
 
 
 # ------------------------------------------------------------------ ensemble (graph)
-@pytest.mark.parametrize("mode", ["chained", "pipelined", "auto", "chained-2-lanes"])
+@pytest.mark.parametrize("mode", ["chained", "pipelined", "auto", "chained-2-lanes", "chained-4-lanes"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_ensemble_graph_matches_plain_and_oracle(cmbx, dt, mode):
-    """The hipGraph ensemble (mixed sizes, batches, both interpolants; one lane or two) gives
+    """The hipGraph ensemble (mixed sizes, batches, both interpolants; one lane or several) gives
     the plain path's maps up to rounding, and the oracle's to the parity bar, on every
     replay."""
     specs = [(32, 3, 12.0, "tricubic"), (48, 2, 25.0, "trilinear"), (32, 1, 33.0, "tricubic"),
@@ -527,12 +527,12 @@ def test_ensemble_graph_matches_plain_and_oracle(cmbx, dt, mode):
         dirs = torch.tensor(dirs_np, device="cuda")
         out = torch.empty((batch, dirs.shape[0]), dtype=p.torch_dtype, device="cuda")
         jobs.append(dict(plan=p, seed=50 + 10 * i, r=0.45, dirs=dirs, out=out, dirs_np=dirs_np, k=k, pk=pk))
-    lanes = 2 if mode.endswith("2-lanes") else None
+    lanes = int(mode.split("-")[1]) if mode.endswith("lanes") else None
     mode = mode.split("-")[0]
     ens = cmbx.Ensemble([{kk: j[kk] for kk in ("plan", "seed", "r", "dirs", "out")} for j in jobs], mode=mode,
                         lanes=lanes)
     assert len(ens.modes) == 3 and (mode == "auto" or set(ens.modes) == {mode})
-    assert ens.lanes == (2 if lanes == 2 else ens.lanes) and ens.lanes in (1, 2)
+    assert ens.lanes == (lanes if lanes else ens.lanes) and 1 <= ens.lanes <= 4
     if mode == "pipelined":
         assert ens.lanes == 1
     refs = []
