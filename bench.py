@@ -85,7 +85,7 @@ def build_jobs(torch, cmbx, workloads, n_boxes):
         k, p = spectrum.synthetic_job_spectrum(N, L, j["r_over_L"] * L, j["theta_deg"], j["amp"])
         plan.spectrum_table(k, p)
         dirs = torch.tensor(workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"]), device="cuda")
-        tuned = plan.autotune(reps=5, r=j["r_over_L"] * L, dirs=dirs)
+        tuned = plan.autotune(reps=10, r=j["r_over_L"] * L, dirs=dirs)
         res = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
         out.append(dict(plan=plan, seed=j["seed"], r=j["r_over_L"] * L, dirs=dirs, out=res,
                         theta=j["theta_deg"], n_pix=int(dirs.shape[0]), tuned=tuned,

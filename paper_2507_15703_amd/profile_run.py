@@ -46,7 +46,7 @@ def main():
     if args.tile_xy or args.lines_z:
         plan.set_tiles(args.tile_xy, args.lines_z)
     else:
-        plan.autotune(reps=3, r=job["r_over_L"], dirs=dirs)  # the tile shapes bench.py uses
+        plan.autotune(reps=10, r=job["r_over_L"], dirs=dirs)  # as bench.py tunes
     out = torch.empty((1, dirs.shape[0]), dtype=plan.torch_dtype, device="cuda")
     seed, r = job["seed"], job["r_over_L"]
     plan.simulate_patch(seed, r, dirs, out)
