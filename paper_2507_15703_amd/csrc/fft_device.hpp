@@ -203,17 +203,27 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ tw, Src& sr
   dst.done();
 }
 
-// LDS-resident sequences. SEQFAST layout: element n of sequence q at n * NSEQ + q;
-// otherwise at q * L + n.
+// LDS-resident sequences. SEQFAST layout: element n of sequence q in row sw(n), at
+// sw(n) * NSEQ + q; otherwise at q * L + n. sw permutes the rows within aligned blocks of
+// the first stage's radix R0 (a power of two): it flips the low bits of n by the bits
+// above them, n ^ ((n / R0) & MASK). The first stage writes its output rows R0 apart, so
+// without it the lanes of one write land on the same few of the 64 four-byte banks; with
+// it the rows spread over the G = 256 B / row bytes row positions of a bank sweep. Reads,
+// which run over consecutive rows, keep their banks. sw is the identity for a radix-3
+// first stage.
 template <typename T, int L, int NSEQ, bool SEQFAST>
 struct LdsIO {
+  static constexpr int R0 = stage_radix(L, 0);
+  static constexpr bool POW2 = (R0 & (R0 - 1)) == 0;
+  static constexpr int BANK_CPX = 256 / (int)sizeof(cpx<T>);  // complex values in one sweep of the banks
+  // measured: the line layout (the z pass) runs slower permuted, so only rows are
+  static constexpr int G = SEQFAST ? (NSEQ >= BANK_CPX ? 1 : BANK_CPX / NSEQ) : 1;
+  static constexpr int MASK = POW2 ? (G < R0 ? G : R0) - 1 : 0;
+  __device__ static __forceinline__ int sw(int n) { return MASK ? n ^ ((n / R0) & MASK) : n; }
+  __device__ static __forceinline__ int index(int q, int n) { return SEQFAST ? sw(n) * NSEQ + q : q * L + sw(n); }
   cpx<T>* p;
-  __device__ __forceinline__ cpx<T> operator()(int q, int n) const {
-    return p[SEQFAST ? n * NSEQ + q : q * L + n];
-  }
-  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const {
-    p[SEQFAST ? n * NSEQ + q : q * L + n] = v;
-  }
+  __device__ __forceinline__ cpx<T> operator()(int q, int n) const { return p[index(q, n)]; }
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const { p[index(q, n)] = v; }
   __device__ __forceinline__ void done() const { __syncthreads(); }
 };
 

@@ -70,14 +70,15 @@ struct KeptLinesIO {
 //   Z_k = (X_k + conj X_{M-k}) + i w^k (X_k - conj X_{M-k}),  w = exp(2 pi i / N),
 //   Z_0 = (a + b) + i (a - b)   with X_0 = a, X_{N/2} = b (column 0 holds a + i b),
 // whose inverse M-point DFT z_n gives the real outputs x_{2n} = Re z_n, x_{2n+1} = Im z_n.
-template <typename T, int M>
+template <typename T, int M, int LINES>
 struct HalfToComplex {
+  using Lds = LdsIO<T, M, LINES, false>;  // the tile's layout
   const cpx<T>* x;
   const cpx<T>* tw;  // N = 2M roots
   __device__ __forceinline__ cpx<T> operator()(int q, int k) const {
-    const cpx<T> xk = x[q * M + k];
+    const cpx<T> xk = x[Lds::index(q, k)];
     if (k == 0) return {xk.x + xk.y, xk.x - xk.y};
-    const cpx<T> xc = conj(x[q * M + (M - k)]);
+    const cpx<T> xc = conj(x[Lds::index(q, M - k)]);
     return (xk + xc) + mul_i(cmul(tw[k], xk - xc));
   }
   __device__ __forceinline__ void done() const { __syncthreads(); }
@@ -124,6 +125,7 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   constexpr int M = N / 2;
   constexpr int PAIRS = TZ / 2;
   static_assert(M % TZ == 0 && TZ % 2 == 0, "tile must divide N/2 and be even");
+  using Lds = LdsIO<T, N, TZ, true>;  // the tile's layout, as the transform reads it
   cpx<T>* tile = smem;
   cpx<T>* tw = smem + N * TZ;
   const int tid = threadIdx.x;
@@ -149,8 +151,8 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
     for (int ix = tid; ix < N; ix += NT) {
       const cpx<T> a = mode_value<T>(N, ix, iy, 0, k0, k1, wtab, wself, tab);
       const cpx<T> b = mode_value<T>(N, ix, iy, M, k0, k1, wtab, wself, tab);
-      tile[ix * TZ] = {a.x - b.y, a.y + b.x};  // Z_0 + i Z_{N/2}
-      tile[ix * TZ + 1] = mode_value<T>(N, ix, iy, 1, k0, k1, wtab, wself, tab);
+      tile[Lds::index(0, ix)] = {a.x - b.y, a.y + b.x};  // Z_0 + i Z_{N/2}
+      tile[Lds::index(1, ix)] = mode_value<T>(N, ix, iy, 1, k0, k1, wtab, wself, tab);
     }
   }
   // every other pair of columns (2p, 2p + 1) holds two generic modes drawn from one
@@ -162,14 +164,14 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
     if (zc == 0) continue;
     const int m0 = freq2(ix, N) + fy2 + zc * zc;
     if (m0 > m_hi) {  // both modes beyond the spectrum's support: +0, no draw, no load
-      tile[ix * TZ + 2 * pr] = {T(0), T(0)};
-      tile[ix * TZ + 2 * pr + 1] = {T(0), T(0)};
+      tile[Lds::index(2 * pr, ix)] = {T(0), T(0)};
+      tile[Lds::index(2 * pr + 1, ix)] = {T(0), T(0)};
       continue;
     }
     const int m1 = m0 + 2 * zc + 1;
     const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
-    tile[ix * TZ + 2 * pr] = weighted<T>(wtab[m0], w.x, w.y, tab);
-    tile[ix * TZ + 2 * pr + 1] = weighted<T>(wtab[m1], w.z, w.w, tab);
+    tile[Lds::index(2 * pr, ix)] = weighted<T>(wtab[m0], w.x, w.y, tab);
+    tile[Lds::index(2 * pr + 1, ix)] = weighted<T>(wtab[m1], w.z, w.w, tab);
   }
   __syncthreads();
   LdsIO<T, N, TZ, true> first{tile};
@@ -257,23 +259,24 @@ __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict
       if (!__syncthreads_or(any)) return;
     }
   }
+  using Lds = LdsIO<T, M, LINES, false>;  // the tile's layout, as the transform reads it
   cpx<T>* g = buf + (size_t)blk * LINES * M;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   if constexpr (NT % M == 0) {
     // a thread meets one column only: its test is taken once, and its loads stay batched
     if ((tid % M) * (tid % M) > m_hi) {
-      for (int i = tid; i < LINES * M; i += NT) tile[i] = {T(0), T(0)};
+      for (int i = tid; i < LINES * M; i += NT) tile[Lds::index(i / M, i % M)] = {T(0), T(0)};
     } else {
-      for (int i = tid; i < LINES * M; i += NT) tile[i] = g[i];
+      for (int i = tid; i < LINES * M; i += NT) tile[Lds::index(i / M, i % M)] = g[i];
     }
   } else {
     for (int i = tid; i < LINES * M; i += NT) {
       const int zc = i % M;
-      tile[i] = zc * zc > m_hi ? cpx<T>{T(0), T(0)} : g[i];
+      tile[Lds::index(i / M, zc)] = zc * zc > m_hi ? cpx<T>{T(0), T(0)} : g[i];
     }
   }
   __syncthreads();
-  HalfToComplex<T, M> first{tile, tw};
+  HalfToComplex<T, M, LINES> first{tile, tw};
   KeptLinesIO<T, M, LINES> last{g, keep, fp ? keep_lds : nullptr, zmask};
   fft_run<T, M, LINES, NT, false, 2, 0>(tw, tile, first, last);
 }
