@@ -31,7 +31,7 @@ METRIC = "maps/s batched FP32 vs plain at 512³ box+cap sample, px err≤1e-5; H
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE, WRITE_SIZE (KiB per dispatch) of the noise + x kernel on the first
 # box (profile_run), by x tile width
-TRAFFIC_X = {8: (1442.0, 114141.0), 16: (1170.81, 116431.0)}
+TRAFFIC_X = {8: (1456.47, 114141.0), 16: (1170.5, 116431.0)}
 
 
 def support(N, L, k, p):
@@ -142,8 +142,8 @@ def cpu_baseline(jobs_meta, frac_planes=16):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--boxes", type=int, default=4, help="512^3 boxes per step (<= 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
