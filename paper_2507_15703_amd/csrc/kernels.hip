@@ -118,34 +118,47 @@ struct ZShape {
 // FP32 TZ = 16) to the strided x axis. smem: N TZ + N complex (tile, then twiddles), then
 // for binary32 the Box-Muller tables. With a map footprint `fp`, only the rows ix of the
 // x-planes that the map's stencils read are written (the transform itself is whole).
+// LDS of the x pass after the tile: N twiddles, then for binary32 the Box-Muller tables.
+template <typename T, int N, int TZ>
+struct XLds {
+  static constexpr int TW = N * TZ;                 // twiddles, in cpx<T>
+  static constexpr int TAB = TW + N;                // binary32 tables
+  static constexpr int SIZE = TAB + tab_cpx<T>();   // cpx<T> units
+};
+
+// Twiddles, binary32 tables and the footprint's plane flags into LDS (once per workgroup;
+// the caller synchronises before the first tile).
 template <typename T, int N, int TZ, int NT>
-__device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __restrict__ buf,
-                                       const T* __restrict__ wtab, const cpx<T>* __restrict__ twg, uint32_t k0,
-                                       uint32_t k1, int m_hi, const uint8_t* __restrict__ fp) {
+__device__ __forceinline__ void x_setup(cpx<T>* smem, const cpx<T>* __restrict__ twg,
+                                        const uint8_t* __restrict__ fp, uint8_t* planes) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) smem[XLds<T, N, TZ>::TW + i] = twg[i];
+  if constexpr (tab_cpx<T>() > 0) {
+    float* tab = reinterpret_cast<float*>(smem + XLds<T, N, TZ>::TAB);
+    for (int i = tid; i < bmf::kTabSize; i += NT) tab[i] = g_bm_tab[i];
+  }
+  if (fp)
+    for (int i = tid; i < N; i += NT) planes[i] = fp[i];
+}
+
+// One tile: the modes of z tile zt (TZ packed columns) at row iy into LDS, the length-N
+// inverse transform along x, and the rows written (with a map footprint, only the rows ix
+// of the x-planes the map's stencils read; the transform itself is whole). Needs
+// x_setup's LDS and no thread still reading the tile of an earlier call.
+template <typename T, int N, int TZ, int NT>
+__device__ __forceinline__ void x_tile(cpx<T>* smem, int zt, int iy, cpx<T>* __restrict__ buf,
+                                       const T* __restrict__ wtab, uint32_t k0, uint32_t k1, int m_hi,
+                                       const uint8_t* planes) {
   constexpr int M = N / 2;
   constexpr int PAIRS = TZ / 2;
-  static_assert(M % TZ == 0 && TZ % 2 == 0, "tile must divide N/2 and be even");
   using Lds = LdsIO<T, N, TZ, true>;  // the tile's layout, as the transform reads it
   cpx<T>* tile = smem;
-  cpx<T>* tw = smem + N * TZ;
+  const cpx<T>* tw = smem + XLds<T, N, TZ>::TW;
+  const float* tab = tab_cpx<T>() > 0 ? reinterpret_cast<const float*>(smem + XLds<T, N, TZ>::TAB) : nullptr;
   const int tid = threadIdx.x;
   const int zc0 = zt * TZ;
   const T* wself = wtab + 3 * M * M + 1;
   const int fy2 = freq2(iy, N);
-  // Every mode of the tile (the packed plane iz = N/2 included) beyond the spectrum's
-  // support: its transform is zero, and pass y does not read those lines (it takes them
-  // as zero), so the tile is left as it is.
-  if (fy2 + zc0 * zc0 > m_hi) return;
-  __shared__ uint8_t planes[N];
-  if (fp)
-    for (int i = tid; i < N; i += NT) planes[i] = fp[i];
-  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
-  float* tab = nullptr;
-  if constexpr (tab_cpx<T>() > 0) {
-    tab = reinterpret_cast<float*>(smem + N * TZ + N);
-    for (int i = tid; i < bmf::kTabSize; i += NT) tab[i] = g_bm_tab[i];
-    __syncthreads();
-  }
   if (zc0 == 0) {
     // column 0 packs the Hermitian planes iz = 0 and N/2; column 1 is iz = 1
     for (int ix = tid; ix < N; ix += NT) {
@@ -174,9 +187,39 @@ __device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __r
     tile[Lds::index(2 * pr + 1, ix)] = weighted<T>(wtab[m1], w.z, w.w, tab);
   }
   __syncthreads();
-  LdsIO<T, N, TZ, true> first{tile};
-  KeptRowsColIO<T, 0> last{{buf + (size_t)iy * M + zc0, (size_t)N * M}, fp ? planes : nullptr};
+  Lds first{tile};
+  KeptRowsColIO<T, 0> last{{buf + (size_t)iy * M + zc0, (size_t)N * M}, planes};
   fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, first, last);
+}
+
+// Largest s with s^2 <= d (d >= 0, below 2^24).
+__device__ __forceinline__ int isqrt_floor(int d) {
+  int s = (int)sqrtf((float)d);
+  while (s * s > d) --s;
+  while ((s + 1) * (s + 1) <= d) ++s;
+  return s;
+}
+
+// Tiles of the x pass within the spectrum's support: z tile zt holds modes of nonzero
+// weight only for rows with fy^2 + (zt TZ)^2 <= m_hi, i.e. |fy| <= R(zt): the rows
+// 0 .. R and N - R .. N - 1, min(N, 2R + 1) of them (none if (zt TZ)^2 > m_hi).
+__host__ __device__ constexpr int x_rows_in_support(int N, int TZ, int zt, int R) {
+  return R < 0 ? 0 : (2 * R + 1 < N ? 2 * R + 1 : N);
+}
+
+// One pass-x workgroup per tile of the pipelined kernel (setup included).
+template <typename T, int N, int TZ, int NT>
+__device__ __forceinline__ void role_x(cpx<T>* smem, int zt, int iy, cpx<T>* __restrict__ buf,
+                                       const T* __restrict__ wtab, const cpx<T>* __restrict__ twg, uint32_t k0,
+                                       uint32_t k1, int m_hi, const uint8_t* __restrict__ fp) {
+  // Every mode of the tile (the packed plane iz = N/2 included) beyond the spectrum's
+  // support: its transform is zero, and pass y does not read those lines (it takes them
+  // as zero), so the tile is left as it is.
+  if (freq2(iy, N) + zt * TZ * zt * TZ > m_hi) return;
+  __shared__ uint8_t planes[N];
+  x_setup<T, N, TZ, NT>(smem, twg, fp, planes);
+  __syncthreads();
+  x_tile<T, N, TZ, NT>(smem, zt, iy, buf, wtab, k0, k1, m_hi, fp ? planes : nullptr);
 }
 
 // ------------------------------------------------------------------ pass 2: y
@@ -281,14 +324,44 @@ __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict
   fft_run<T, M, LINES, NT, false, 2, 0>(tw, tile, first, last);
 }
 
+// One workgroup per tile within the spectrum's support, listed by z tile (a prefix of the
+// per-zt row counts, made in LDS; rows in the order 0 .. R, N - R .. N - 1): tiles beyond
+// the support get no workgroup at all.
 template <typename T, int N, int TZ>
 __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __restrict__ buf,
                                                                  const T* __restrict__ wtab,
                                                                  const cpx<T>* __restrict__ twg,
                                                                  uint32_t k0, uint32_t k1, int m_hi,
                                                                  const uint8_t* __restrict__ fp) {
-  __shared__ cpx<T> smem[N * TZ + N + tab_cpx<T>()];
-  role_x<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, blockIdx.x, blockIdx.y, buf, wtab, twg, k0, k1, m_hi, fp);
+  constexpr int NT = XYShape<T, N, TZ>::NT;
+  constexpr int T_ = N / 2 / TZ;  // z tiles
+  __shared__ cpx<T> smem[XLds<T, N, TZ>::SIZE];
+  __shared__ uint8_t planes[N];
+  __shared__ int start[T_ + 1];   // first listed tile of each z tile
+  __shared__ int radius[T_];      // R(zt)
+  x_setup<T, N, TZ, NT>(smem, twg, fp, planes);
+  for (int zt = threadIdx.x; zt < T_; zt += NT) {
+    const int d = m_hi - zt * TZ * zt * TZ;
+    radius[zt] = d < 0 ? -1 : isqrt_floor(d);
+    start[zt + 1] = x_rows_in_support(N, TZ, zt, radius[zt]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    start[0] = 0;
+    for (int zt = 0; zt < T_; ++zt) start[zt + 1] += start[zt];
+  }
+  __syncthreads();
+  const int e = blockIdx.x;
+  if (e >= start[T_]) return;  // (the grid is the host's count of the same tiles)
+  int lo = 0, hi = T_ - 1;       // the z tile whose range holds e
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (start[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  const int k = e - start[lo], R = radius[lo];
+  const int iy = k <= R ? k : N - (start[lo + 1] - start[lo] - k);
+  x_tile<T, N, TZ, NT>(smem, lo, iy, buf, wtab, k0, k1, m_hi, fp ? planes : nullptr);
 }
 
 template <typename T, int N, int TZ>
@@ -677,9 +750,25 @@ constexpr int lines_choice(int N, int k) {
 
 using PassFn = hipError_t (*)(const FieldArgs&, hipStream_t);
 
+// Tiles of the x pass within the support (as k_pass_x lists them), at least one.
+inline int x_tiles_in_support(int N, int TZ, int m_hi) {
+  int total = 0;
+  for (int zt = 0; zt < N / 2 / TZ; ++zt) {
+    const int d = m_hi - zt * TZ * zt * TZ;
+    int R = -1;
+    if (d >= 0) {
+      R = (int)std::sqrt((double)d);
+      while (R * R > d) --R;
+      while ((R + 1) * (R + 1) <= d) ++R;
+    }
+    total += x_rows_in_support(N, TZ, zt, R);
+  }
+  return total > 0 ? total : 1;
+}
+
 template <typename T, int N, int TZ>
 hipError_t run_x(const FieldArgs& a, hipStream_t s) {
-  dim3 grid(N / 2 / TZ, N);
+  dim3 grid(x_tiles_in_support(N, TZ, a.m_hi));
   hipLaunchKernelGGL((k_pass_x<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
                      (const T*)a.wtab, (const cpx<T>*)a.tw, a.k0, a.k1, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
