@@ -165,12 +165,11 @@ constexpr bool plan_ok(int L, int i = 0, int prod = 1) {
 // j within one sequence (line tiles). src(seq, n) / dst(seq, n, v) access element n of a
 // sequence. tw is the table of NTW-th roots exp(2 pi i m / NTW), NTW = L * TWMUL.
 template <typename T, int L, int NSEQ, int NT, int R, int NS, bool SEQFAST, int TWMUL, class Src, class Dst>
-__device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ tw, Src& src, Dst& dst) {
+__device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ tw, Src& src, Dst& dst, int tid) {
   constexpr int J = L / R;
   constexpr int SLOTS = J * NSEQ;
   constexpr int PER = (SLOTS + NT - 1) / NT;
   constexpr bool FULL = (SLOTS % NT) == 0;
-  const int tid = threadIdx.x;
   cpx<T> v[PER][R];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -228,9 +227,11 @@ struct LdsIO {
 };
 
 // Run all stages of a length-L transform: stage 0 reads from `first`, the last stage
-// writes to `last`, stages in between go through the LDS sequences `lds`.
+// writes to `last`, stages in between go through the LDS sequences `lds`. `tid` is the
+// thread's index in the workgroup.
 template <typename T, int L, int NSEQ, int NT, bool SEQFAST, int TWMUL, int S, class First, class Last>
-__device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* lds, First& first, Last& last) {
+__device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* lds, First& first, Last& last,
+                                        int tid) {
   constexpr int NST = stage_count(L);
   static_assert(plan_ok(L), "unsupported transform length");
   if constexpr (S < NST) {
@@ -238,15 +239,15 @@ __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* l
     constexpr int NS = stage_stride(L, S);
     LdsIO<T, L, NSEQ, SEQFAST> mid{lds};
     if constexpr (S == 0 && NST == 1) {
-      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, last);
+      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, last, tid);
     } else if constexpr (S == 0) {
-      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, mid);
+      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, mid, tid);
     } else if constexpr (S == NST - 1) {
-      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, last);
+      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, last, tid);
     } else {
-      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, mid);
+      fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, mid, tid);
     }
-    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1>(tw, lds, first, last);
+    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1>(tw, lds, first, last, tid);
   }
 }
 
