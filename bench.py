@@ -31,7 +31,7 @@ METRIC = "maps/s batched FP32 vs plain at 512³ box+cap sample, px err≤1e-5; H
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE, WRITE_SIZE (KiB per dispatch) of the noise + x kernel on the first
 # box (profile_run), by x tile width
-TRAFFIC_X = {8: (1456.47, 114141.0), 16: (1170.5, 116431.0)}
+TRAFFIC_X = {4: (2755.3, 113286.5), 8: (2600.25, 114141.0), 16: (2610.85, 116431.0)}
 
 
 def support(N, L, k, p):
@@ -247,8 +247,7 @@ def main():
     # HBM bytes per launch of this kernel from rocprofv3 FETCH_SIZE (x2.0 calibration against
     # a plain copy) + WRITE_SIZE (x1.0), by tile width, for this box's spectrum (counters of
     # the current kernel code)
-    traffic_by_tile = {8: (TRAFFIC_X[8][0] * 2.0 + TRAFFIC_X[8][1]) * 1024,
-                       16: (TRAFFIC_X[16][0] * 2.0 + TRAFFIC_X[16][1]) * 1024}
+    traffic_by_tile = {t: (f * 2.0 + w) * 1024 for t, (f, w) in TRAFFIC_X.items()}
     tile_x = jobs[0]["tuned"]["tile_x"]
     roofline = {"kernel": names[0], "bound": "alu", "achieved": round(ach_ops / 1e12, 2),
                 "peak": round(alu_peak / 1e12, 2), "unit": "Tops/s", "frac": round(ach_ops / alu_peak, 4),
