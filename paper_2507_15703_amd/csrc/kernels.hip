@@ -407,10 +407,11 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __re
   }
 }
 
-// Without a footprint one workgroup per block of LINES lines. With one, a grid of at most
-// kZGrid workgroups walks the footprint's list of blocks that hold a read line (if the
-// list was made for another block size, every block, each checked line by line).
-constexpr int kZGrid = 1024;
+// Without a footprint one workgroup per block of LINES lines. With one, a grid of as many
+// workgroups as the device holds at once walks the footprint's list of blocks that hold
+// a read line (if the list was made for another block size, every block, each checked
+// line by line).
+constexpr int kZGrid = 1024;  // the y pass's walking grid (its tiles fit 2-4 per CU)
 
 template <typename T, int N, int LINES>
 __global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __restrict__ buf,
@@ -785,6 +786,18 @@ hipError_t run_x(const FieldArgs& a, hipStream_t s) {
                      (const T*)a.wtab, (const cpx<T>*)a.tw, a.k0, a.k1, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
 }
+// Workgroups of `kernel` resident on the current device at once (occupancy x CUs; taken
+// once per kernel, every device of a process being of one kind), 1024 if not known.
+template <typename K>
+int resident_grid(K kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess)
+    return 1024;
+  return per > 0 && cus > 0 ? per * cus : 1024;
+}
+
 template <typename T, int N, int TZ>
 hipError_t run_y(const FieldArgs& a, hipStream_t s) {
   constexpr int NWG = N / 2 / TZ * N;
@@ -796,7 +809,10 @@ hipError_t run_y(const FieldArgs& a, hipStream_t s) {
 template <typename T, int N, int LINES>
 hipError_t run_z(const FieldArgs& a, hipStream_t s) {
   constexpr int NBLK = N * N / LINES;
-  dim3 grid(a.fp && NBLK > kZGrid ? kZGrid : NBLK);
+  // z blocks are small (8-32 lines): a fixed grid either leaves CUs half full (8 lines)
+  // or runs a second partial round (16 lines: 3 workgroups per CU by registers)
+  static const int resident = resident_grid(k_pass_z<T, N, LINES>, ZShape<T, N, LINES>::NT);
+  dim3 grid(a.fp && NBLK > resident ? resident : NBLK);
   hipLaunchKernelGGL((k_pass_z<T, N, LINES>), grid, dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf,
                      (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
