@@ -274,6 +274,23 @@ int cmbx_tile_choices(int dtype, int N, int which, int* out);
 int cmbx_enqueue_stage(cmbx_plan* plan, int stage, uint64_t seed, void* buf, double r, const double* dirs,
                        int64_t n_pix, void* out, void* stream);
 
+/* ---- sky pixels ----
+ * HEALPix pixel centres of the cap centred on the pole (Sec. II D 1: for a cap about the
+ * pole the pixels to sample are the leading pixels of a HEALPix map in RING order;
+ * pixelization of Gorski et al., ApJ 622 (2005) 759). Resolution nside (1 .. 2^20): 12
+ * nside^2 pixels on rings 1 .. 4 nside - 1 from the pole. The cap holds every ring whose
+ * height z is >= z_min (z_min = cos theta_max); each ring's z is one correctly rounded
+ * FP64 quotient of integers, (3n^2 - i^2) / (3n^2) for polar rings and (4n - 2i) / (3n)
+ * for the others (south rings: the negated mirror), so the cut is reproducible.
+ * Sets *n_pix (host pointer, required) to the cap's pixel count. If dirs is not NULL
+ * (device memory, caller-owned, room for `capacity` pixels of 3 FP64 each), enqueues on
+ * `stream` (a hipStream_t; NULL = the null stream) the unit directions in RING order,
+ * (sin t cos phi, sin t sin phi, z) with sin t = sqrt((1 - z)(1 + z)): the `dirs` that
+ * cmbx_simulate_patch and the ensembles take. With dirs NULL the call touches no device.
+ * Errors: CMBX_EINVAL (n_pix NULL, nside out of range, z_min NaN, capacity < *n_pix: the
+ * count is still set), CMBX_EHIP. */
+int cmbx_healpix_cap(int64_t nside, double z_min, double* dirs, int64_t capacity, int64_t* n_pix, void* stream);
+
 /* ---- spectrum surrogate network (Sec. II B inversion, learned) ----
  * Building blocks of a small MLP that maps a C_l vector to a P_inf table. All pointers are
  * device memory, row-major, caller-owned; work is enqueued on `stream` (NULL = null

@@ -65,6 +65,7 @@ def lib():
             "cmbx_debug_field": (I, [P, U64, P]),
             "cmbx_debug_gather": (I, [P, P, D, P, I64, P]),
             "cmbx_footprint_bytes": (I64, [I]),
+            "cmbx_healpix_cap": (I, [I64, D, P, I64, ctypes.POINTER(I64), P]),
             "cmbx_plan_autotune_patch": (I, [P, I, D, P, I64, P, P]),
             "cmbx_debug_footprint": (I, [P, D, P, I64, P]),
             "cmbx_debug_passes": (I, [P, U64, I, P]),
@@ -161,6 +162,32 @@ def debug_gather(h, field, r, dirs, n_pix, out):
 
 
 # ------------------------------------------------------------------ owners
+def healpix_cap_count(nside, z_min):
+    """Pixels of the HEALPix (RING) cap of resolution nside holding the rings with z >= z_min
+    (host only)."""
+    n = ctypes.c_int64(0)
+    _check(lib().cmbx_healpix_cap(int(nside), float(z_min), None, 0, ctypes.byref(n), None))
+    return n.value
+
+
+def healpix_cap(nside, z_min, out=None, stream=None):
+    """Unit directions of that cap's pixels in RING order, made on the device: a
+    [n_pix, 3] float64 CUDA tensor (`out` if given, with room for them)."""
+    import torch
+    n = healpix_cap_count(nside, z_min)
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    if out.dim() != 2 or out.shape[1] != 3:
+        raise ValueError("out must be a [n_pix, 3] float64 CUDA tensor")
+    d = _ptr(out, n * 24, torch.float64, "out")
+    if n == 0:
+        return out[:0]
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    cnt = ctypes.c_int64(0)
+    _check(lib().cmbx_healpix_cap(int(nside), float(z_min), d, out.shape[0], ctypes.byref(cnt), s))
+    return out[:n]
+
+
 class Plan:
     """A box plan (N^3, side L, precision, batch) bound to a stream.
 

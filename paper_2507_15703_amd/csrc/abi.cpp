@@ -484,6 +484,21 @@ int cmbx_debug_gather(cmbx_plan* p, const void* field, double r, const double* d
   return ok();
 }
 
+int cmbx_healpix_cap(int64_t nside, double z_min, double* dirs, int64_t capacity, int64_t* n_pix, void* stream) {
+  if (!n_pix) return fail(CMBX_EINVAL, "healpix_cap: n_pix is NULL");
+  if (nside < 1 || nside > cmbx::kHealpixMaxNside)
+    return fail(CMBX_EINVAL, "healpix_cap: nside = %lld must be in [1, %lld]", (long long)nside,
+                (long long)cmbx::kHealpixMaxNside);
+  if (std::isnan(z_min)) return fail(CMBX_EINVAL, "healpix_cap: z_min is NaN");
+  const int64_t count = cmbx::healpix_cap_count(nside, z_min);
+  *n_pix = count;
+  if (!dirs) return ok();
+  if (capacity < count)
+    return fail(CMBX_EINVAL, "healpix_cap: capacity %lld < %lld pixels", (long long)capacity, (long long)count);
+  HIP_TRY(cmbx::launch_healpix_cap(nside, count, dirs, (hipStream_t)stream));
+  return ok();
+}
+
 int64_t cmbx_footprint_bytes(int N) {
   if (N < 8 || N > 1024) return fail(CMBX_EINVAL, "N = %d must be in [8, 1024]", N);
   return (int64_t)cmbx::footprint_bytes(N);

@@ -87,6 +87,12 @@ struct GatherArgs {
 };
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 
+// HEALPix RING pixel centres of the polar cap: the number of pixels in the rings with
+// z >= z_min (host only), and their unit directions, [count][3] FP64, for resolution n.
+int64_t healpix_cap_count(int64_t n, double z_min);
+hipError_t launch_healpix_cap(int64_t n, int64_t count, double* dirs, hipStream_t s);
+constexpr int64_t kHealpixMaxNside = int64_t(1) << 20;
+
 // Pipelined launch: one workgroup per schedule entry (role << 30 | index), role 0 = pass x
 // (tile index zt + (N/2/tx) iy), 1 = pass y (zt + (N/2/ty) ix), 2 = pass z (line block of
 // lz lines), 3 = gather (pixel block of 256). Each role works on its own buffer.

@@ -122,3 +122,29 @@ def test_ensemble_rejects_too_many_lanes(L):
     assert rc == cmbx.EINVAL and "lanes" in cmbx.last_error()
     rc = L.cmbx_ensemble_create(None, 0, cmbx.ENS_MAX_LANES << 8, ctypes.byref(h))
     assert rc == cmbx.EINVAL and "job" in cmbx.last_error()
+
+
+def test_healpix_cap_count_matches_oracle_host_only():
+    # the count path of cmbx_healpix_cap runs on the host and touches no device
+    import math
+    from oracle import healpix as hp
+    from paper_2507_15703_amd import cmbx
+    for n in (1, 2, 3, 7, 40, 333):
+        for z_min in (2.0, 1.0, 0.999, 2.0 / 3.0, 0.5, 1.0 / 3.0, 0.0, -1.0 / 3.0, -2.0 / 3.0, -0.999, -1.0,
+                      math.cos(math.radians(26.85))):
+            assert cmbx.healpix_cap_count(n, z_min) == hp.cap_count(n, z_min), (n, z_min)
+
+
+def test_healpix_cap_errors():
+    import ctypes
+    from paper_2507_15703_amd import cmbx
+    L = cmbx.lib()
+    cnt = ctypes.c_int64(-5)
+    assert L.cmbx_healpix_cap(0, 0.5, None, 0, ctypes.byref(cnt), None) == cmbx.EINVAL
+    assert L.cmbx_healpix_cap((1 << 20) + 1, 0.5, None, 0, ctypes.byref(cnt), None) == cmbx.EINVAL
+    assert L.cmbx_healpix_cap(4, float("nan"), None, 0, ctypes.byref(cnt), None) == cmbx.EINVAL
+    assert L.cmbx_healpix_cap(4, 0.5, None, 0, None, None) == cmbx.EINVAL
+    # too little room: refused before any device work, the count still set
+    assert L.cmbx_healpix_cap(4, -1.0, ctypes.c_void_p(256), 191, ctypes.byref(cnt), None) == cmbx.EINVAL
+    assert cnt.value == 192
+    assert "capacity" in cmbx.last_error()
