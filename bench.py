@@ -261,6 +261,22 @@ def main():
                     + 52 * j["n_pix"] for j in jobs) / nmaps
     path_gbs = map_bytes * value / 1e9
 
+    # HEALPix cap pixels made on the device (an input of the path, outside the step):
+    # nside 2048, 26.85 deg cap (2.7M pixels), 24 bytes written per pixel
+    hp_z = math.cos(math.radians(26.85))
+    hp_n = cmbx.healpix_cap_count(2048, hp_z)
+    hp_buf = torch.empty((hp_n, 3), dtype=torch.float64, device="cuda")
+    cmbx.healpix_cap(2048, hp_z, out=hp_buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cmbx.healpix_cap(2048, hp_z, out=hp_buf)
+    e1.record()
+    torch.cuda.synchronize()
+    hp_ms = e0.elapsed_time(e1) / 10
+    healpix = {"nside": 2048, "theta_max_deg": 26.85, "pixels": hp_n, "ms": round(hp_ms, 4),
+               "GBps": round(24 * hp_n / (hp_ms * 1e-3) / 1e9, 1)}
+
     result = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -286,6 +302,7 @@ def main():
         "kernels": kernels,
         "tiles": {k: jobs[0]["tuned"][k] for k in ("tile_x", "tile_y", "lines_z")},
         "roofline": roofline,
+        "healpix_cap": healpix,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
