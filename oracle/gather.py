@@ -38,17 +38,20 @@ def linear_kernel(x):
     return np.where(x < 1.0, 1.0 - x, 0.0)
 
 
-def positions(N, L, r, dirs):
-    """Grid-unit positions p (n_pix, 3) of the pixels, FP64, in the fixed operation order."""
+def positions(N, L, r, dirs, observer=None):
+    """Grid-unit positions p (n_pix, 3) of the pixels, FP64, in the fixed operation order:
+    p = (r n + o) (N / L), o the observer's position in the box (default the centre, L/2
+    on each axis). Sec. II D 1 places the box about the cap instead, centred on the cap's
+    axis at (1 + z_min)/2 of the radius: the observer then sits below the box centre."""
     dirs = np.asarray(dirs, dtype=np.float64)
     s = N / L
-    h = 0.5 * L
-    return (r * dirs + h) * s
+    o = np.full(3, 0.5 * L) if observer is None else np.asarray(observer, dtype=np.float64).reshape(3)
+    return (r * dirs + o) * s
 
 
-def stencil(N, L, r, dirs, interp):
+def stencil(N, L, r, dirs, interp, observer=None):
     """Node indices (n_pix, 3, K) and 1-D weights (n_pix, 3, K) of every pixel's stencil."""
-    p = positions(N, L, r, dirs)
+    p = positions(N, L, r, dirs, observer)
     i0 = np.floor(p)
     f = p - i0
     if interp == TRILINEAR:
@@ -62,11 +65,11 @@ def stencil(N, L, r, dirs, interp):
     return idx, w
 
 
-def gather(fld, L, r, dirs, interp):
+def gather(fld, L, r, dirs, interp, observer=None):
     """Interpolated field values at the pixels, FP64, shape (n_pix,)."""
     fld = np.asarray(fld, dtype=np.float64)
     N = fld.shape[0]
-    idx, w = stencil(N, L, r, dirs, interp)
+    idx, w = stencil(N, L, r, dirs, interp, observer)
     K = idx.shape[2]
     out = np.zeros(idx.shape[0])
     for a in range(K):

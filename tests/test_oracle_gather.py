@@ -82,3 +82,31 @@ def test_periodic_wrap():
                     acc += w * shifted[(i0[0] + a) % N, (i0[1] + b) % N, (i0[2] + c) % N]
         ref.append(acc)
     assert np.allclose(got, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("interp", [gather.TRILINEAR, gather.TRICUBIC])
+def test_observer_offset_is_a_periodic_shift(interp):
+    # moving the observer by whole cells samples the field shifted by those cells (the box
+    # is periodic); the default observer is the box centre
+    N, L, r = 16, 2.0, 0.7
+    rng = np.random.default_rng(7)
+    fld = rng.standard_normal((N, N, N))
+    dirs = workloads.cap_directions(35.0, 6, 24)
+    base = gather.gather(fld, L, r, dirs, interp)
+    np.testing.assert_array_equal(base, gather.gather(fld, L, r, dirs, interp, observer=(1.0, 1.0, 1.0)))
+    k = np.array([3, -2, -5])
+    obs = 0.5 * L + k * (L / N)
+    got = gather.gather(fld, L, r, dirs, interp, observer=obs)
+    ref = gather.gather(np.roll(fld, shift=tuple(-k), axis=(0, 1, 2)), L, r, dirs, interp)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+def test_observer_below_centre_reaches_node():
+    # observer lowered by s: the pixel straight up at radius r sits at height L/2 - s + r
+    N, L = 16, 1.0
+    rng = np.random.default_rng(3)
+    fld = rng.standard_normal((N, N, N))
+    c = N // 2
+    got = gather.gather(fld, L, 7 * L / N, np.array([[0.0, 0.0, 1.0]]), gather.TRICUBIC,
+                        observer=(0.5 * L, 0.5 * L, 0.5 * L - 4 * L / N))
+    assert abs(got[0] - fld[c, c, c + 3]) <= 1e-14
