@@ -10,9 +10,9 @@
  * ---------------------------------------
  * - Box: N^3 nodes, side L, node j at j L / N, periodic. N must be even, 8 <= N <= 1024,
  *   and of the form 2^a 3^b with N/2 also of that form.
- * - Observer at the box centre c = (L/2, L/2, L/2); pixel with unit direction n sits at
- *   c + r n. In grid units p = (r n + L/2) (N / L), evaluated in FP64; the stencil is
- *   chosen by floor(p) and node indices wrap modulo N.
+ * - Observer at the box centre c = (L/2, L/2, L/2) unless cmbx_plan_observer moves it;
+ *   pixel with unit direction n sits at c + r n. In grid units p = (r n + c) (N / L),
+ *   evaluated in FP64; the stencil is chosen by floor(p) and node indices wrap modulo N.
  * - Spectrum normalisation: the caller gives P_inf(k), the infinite-space spectrum with
  *   xi(r) = int d^3k P_inf e^{i k.r} (Sec. II A, eq. xiinfpinf); the box uses
  *   P_box = P_inf (2 pi / L)^3 (Sec. II C, eq. finalpbox with M = N) and drops k = 0.
@@ -87,6 +87,15 @@ int cmbx_plan_box(int N, double L, int dtype, int batch, cmbx_plan** out);
 /* Release a plan and its device memory (waits for its stream). NULL is accepted. */
 int cmbx_plan_destroy(cmbx_plan* plan);
 
+/* Observer position o = (x, y, z) in the box, in the units of L (default: the centre,
+ * L/2 each). Pixels then sit at o + r n: in grid units p = (r n + o) (N / L), in FP64 and
+ * in that order, every later gather, map and footprint of the plan (an ensemble keeps the
+ * position its plan had at creation). Sec. II D 1 places the box about the cap rather than
+ * about the observer: with the cap about +z at radius r, the box centre on the cap's axis
+ * at height r (1 + z_min) / 2 is the observer at (L/2, L/2, L/2 - r (1 + z_min) / 2); any
+ * position is reduced modulo the periodic box. CMBX_EINVAL for a non-finite coordinate. */
+int cmbx_plan_observer(cmbx_plan* plan, double x, double y, double z);
+
 /* Set a plan option (CMBX_OPT_*). CMBX_EINVAL for an unknown key or a bad value. */
 int cmbx_plan_set(cmbx_plan* plan, int key, int64_t value);
 
@@ -107,7 +116,8 @@ int cmbx_spectrum_table(cmbx_plan* plan, const double* k, const double* P_inf, i
 /*
  * Simulate the plan's batch and sample it on a sky patch (Sec. II D 1).
  *   seed   realisation b uses seed + b
- *   r      shell radius, 0 < r < L/2
+ *   r      shell radius, 0 < r < L/2 (observer at the centre; once cmbx_plan_observer has
+ *          moved it, any finite r > 0: keeping the cap inside the box is the caller's part)
  *   dirs   device FP64 [n_pix][3] unit vectors (caller-owned)
  *   out    device array [batch][n_pix] of the plan's precision (caller-owned)
  * The field of realisation b is left in the plan's workspace (cmbx_plan_info): the whole

@@ -51,6 +51,7 @@ def lib():
             "cmbx_plan_box": (I, [I, D, I, I, ctypes.POINTER(P)]),
             "cmbx_plan_destroy": (I, [P]),
             "cmbx_plan_set": (I, [P, I, I64]),
+            "cmbx_plan_observer": (I, [P, D, D, D]),
             "cmbx_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(I),
                                    ctypes.POINTER(P)]),
             "cmbx_spectrum_table": (I, [P, P, P, I64]),
@@ -224,6 +225,18 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_observer(self, position):
+        """Observer position (x, y, z) in the box, units of L (default: the centre)."""
+        x, y, z = (float(v) for v in position)
+        _check(lib().cmbx_plan_observer(self.handle, x, y, z))
+        self.observer = (x, y, z)
+
+    def observer_for_cap(self, r, z_min):
+        """The position that centres the box on the cap about +z at radius r whose edge is
+        z_min (Sec. II D 1: box centre at r (1 + z_min) / 2 on the cap's axis)."""
+        h = 0.5 * self.L
+        return (h, h, h - r * (1.0 + z_min) / 2.0)
 
     def set_prune(self, prune):
         self.prune = bool(prune)

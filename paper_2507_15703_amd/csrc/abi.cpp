@@ -22,6 +22,7 @@
 struct cmbx_plan {
   int N = 0;
   double L = 0;
+  double obs[3] = {0, 0, 0};  // observer position in the box (set to the centre at creation)
   int dtype = 0;
   int batch = 0;
   int device = 0;
@@ -177,6 +178,17 @@ int enqueue_field(const cmbx_plan* p, uint64_t seed, void* buf, hipStream_t s, c
   return CMBX_OK;
 }
 
+// Shell radius: with the observer at the box centre the whole sphere must lie in the box,
+// 0 < r < L/2; with the observer moved only the cap has to (the caller's part: the box is
+// periodic and any position is reduced into it), so r need only be positive and finite.
+int check_radius(const cmbx_plan* p, double r) {
+  const double h = 0.5 * p->L;
+  const bool centred = p->obs[0] == h && p->obs[1] == h && p->obs[2] == h;
+  if (centred && !(r > 0.0 && r < h)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2 = %g", r, h);
+  if (!(r > 0.0 && std::isfinite(r))) return fail(CMBX_EINVAL, "r = %g must be positive and finite", r);
+  return CMBX_OK;
+}
+
 int enqueue_gather(const cmbx_plan* p, const void* field, double r, const double* dirs, int64_t n_pix, void* out,
                    hipStream_t s) {
   cmbx::GatherArgs g{};
@@ -185,7 +197,7 @@ int enqueue_gather(const cmbx_plan* p, const void* field, double r, const double
   g.N = p->N;
   g.field = field;
   g.scale = (double)p->N / p->L;
-  g.half = 0.5 * p->L;
+  for (int d = 0; d < 3; ++d) g.obs[d] = p->obs[d];
   g.r = r;
   g.dirs = dirs;
   g.n_pix = n_pix;
@@ -204,7 +216,7 @@ int enqueue_footprint(const cmbx_plan* p, void* fp, double r, const double* dirs
   f.lines = lines > 0 ? lines : cmbx::resolve_lines_z(p->dtype, p->N, p->lines_z);
   f.fp = fp;
   f.scale = (double)p->N / p->L;
-  f.half = 0.5 * p->L;
+  for (int d = 0; d < 3; ++d) f.obs[d] = p->obs[d];
   f.r = r;
   f.dirs = dirs;
   f.n_pix = n_pix;
@@ -214,7 +226,7 @@ int enqueue_footprint(const cmbx_plan* p, void* fp, double r, const double* dirs
 
 int check_patch_args(const cmbx_plan* p, double r, const double* dirs, int64_t n_pix, const void* out) {
   if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set: call cmbx_spectrum_table first");
-  if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2 = %g", r, 0.5 * p->L);
+  if (int rc = check_radius(p, r)) return rc;
   if (n_pix < 1) return fail(CMBX_EINVAL, "n_pix = %lld must be >= 1", (long long)n_pix);
   if (n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "n_pix = %lld exceeds 2^31", (long long)n_pix);
   if (!dirs || !out) return fail(CMBX_EINVAL, "dirs and out must be non-NULL device pointers");
@@ -305,6 +317,7 @@ int cmbx_plan_box(int N, double L, int dtype, int batch, cmbx_plan** out) {
   cmbx_plan* p = new cmbx_plan;
   p->N = N;
   p->L = L;
+  p->obs[0] = p->obs[1] = p->obs[2] = 0.5 * L;
   p->dtype = dtype;
   p->batch = batch;
   hipError_t e = hipGetDevice(&p->device);
@@ -352,6 +365,16 @@ int cmbx_plan_destroy(cmbx_plan* p) {
   if (p->fp) (void)hipFree(p->fp);
   if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
   delete p;
+  return ok();
+}
+
+int cmbx_plan_observer(cmbx_plan* p, double x, double y, double z) {
+  if (int rc = check_plan(p)) return rc;
+  if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+    return fail(CMBX_EINVAL, "observer position must be finite");
+  p->obs[0] = x;
+  p->obs[1] = y;
+  p->obs[2] = z;
   return ok();
 }
 
@@ -476,7 +499,7 @@ int cmbx_debug_gather(cmbx_plan* p, const void* field, double r, const double* d
   if (int rc = check_plan(p)) return rc;
   if (!field) return fail(CMBX_EINVAL, "field is NULL");
   if ((uintptr_t)field % 16 != 0) return fail(CMBX_EINVAL, "field must be 16-byte aligned");
-  if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2", r);
+  if (int rc = check_radius(p, r)) return rc;
   if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "bad n_pix %lld", (long long)n_pix);
   if (!dirs || !out) return fail(CMBX_EINVAL, "dirs and out must be non-NULL");
   DeviceGuard g(p->device);
@@ -506,7 +529,7 @@ int64_t cmbx_footprint_bytes(int N) {
 
 int cmbx_debug_footprint(cmbx_plan* p, double r, const double* dirs, int64_t n_pix, void* fp) {
   if (int rc = check_plan(p)) return rc;
-  if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2", r);
+  if (int rc = check_radius(p, r)) return rc;
   if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "bad n_pix %lld", (long long)n_pix);
   if (!dirs || !fp) return fail(CMBX_EINVAL, "dirs and fp must be non-NULL");
   if ((uintptr_t)fp % 4 != 0) return fail(CMBX_EINVAL, "fp must be 4-byte aligned");
@@ -861,7 +884,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
           a.npix = it.n_pix;
           a.r = it.r;
           a.scale = (double)N / it.plan->L;
-          a.half = 0.5 * it.plan->L;
+          for (int d = 0; d < 3; ++d) a.obs[d] = it.plan->obs[d];
           a.cubic = it.plan->interp == CMBX_TRICUBIC;
         }
         gr.sched_off.push_back(sched.size());
@@ -1140,7 +1163,7 @@ int cmbx_plan_autotune(cmbx_plan* p, int reps, int* best, double* ms) {
 int cmbx_plan_autotune_patch(cmbx_plan* p, int reps, double r, const double* dirs, int64_t n_pix, int* best,
                              double* ms) {
   if (int rc = check_plan(p)) return rc;
-  if (!(r > 0.0 && r < 0.5 * p->L)) return fail(CMBX_EINVAL, "r = %g must satisfy 0 < r < L/2", r);
+  if (int rc = check_radius(p, r)) return rc;
   if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "bad n_pix %lld", (long long)n_pix);
   if (!dirs) return fail(CMBX_EINVAL, "dirs must be a non-NULL device pointer");
   return autotune(p, reps, best, ms, r, dirs, n_pix);

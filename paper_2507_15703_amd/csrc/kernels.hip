@@ -470,13 +470,14 @@ __device__ __forceinline__ int wrap(int i, int N) { return i < 0 ? i + N : (i >=
 // K-point stencil of pixel i. The gather and the map footprint both take their integer
 // decisions here.
 template <int K>
-__device__ __forceinline__ void stencil_origin(int N, double scale, double half, double r,
+__device__ __forceinline__ void stencil_origin(int N, double scale, double3 obs, double r,
                                                const double* __restrict__ dirs, int64_t i, int i0[3],
                                                double frac[3]) {
 #pragma clang fp contract(off)
+  const double o[3] = {obs.x, obs.y, obs.z};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    double p = (r * dirs[3 * i + d] + half) * scale;
+    double p = (r * dirs[3 * i + d] + o[d]) * scale;
     // any finite position is reduced modulo N; non-finite input samples node 0
     if (!(p > -1.0e9 && p < 1.0e9)) p = 0.0;
     const double fl = floor(p);
@@ -527,14 +528,14 @@ __device__ __forceinline__ T stencil_sum(const T* __restrict__ field, int N, con
 }
 
 template <typename T, int K>
-__device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N, double scale, double half,
+__device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N, double scale, double3 obs,
                                              double r, const double* __restrict__ dirs, int64_t i,
                                              T* __restrict__ out) {
   int i0[3];
   T w[3][4];
   {
     double frac[3];
-    stencil_origin<K>(N, scale, half, r, dirs, i, i0, frac);
+    stencil_origin<K>(N, scale, obs, r, dirs, i, i0, frac);
 #pragma unroll
     for (int d = 0; d < 3; ++d) weights1d<T>((T)frac[d], w[d], K == 4 ? kTricubic : kTrilinear);
   }
@@ -551,7 +552,7 @@ __device__ __forceinline__ void gather_pixel(const T* __restrict__ field, int N,
 
 // Blocks are assigned so that each XCD's L2 serves a contiguous pixel range.
 template <typename T, int K>
-__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int N, double scale, double half,
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int N, double scale, double3 obs,
                                                 double r, const double* __restrict__ dirs, int64_t npix,
                                                 T* __restrict__ out) {
   const int nb = gridDim.x;
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int
   const int logical = (nb % 8 == 0) ? (b % 8) * per + b / 8 : b;
   const int64_t i = (int64_t)logical * blockDim.x + threadIdx.x;
   if (i >= npix) return;
-  gather_pixel<T, K>(field, N, scale, half, r, dirs, i, out);
+  gather_pixel<T, K>(field, N, scale, obs, r, dirs, i, out);
 }
 
 // ------------------------------------------------------------------ map footprint
@@ -569,13 +570,13 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int
 // k_zlist: every pixel would store into the same few bytes). Many threads store the same
 // byte 1; nothing else writes it.
 template <int K>
-__global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int N, double scale, double half,
+__global__ __launch_bounds__(256) void k_footprint(uint8_t* __restrict__ fp, int N, double scale, double3 obs,
                                                    double r, const double* __restrict__ dirs, int64_t npix) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npix) return;
   int i0[3];
   double frac[3];
-  stencil_origin<K>(N, scale, half, r, dirs, i, i0, frac);
+  stencil_origin<K>(N, scale, obs, r, dirs, i, i0, frac);
   const int nb = footprint_blocks(N);
   // z blocks: every pixel's few bytes are the same handful for the whole map, so a byte
   // already set is only read (stores from every thread to one cache line would queue)
@@ -669,7 +670,8 @@ struct PipeArgs {
   const double* dirs;  // gather directions
   T* out;              // gather output
   int64_t npix;
-  double r, scale, half;
+  double r, scale;
+  double3 obs;         // observer position in the box
   int cubic;
   const cpx<T>* tw;    // twiddles of this N
 };
@@ -717,9 +719,9 @@ __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict
     const int64_t i = (int64_t)idx * kPipeNT + threadIdx.x;
     if (i < a.npix) {
       if (a.cubic)
-        gather_pixel<T, 4>(a.field_g, N, a.scale, a.half, a.r, a.dirs, i, a.out);
+        gather_pixel<T, 4>(a.field_g, N, a.scale, a.obs, a.r, a.dirs, i, a.out);
       else
-        gather_pixel<T, 2>(a.field_g, N, a.scale, a.half, a.r, a.dirs, i, a.out);
+        gather_pixel<T, 2>(a.field_g, N, a.scale, a.obs, a.r, a.dirs, i, a.out);
     }
   }
 }
@@ -843,7 +845,7 @@ hipError_t run_pipe(const PipeLaunch& a, hipStream_t s) {
   p.npix = a.npix;
   p.r = a.r;
   p.scale = a.scale;
-  p.half = a.half;
+  p.obs = make_double3(a.obs[0], a.obs[1], a.obs[2]);
   p.cubic = a.cubic;
   p.tw = (const cpx<T>*)a.tw;
   hipLaunchKernelGGL((k_pipeline<T, N, TX, TY, LZ>), dim3(a.nblocks), dim3(kPipeNT), 0, s, a.sched, p);
@@ -987,10 +989,10 @@ hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)a.fp, words);
   const dim3 grid((unsigned)((a.n_pix + 255) / 256));
   if (a.interp == kTricubic)
-    hipLaunchKernelGGL(k_footprint<4>, grid, dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.scale, a.half, a.r, a.dirs,
+    hipLaunchKernelGGL(k_footprint<4>, grid, dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.scale, make_double3(a.obs[0], a.obs[1], a.obs[2]), a.r, a.dirs,
                        a.n_pix);
   else
-    hipLaunchKernelGGL(k_footprint<2>, grid, dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.scale, a.half, a.r, a.dirs,
+    hipLaunchKernelGGL(k_footprint<2>, grid, dim3(256), 0, s, (uint8_t*)a.fp, a.N, a.scale, make_double3(a.obs[0], a.obs[1], a.obs[2]), a.r, a.dirs,
                        a.n_pix);
   const int threads = a.N * a.N / a.lines > a.N ? a.N * a.N / a.lines : a.N;  // per z block, and per plane
   hipLaunchKernelGGL(k_zlist, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, (uint8_t*)a.fp, a.N,
@@ -1011,11 +1013,11 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
   const bool cubic = a.interp == kTricubic;
   if (a.dtype == kF32) {
     auto k = cubic ? k_gather<float, 4> : k_gather<float, 2>;
-    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const float*)a.field, a.N, a.scale, a.half, a.r, a.dirs, a.n_pix,
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const float*)a.field, a.N, a.scale, make_double3(a.obs[0], a.obs[1], a.obs[2]), a.r, a.dirs, a.n_pix,
                        (float*)a.out);
   } else {
     auto k = cubic ? k_gather<double, 4> : k_gather<double, 2>;
-    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const double*)a.field, a.N, a.scale, a.half, a.r, a.dirs,
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const double*)a.field, a.N, a.scale, make_double3(a.obs[0], a.obs[1], a.obs[2]), a.r, a.dirs,
                        a.n_pix, (double*)a.out);
   }
   return hipGetLastError();

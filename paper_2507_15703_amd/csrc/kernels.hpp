@@ -37,7 +37,8 @@ struct FootprintArgs {
   int interp, N;
   int lines;           // z block (lines per z workgroup) the work list is for
   void* fp;            // footprint_bytes(N), cleared and filled by the launch
-  double scale, half;  // N / L and L / 2
+  double scale;        // N / L
+  double obs[3];       // observer position in the box (L / 2 each: the centre)
   double r;
   const double* dirs;  // [n_pix][3]
   int64_t n_pix;
@@ -79,7 +80,8 @@ hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uin
 struct GatherArgs {
   int dtype, interp, N;
   const void* field;   // [N][N][N] reals
-  double scale, half;  // N / L and L / 2
+  double scale;        // N / L
+  double obs[3];       // observer position in the box
   double r;
   const double* dirs;  // [n_pix][3]
   int64_t n_pix;
@@ -111,7 +113,8 @@ struct PipeLaunch {
   const double* dirs;
   void* out;
   int64_t npix;
-  double r, scale, half;
+  double r, scale;
+  double obs[3];
   int cubic;
   const void* tw;
 };

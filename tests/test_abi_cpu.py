@@ -148,3 +148,10 @@ def test_healpix_cap_errors():
     assert L.cmbx_healpix_cap(4, -1.0, ctypes.c_void_p(256), 191, ctypes.byref(cnt), None) == cmbx.EINVAL
     assert cnt.value == 192
     assert "capacity" in cmbx.last_error()
+
+
+def test_plan_observer_rejects_non_finite():
+    import ctypes
+    from paper_2507_15703_amd import cmbx
+    L = cmbx.lib()
+    assert L.cmbx_plan_observer(None, 0.5, 0.5, 0.5) == cmbx.EINVAL
