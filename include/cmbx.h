@@ -301,6 +301,18 @@ int cmbx_enqueue_stage(cmbx_plan* plan, int stage, uint64_t seed, void* buf, dou
  * count is still set), CMBX_EHIP. */
 int cmbx_healpix_cap(int64_t nside, double z_min, double* dirs, int64_t capacity, int64_t* n_pix, void* stream);
 
+/* ---- covariance test of the maps ----
+ * Pixel covariance of a sky map with angular power spectrum C_l (Sec. III B tests the
+ * maps against it; eq. harmonics): gamma[i][j] = sum_{l=0}^{lmax} (2l + 1) C_l
+ * P_l(n_i . n_j) / (4 pi), with n_i . n_j clamped to [-1, 1], for i, j < n_pix, FP64,
+ * row-major. dirs ([n_pix][3] unit directions), cl (lmax + 1 values) and gamma
+ * (n_pix^2 values) are device memory, caller-owned; enqueued on `stream` (a hipStream_t,
+ * NULL = the null stream). P_l comes from the three-term recurrence in FP64. Whitening and
+ * the KS test on the result are left to the caller. Errors: CMBX_EINVAL (NULL pointer,
+ * n_pix outside [1, 1048560], lmax outside [0, 65536]), CMBX_EHIP. */
+int cmbx_pixel_covariance(const double* dirs, int64_t n_pix, const double* cl, int lmax, double* gamma,
+                          void* stream);
+
 /* ---- spectrum surrogate network (Sec. II B inversion, learned) ----
  * Building blocks of a small MLP that maps a C_l vector to a P_inf table. All pointers are
  * device memory, row-major, caller-owned; work is enqueued on `stream` (NULL = null

@@ -19,7 +19,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libcmbx.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["kernels.hip", "mlp.hip", "healpix.hip", "abi.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "healpix.hip", "covariance.hip", "abi.cpp"]
 # calibration program of the ALU roofline's peak (standalone executable, not in the library)
 CALIB = os.path.join(OUT_DIR, "valu_rate")
 ARCH = "gfx950"

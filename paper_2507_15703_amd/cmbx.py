@@ -67,6 +67,7 @@ def lib():
             "cmbx_debug_gather": (I, [P, P, D, P, I64, P]),
             "cmbx_footprint_bytes": (I64, [I]),
             "cmbx_healpix_cap": (I, [I64, D, P, I64, ctypes.POINTER(I64), P]),
+            "cmbx_pixel_covariance": (I, [P, I64, P, I, P, P]),
             "cmbx_plan_autotune_patch": (I, [P, I, D, P, I64, P, P]),
             "cmbx_debug_footprint": (I, [P, D, P, I64, P]),
             "cmbx_debug_passes": (I, [P, U64, I, P]),
@@ -187,6 +188,23 @@ def healpix_cap(nside, z_min, out=None, stream=None):
     cnt = ctypes.c_int64(0)
     _check(lib().cmbx_healpix_cap(int(nside), float(z_min), d, out.shape[0], ctypes.byref(cnt), s))
     return out[:n]
+
+
+def pixel_covariance(dirs, cl, out=None, stream=None):
+    """Covariance [n_pix, n_pix] (float64 CUDA tensor) of maps with spectrum cl (l = 0 ..
+    len(cl) - 1) at the unit directions dirs ([n_pix, 3] float64 CUDA tensor)."""
+    import torch
+    if dirs.dim() != 2 or dirs.shape[1] != 3:
+        raise ValueError("dirs must be a [n_pix, 3] float64 CUDA tensor")
+    n = dirs.shape[0]
+    cl = torch.as_tensor(cl, dtype=torch.float64, device=dirs.device).contiguous()
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float64, device=dirs.device)
+    d = _ptr(dirs, n * 24, torch.float64, "dirs")
+    g = _ptr(out, n * n * 8, torch.float64, "out")
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().cmbx_pixel_covariance(d, n, cl.data_ptr(), cl.numel() - 1, g, s))
+    return out
 
 
 class Plan:

@@ -522,6 +522,18 @@ int cmbx_healpix_cap(int64_t nside, double z_min, double* dirs, int64_t capacity
   return ok();
 }
 
+int cmbx_pixel_covariance(const double* dirs, int64_t n_pix, const double* cl, int lmax, double* gamma,
+                          void* stream) {
+  if (!dirs || !cl || !gamma) return fail(CMBX_EINVAL, "pixel_covariance: NULL pointer");
+  if (n_pix < 1 || n_pix > cmbx::kCovMaxPixels)
+    return fail(CMBX_EINVAL, "pixel_covariance: n_pix = %lld must be in [1, %lld]", (long long)n_pix,
+                (long long)cmbx::kCovMaxPixels);
+  if (lmax < 0 || lmax > cmbx::kCovMaxL)
+    return fail(CMBX_EINVAL, "pixel_covariance: lmax = %d must be in [0, %d]", lmax, cmbx::kCovMaxL);
+  HIP_TRY(cmbx::launch_pixel_cov(dirs, n_pix, cl, lmax, gamma, (hipStream_t)stream));
+  return ok();
+}
+
 int64_t cmbx_footprint_bytes(int N) {
   if (N < 8 || N > 1024) return fail(CMBX_EINVAL, "N = %d must be in [8, 1024]", N);
   return (int64_t)cmbx::footprint_bytes(N);

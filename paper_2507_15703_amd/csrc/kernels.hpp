@@ -95,6 +95,13 @@ int64_t healpix_cap_count(int64_t n, double z_min);
 hipError_t launch_healpix_cap(int64_t n, int64_t count, double* dirs, hipStream_t s);
 constexpr int64_t kHealpixMaxNside = int64_t(1) << 20;
 
+// Pixel covariance Gamma [n][n] FP64 of unit directions dirs [n][3] for C_l, l = 0 .. lmax
+// (all device memory); n <= kCovMaxPixels (the grid's y extent), lmax <= kCovMaxL.
+hipError_t launch_pixel_cov(const double* dirs, int64_t n, const double* cl, int lmax, double* gamma,
+                            hipStream_t s);
+constexpr int64_t kCovMaxPixels = int64_t(65535) * 16;
+constexpr int kCovMaxL = 1 << 16;
+
 // Pipelined launch: one workgroup per schedule entry (role << 30 | index), role 0 = pass x
 // (tile index zt + (N/2/tx) iy), 1 = pass y (zt + (N/2/ty) ix), 2 = pass z (line block of
 // lz lines), 3 = gather (pixel block of 256). Each role works on its own buffer.

@@ -155,3 +155,16 @@ def test_plan_observer_rejects_non_finite():
     from paper_2507_15703_amd import cmbx
     L = cmbx.lib()
     assert L.cmbx_plan_observer(None, 0.5, 0.5, 0.5) == cmbx.EINVAL
+
+
+def test_pixel_covariance_argument_errors():
+    # refused before any device work
+    from paper_2507_15703_amd import cmbx
+    L = cmbx.lib()
+    p = 256
+    assert L.cmbx_pixel_covariance(None, 4, p, 2, p, None) == cmbx.EINVAL
+    assert L.cmbx_pixel_covariance(p, 0, p, 2, p, None) == cmbx.EINVAL
+    assert L.cmbx_pixel_covariance(p, 65535 * 16 + 1, p, 2, p, None) == cmbx.EINVAL
+    assert L.cmbx_pixel_covariance(p, 4, p, -1, p, None) == cmbx.EINVAL
+    assert L.cmbx_pixel_covariance(p, 4, p, (1 << 16) + 1, p, None) == cmbx.EINVAL
+    assert "lmax" in cmbx.last_error()
