@@ -277,6 +277,25 @@ def main():
     healpix = {"nside": 2048, "theta_max_deg": 26.85, "pixels": hp_n, "ms": round(hp_ms, 4),
                "GBps": round(24 * hp_n / (hp_ms * 1e-3) / 1e9, 1)}
 
+    # pixel covariance from C_l for the covariance test of the maps (outside the step):
+    # nside 128, 20 deg HEALPix cap, lmax 1000; 4 FP64 operations per entry and l
+    cv_dirs = cmbx.healpix_cap(128, math.cos(math.radians(20.0)))
+    cv_n, cv_l = cv_dirs.shape[0], 1000
+    cv_cl = 1.0 / (1.0 + torch.arange(cv_l + 1, dtype=torch.float64, device="cuda")) ** 2
+    cv_out = torch.empty((cv_n, cv_n), dtype=torch.float64, device="cuda")
+    cmbx.pixel_covariance(cv_dirs, cv_cl, out=cv_out)
+    e0.record()
+    for _ in range(5):
+        cmbx.pixel_covariance(cv_dirs, cv_cl, out=cv_out)
+    e1.record()
+    torch.cuda.synchronize()
+    cv_ms = e0.elapsed_time(e1) / 5
+    cv_ops = 4.0 * cv_n * cv_n * (cv_l + 1)
+    covariance = {"nside": 128, "theta_max_deg": 20.0, "pixels": cv_n, "lmax": cv_l, "ms": round(cv_ms, 3),
+                  "Tops": round(cv_ops / (cv_ms * 1e-3) / 1e12, 2),
+                  "alu_frac": round(cv_ops / (cv_ms * 1e-3) / alu_peak, 4)}
+    del cv_out
+
     result = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -303,6 +322,7 @@ def main():
         "tiles": {k: jobs[0]["tuned"][k] for k in ("tile_x", "tile_y", "lines_z")},
         "roofline": roofline,
         "healpix_cap": healpix,
+        "pixel_covariance": covariance,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
