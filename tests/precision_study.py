@@ -1,7 +1,7 @@
 """Precision study: FP32 and FP64 maps of the HIP path against the FP64 oracle.
 
     python tests/precision_study.py --N 1024 --cap 40 --rings 4096 --phi 2048 \
-        --out gpurun_out/precision_1024.json
+        --out precision_1024.json
 
 One realisation (Philox seed --seed) of the box N^3, L = 1, shell r = 0.45 L, on the
 polar cap of half-angle --cap as rings uniform in cos(theta) x equally spaced azimuths,

@@ -1,7 +1,7 @@
 """What the trained spectrum surrogate gains over the plain inversion, judged by the oracle.
 
     python tests/surrogate_study.py [--weights W.npz] [--n 64] [--n-maps 4] [--seeds 64] \
-        [--out gpurun_out/sur.json]
+        [--out sur.json]
 
 Held-out spectra (shape parameters of seeds 5000 .. 5000 + n - 1, damping l_d uniform in
 [0.4, 0.8] l_max) at 256^3, r = 0.45 L, on the 30-degree cap. Each spectrum goes through

@@ -3,9 +3,7 @@
 Both sides sum the same series in FP64, the oracle with SciPy's Legendre polynomials, the
 kernel by the three-term recurrence; the bar, max|dGamma| <= 1e-12 max|Gamma|, bounds
 the recurrence's rounding (about l ulp) for l up to 700. Sizes span several 16 x 16 tiles
-with ragged edges. The whitening of GPU maps closes the loop: maps of a plan whose spectrum
-has support on a single shell are checked for finiteness of the whitened vector only (the
-paper's KS verdict needs its added-noise sweep, outside this test).
+with ragged edges.
 """
 import math
 
