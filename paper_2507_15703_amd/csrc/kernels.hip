@@ -811,8 +811,8 @@ hipError_t run_y(const FieldArgs& a, hipStream_t s) {
 template <typename T, int N, int LINES>
 hipError_t run_z(const FieldArgs& a, hipStream_t s) {
   constexpr int NBLK = N * N / LINES;
-  // z blocks are small (8-32 lines): a fixed grid either leaves CUs half full (8 lines)
-  // or runs a second partial round (16 lines: 3 workgroups per CU by registers)
+  // a walking grid of what the device holds at once: a fixed one ran a second, partial
+  // round of workgroups for blocks of 16 and 32 lines
   static const int resident = resident_grid(k_pass_z<T, N, LINES>, ZShape<T, N, LINES>::NT);
   dim3 grid(a.fp && NBLK > resident ? resident : NBLK);
   hipLaunchKernelGGL((k_pass_z<T, N, LINES>), grid, dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf,
