@@ -98,3 +98,34 @@ def test_ensemble_keeps_observer_of_creation(env):
     np.testing.assert_array_equal(out.cpu().numpy()[0], ref)
     ens.close()
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["pipelined", "chained"])
+def test_ensemble_modes_follow_moved_observer(env, mode):
+    # the pipelined kernel carries the observer in its own arguments: both modes against
+    # the plan's plain maps, for two plans with different observers
+    cmbx, torch = env
+    from paper_2507_15703_amd import workloads
+    jobs, refs = [], []
+    for i, (N, theta) in enumerate([(48, 20.0), (48, 30.0), (48, 12.0), (48, 25.0)]):
+        k, p = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=12)
+        z_min = math.cos(math.radians(theta))
+        r = 0.7
+        plan = cmbx.Plan(N, 1.0, "f32", interp="tricubic" if i % 2 == 0 else "trilinear")
+        plan.spectrum_table(k, p)
+        plan.set_observer(plan.observer_for_cap(r, z_min))
+        dirs = cmbx.healpix_cap(16, z_min)
+        out = torch.empty((1, dirs.shape[0]), dtype=torch.float32, device="cuda")
+        jobs.append(dict(plan=plan, seed=70 + i, r=r, dirs=dirs, out=out))
+        refs.append(plan.simulate_patch(70 + i, r, dirs).cpu().numpy()[0])
+    print(f"[observer] ensemble {mode}", flush=True)
+    ens = cmbx.Ensemble([dict(j) for j in jobs], mode=mode)
+    for _ in range(2):
+        ens.launch()
+        torch.cuda.synchronize()
+        for j, ref in zip(jobs, refs):
+            got = j["out"].cpu().numpy()[0]
+            assert np.max(np.abs(got - ref)) / np.sqrt(np.mean(ref**2)) <= 1e-6, (mode, j["plan"].N)
+    ens.close()
+    for j in jobs:
+        j["plan"].close()
