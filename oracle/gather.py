@@ -65,9 +65,17 @@ def stencil(N, L, r, dirs, interp, observer=None):
     return idx, w
 
 
-def gather(fld, L, r, dirs, interp, observer=None):
-    """Interpolated field values at the pixels, FP64, shape (n_pix,)."""
+def gather(fld, L, r, dirs, interp, observer=None, threads=None, chunk=1 << 16):
+    """Interpolated field values at the pixels, FP64, shape (n_pix,). threads > 1 evaluates
+    chunks of ``chunk`` pixels in that many threads (each pixel's sum is the same)."""
     fld = np.asarray(fld, dtype=np.float64)
+    dirs = np.asarray(dirs, dtype=np.float64)
+    if threads is not None and threads > 1 and dirs.shape[0] > chunk:
+        from concurrent.futures import ThreadPoolExecutor
+        starts = range(0, dirs.shape[0], chunk)
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            parts = ex.map(lambda i: gather(fld, L, r, dirs[i:i + chunk], interp, observer), starts)
+            return np.concatenate(list(parts))
     N = fld.shape[0]
     idx, w = stencil(N, L, r, dirs, interp, observer)
     K = idx.shape[2]

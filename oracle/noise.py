@@ -45,9 +45,11 @@ def _normals_chunk(args):
     return unit_normals(N, seed, np.arange(x0, x1), rdt)
 
 
-def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32, workers=None):
+def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32, workers=None, threads=None):
     """The weighted half grid, complex array of shape (N, N, N/2 + 1), complex128 or complex64.
-    workers > 1 draws the normals of independent x-chunks in that many processes."""
+    workers > 1 draws the normals of independent x-chunks in that many processes; threads > 1
+    in that many threads of this process instead (NumPy's array loops release the GIL), for
+    callers that must not fork, such as a process that already drives a GPU."""
     if N % 2:
         raise ValueError("N must be even")
     rdt = np.dtype(dtype)
@@ -57,7 +59,11 @@ def halfgrid(N, L, seed, k_tab, p_tab, dtype=np.float64, chunk=32, workers=None)
     full = full.astype(rdt)
     out = np.empty((N, N, N // 2 + 1), dtype=cdt)
     jobs = [(N, seed, x0, min(N, x0 + chunk), rdt) for x0 in range(0, N, chunk)]
-    if workers is not None and workers > 1 and len(jobs) > 1:
+    if threads is not None and threads > 1 and len(jobs) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        ex = ThreadPoolExecutor(max_workers=threads)
+        normals = ex.map(_normals_chunk, jobs)
+    elif workers is not None and workers > 1 and len(jobs) > 1:
         from concurrent.futures import ProcessPoolExecutor
         ex = ProcessPoolExecutor(max_workers=workers)
         normals = ex.map(_normals_chunk, jobs)

@@ -3,9 +3,7 @@
 Usage: ``python -m paper_2507_15703_amd.build`` or ``build()`` from Python. The device code
 is compiled with packed FP32 instructions disabled (-packed-fp32-ops) and -O3; the
 translation units are compiled in parallel and linked into one shared library that
-exports the C ABI of ``include/cmbx.h``. Beside it, ``_lib/valu_rate`` (from
-``csrc/valu_rate.hip``) measures the device's issue rate of plain vector operations, the
-calibration of the noise pass's ALU roofline.
+exports the C ABI of ``include/cmbx.h``.
 """
 import os
 import shutil
@@ -20,8 +18,6 @@ LIB = os.path.join(OUT_DIR, "libcmbx.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["kernels.hip", "mlp.hip", "healpix.hip", "covariance.hip", "abi.cpp"]
-# calibration program of the ALU roofline's peak (standalone executable, not in the library)
-CALIB = os.path.join(OUT_DIR, "valu_rate")
 ARCH = "gfx950"
 
 
@@ -54,16 +50,8 @@ def build(verbose=False):
             print(" ".join(cmd), flush=True)
         return obj
 
-    def compile_calib():
-        cmd = [hipcc] + flags() + ["-x", "hip", os.path.join(CSRC, "valu_rate.hip"), "-o", CALIB]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"compile of valu_rate.hip failed:\n{r.stderr[-4000:]}")
-
-    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
-        calib = ex.submit(compile_calib)
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-        calib.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

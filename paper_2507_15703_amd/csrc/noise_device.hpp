@@ -13,7 +13,8 @@
 //   ln u1, u1 = (a + 1) 2^-32: a + 1 = m 2^e with m in [1/sqrt2, sqrt2); ln u1 =
 //     (e - 32) ln2_head + ((e - 32) ln2_tail + 2 s P(s^2)), s = (m - 1)/(m + 1) with the
 //     reciprocal from five Newton steps started at 1/2, P the artanh series to s^20;
-//   sqrt x: four Newton steps for 1/sqrt(x) from the integer-shift seed, times x;
+//   sqrt x: four Newton steps for 1/sqrt(x) from the integer-shift seed (the binary64
+//     magic constant of Lomont, "Fast inverse square root", 2003), times x;
 //   cos, sin of 2 pi b 2^-32: quadrant from the top two bits, the rest folded to
 //     t in [0, pi/4] with sin/cos swapped when folded, Taylor series to t^17 / t^18.
 // Single-precision plans use their own binary32 sequence with small tables (below);
@@ -46,7 +47,7 @@ constexpr double kLn2Head = 0x1.62e42fefa3000p-1;  // ln 2 with 12 low mantissa 
 constexpr double kLn2Tail = 0x1.3de6af278ece6p-42; // ln 2 - head, rounded
 constexpr double kSqrt2 = 0x1.6a09e667f3bcdp+0;
 constexpr double kTwoPi2m32 = 0x1.921fb54442d18p-30;  // 2 pi / 2^32, rounded
-constexpr uint64_t kRsqrtMagic = 0x5FE6EB50C7B537A9ull;
+constexpr uint64_t kRsqrtMagic = 0x5FE6EB50C7B537A9ull;  // Lomont (2003), binary64 seed of 1/sqrt
 
 constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }  // exact up to 18!
 constexpr double sgn(int k) { return (k & 1) ? -1.0 : 1.0; }
@@ -128,7 +129,7 @@ constexpr float kLn2Tail = 0x1.7f7d1cp-20f;  // ln 2 - head, rounded to binary32
 constexpr float kTwoPi2m32 = 0x1.921fb6p-30f;
 constexpr float kThird = 0x1.555556p-2f;     // 1/3 rounded to binary32
 constexpr float kSixth = 0x1.555556p-3f;     // 1/6 rounded to binary32
-constexpr uint32_t kRsqrtMagic = 0x5F3759DFu;
+constexpr uint32_t kRsqrtMagic = 0x5F3759DFu;  // the binary32 fast-inverse-square-root seed (Lomont 2003)
 constexpr uint32_t kFoldJ = 54;              // entries with c_j = 1 + j/128 >= sqrt 2 hold ln(c_j / 2)
 // table layout (binary32): ln c_j (or ln(c_j / 2)) and 1 / c_j for j = 0..127, then
 // sin and cos of (k + 1/2) 2 pi / 256 for k = 0..255

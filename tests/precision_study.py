@@ -52,15 +52,17 @@ def spectrum_input(N, cap_deg):
     return cl, k, p
 
 
-def oracle_map(N, seed, k, p, dirs, workers, say, chunk=1 << 20):
-    h = onoise.halfgrid(N, 1.0, seed, k, p, workers=workers)
+def oracle_map(N, seed, k, p, dirs, workers, say, chunk=1 << 20, threads=None):
+    """The FP64 oracle's map: noise in `workers` processes (only before this process uses
+    the GPU) or `threads` threads, the inverse FFT and the gather on as many threads."""
+    h = onoise.halfgrid(N, 1.0, seed, k, p, workers=workers, threads=threads)
     say("oracle half grid")
-    fld = ofield.field(h, workers=workers)
+    fld = ofield.field(h, workers=threads or workers)
     del h
     say("oracle field")
     out = np.empty(dirs.shape[0])
     for i in range(0, dirs.shape[0], chunk):
-        out[i:i + chunk] = ogather.gather(fld, 1.0, R_OVER_L, dirs[i:i + chunk], "tricubic")
+        out[i:i + chunk] = ogather.gather(fld, 1.0, R_OVER_L, dirs[i:i + chunk], "tricubic", threads=threads)
     say("oracle map")
     return out
 
@@ -83,7 +85,9 @@ def gpu_map(N, dtype, seed, k, p, dirs_dev, reps=3):
         plan.close()
 
 
-def run(N=256, cap_deg=30.0, n_ring=1024, n_phi=1024, seed=1, workers=None, log=True):
+def run(N=256, cap_deg=30.0, n_ring=1024, n_phi=1024, seed=1, workers=None, log=True, threads=None):
+    """The study's result dict. `workers` (processes) only in a process that has not used
+    the GPU yet; inside a test session pass `threads` instead."""
     import torch
     t0 = time.time()
     say = (lambda m: _log(m, t0)) if log else (lambda m: None)
@@ -91,7 +95,7 @@ def run(N=256, cap_deg=30.0, n_ring=1024, n_phi=1024, seed=1, workers=None, log=
     say(f"spectrum table ({k.size} nodes)")
     dirs = workloads.cap_directions(cap_deg, n_ring, n_phi)
     # the oracle (and its worker processes) runs before this process touches the GPU
-    ref = oracle_map(N, seed, k, p, dirs, workers, say)
+    ref = oracle_map(N, seed, k, p, dirs, workers, say, threads=threads)
     dirs_dev = torch.tensor(dirs, device="cuda")
     m32, ms32 = gpu_map(N, "f32", seed, k, p, dirs_dev)
     say(f"gpu f32 map ({ms32:.2f} ms per map)")
