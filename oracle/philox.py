@@ -50,18 +50,20 @@ def seed_key(seed):
     return seed & 0xFFFFFFFF, seed >> 32
 
 
-def mode_words(seed, ix, iy, iz):
+def mode_words(seed, ix, iy, iz, stream=0):
     """The two 32-bit words that drive the normal pair of half-grid mode (ix, iy, iz).
 
-    Counter = (iz >> 1, iy, ix, 0), key = the seed's two words. One Philox call serves the
-    two neighbouring modes iz = 2q and 2q + 1: the even one takes words (x0, x1), the odd
-    one (x2, x3). The first word feeds the Box-Muller radius, the second its angle.
+    Counter = (iz >> 1, iy, ix, stream), key = the seed's two words. One Philox call serves
+    the two neighbouring modes iz = 2q and 2q + 1: the even one takes words (x0, x1), the
+    odd one (x2, x3). The first word feeds the Box-Muller radius, the second its angle.
+    The fourth counter word separates the streams of the box kinds: 0 for the cubic box,
+    1 for the layers of the 2-D (hybrid) method, 2 for the flat N x N x M box.
     """
     ix = np.asarray(ix, dtype=np.uint64)
     iy = np.asarray(iy, dtype=np.uint64)
     iz = np.asarray(iz, dtype=np.uint64)
     k0, k1 = seed_key(seed)
-    x0, x1, x2, x3 = philox4x32_10((iz >> np.uint64(1), iy, ix, np.uint64(0)), (k0, k1))
+    x0, x1, x2, x3 = philox4x32_10((iz >> np.uint64(1), iy, ix, np.uint64(stream)), (k0, k1))
     odd = (iz & np.uint64(1)) == np.uint64(1)
     a = np.where(odd, x2, x0)
     b = np.where(odd, x3, x1)
