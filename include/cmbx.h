@@ -70,6 +70,22 @@ extern "C" {
  * call); 0: from the whole field. The maps are the same either way (Sec. II D 1: the box
  * is simulated and then sampled; only the samples are the product). */
 #define CMBX_OPT_PRUNE    7
+/* 1: the caller keeps the directions at a given address unchanged (the paper's batches of
+ * maps of one cap, Sec. IV). A pruning plan then makes the map footprint once per
+ * (r, dirs, n_pix, interpolant, z tile, observer) and reuses it in later
+ * cmbx_simulate_patch calls, and an ensemble created from it makes its footprints once at
+ * creation instead of inside its graph at every launch. Setting the option (again, to 0
+ * or 1) drops the kept footprint: do so after writing new directions at the same address.
+ * Default 0: the footprint is made from the directions at every call. */
+#define CMBX_OPT_FIXED_DIRS 8
+/* FFT stage plan of the x, y and z pass: 0 (default) or 1, an alternative factorisation of
+ * the transform length into radix stages (e.g. 512 = 16 x 8 x 4 instead of 8 x 8 x 8,
+ * 256 = 4 x 8 x 8 instead of 16 x 16), compiled for lengths with a power-of-two part of at
+ * least 32 and for the pass's default tile only: setting plan 1 sets that tile, and
+ * setting another tile sets plan 0. cmbx_plan_autotune chooses among them. */
+#define CMBX_OPT_PLAN_X   9
+#define CMBX_OPT_PLAN_Y   10
+#define CMBX_OPT_PLAN_Z   11
 
 typedef struct cmbx_plan cmbx_plan;
 typedef struct cmbx_ensemble cmbx_ensemble;
@@ -98,6 +114,11 @@ int cmbx_plan_observer(cmbx_plan* plan, double x, double y, double z);
 
 /* Set a plan option (CMBX_OPT_*). CMBX_EINVAL for an unknown key or a bad value. */
 int cmbx_plan_set(cmbx_plan* plan, int key, int64_t value);
+
+/* Read an option back (CMBX_OPT_INTERP, _TILE_X, _TILE_Y, _LINES_Z (the tiles in use, the
+ * defaults resolved), _PRUNE, _FIXED_DIRS, _PLAN_X/Y/Z) into *value. CMBX_EINVAL for a NULL
+ * plan or value or another key. */
+int cmbx_plan_get(const cmbx_plan* plan, int key, int64_t* value);
 
 /* Read back a plan's geometry: any output pointer may be NULL. */
 int cmbx_plan_info(const cmbx_plan* plan, int* N, double* L, int* dtype, int* batch,
@@ -175,7 +196,8 @@ typedef struct cmbx_job {
  * Buffers passed in stay caller-owned and must outlive the ensemble, and so must the
  * plans, whose weight and twiddle tables and workspaces are used when the graph runs
  * (interpolant, prune option, r and pixel counts are fixed at creation; a pruning plan's
- * footprint is made from the directions at every launch). Errors: as cmbx_simulate_patch
+ * footprint is made from the directions at every launch, or once at creation if the plan
+ * has CMBX_OPT_FIXED_DIRS). Errors: as cmbx_simulate_patch
  * for each job, CMBX_EINVAL for n_jobs < 1, an unknown mode or more than
  * CMBX_ENS_MAX_LANES lanes,
  * CMBX_ENOMEM.
@@ -250,12 +272,13 @@ int cmbx_time_passes(cmbx_plan* plan, uint64_t seed, double r, const double* dir
                      void* out, int reps, double* ms);
 
 /*
- * Autotune the plan's workgroup shapes by coordinate descent (two sweeps over tile_x,
- * tile_y, lines_z): each compiled choice (cmbx_tile_choices) of one shape, the other two
- * held at their best so far, is timed with HIP events over `reps` runs of the whole
- * x -> y -> z chain on the plan's stream (one pass's write pattern changes the cost of the
- * next, so a kernel timed alone can mislead); the fastest chain's shapes become the plan's
- * options. best[0..2] receives (tile_x, tile_y, lines_z) and ms[0..2] the average
+ * Autotune the plan's workgroup shapes and FFT stage plans by coordinate descent (two
+ * sweeps over the x, y and z pass): each compiled choice of one pass -- every tile
+ * (cmbx_tile_choices) with stage plan 0, and the default tile with stage plan 1 where
+ * compiled -- the other two held at their best so far, is timed with HIP events over
+ * `reps` runs of the whole x -> y -> z chain on the plan's stream (one pass's write pattern
+ * changes the cost of the next, so a kernel timed alone can mislead); the fastest chain's
+ * shapes and plans become the plan's options (cmbx_plan_get reads them back). best[0..2] receives (tile_x, tile_y, lines_z) and ms[0..2] the average
  * milliseconds of each pass alone at those shapes (either may be NULL). Needs a spectrum
  * (CMBX_ESTATE otherwise); overwrites the first workspace slot; synchronises the plan's
  * stream.
@@ -283,6 +306,80 @@ int cmbx_tile_choices(int dtype, int N, int which, int* out);
  */
 int cmbx_enqueue_stage(cmbx_plan* plan, int stage, uint64_t seed, void* buf, double r, const double* dirs,
                        int64_t n_pix, void* out, void* stream);
+
+/* ---- flat boxes: the 3-D method on N x N x M and the 2-D (hybrid) method ----
+ * Sec. II C sizes the box as N x N points across and M along the line of sight z, all
+ * spaced dp, so P_box = P_inf (2 pi / dp)^3 / (M N^2) (eq. finalpbox) at
+ * |k| = (2 pi / dp) sqrt((fx^2 + fy^2) / N^2 + fz^2 / M^2). A slab plan makes nz layers of
+ * such a box, real [nz][N][N] (y fastest), node (ix, iy, j) at (ix dp, iy dp, j dp),
+ * periodic in x and y:
+ *   CMBX_SLAB_FLAT   -- the 3-D Fourier method (Sec. II D 1) on the whole N x N x M box,
+ *                       nz = M, periodic in z. Modes of the half grid in y (iy = 0 .. N/2,
+ *                       all ix, iz) from Philox counter (iz >> 1, iy, ix, 2), words
+ *                       (x0, x1) / (x2, x3) for even / odd iz, the canonical Box-Muller
+ *                       of the plan precision; generic modes sqrt(P_box / 2) (g_re + i g_im);
+ *                       on the planes iy = 0, N/2 the mode and (-ix, -iz) are conjugate
+ *                       (the smaller ix M + iz drawn), the self-conjugate ones real,
+ *                       sqrt(P_box) g_re. Field: the unnormalised + sign inverse DFT.
+ *   CMBX_SLAB_HYBRID -- the 2-D Fourier method (Sec. II D 2): only the layers j = 0 .. h-1
+ *                       (nz = h <= 32), made in hybrid space (k_x, k_y, z): per column the
+ *                       h values are S g, S the symmetric square root P D^{1/2} P^T of the
+ *                       column covariance Gamma_jk = xi(|j - k| dp), xi the transform
+ *                       along z of P_box over the M values of f_z (eq. gammasvd; same
+ *                       statistics as P D^{1/2}, unique), formed once per spectrum on the
+ *                       host in FP64 (Jacobi eigendecomposition, negative eigenvalues of
+ *                       rounding set to 0) and rounded to the plan precision; g: h normal
+ *                       pairs from Philox counter (j >> 1, iy, ix, 1), divided by sqrt 2
+ *                       for generic columns, the real part only for the four
+ *                       self-conjugate ones; rows iy = 0, N/2 Hermitian in x. Then the
+ *                       inverse 2-D DFT of every layer.
+ * Pixels: p = (r n + o) (1 / dp) per axis in FP64; x, y wrap modulo N; z wraps modulo M on
+ * the flat box, and on the hybrid layers a pixel whose stencil leaves [0, h) is NaN
+ * (place the layers about the cap with cmbx_slab_observer). Default observer: the middle
+ * of the layers, (N dp / 2, N dp / 2, (nz - 1) dp / 2).
+ * Sizes: N as for cmbx_plan_box (2^a 3^b, 8 .. 1024); flat: M even, 2^a 3^b, 8 .. 512;
+ * hybrid: 2 <= M (even), 1 <= h <= min(M, 32); nz N a multiple of a compiled z tile. */
+#define CMBX_SLAB_FLAT   1
+#define CMBX_SLAB_HYBRID 2
+typedef struct cmbx_slab cmbx_slab;
+
+/* Create a slab plan (method, N, M, h (ignored for CMBX_SLAB_FLAT: h = M), dp > 0, dtype,
+ * batch >= 1). It owns batch x nz x N^2 reals of workspace, the twiddles and, once a
+ * spectrum is set, the per-column tables. Errors: CMBX_EINVAL, CMBX_EUNSUPPORTED (sizes not
+ * compiled), CMBX_ENOMEM, CMBX_EHIP. */
+int cmbx_slab_create(int method, int N, int M, int h, double dp, int dtype, int batch, cmbx_slab** out);
+int cmbx_slab_destroy(cmbx_slab* slab);
+/* CMBX_OPT_INTERP and CMBX_OPT_STREAM as for plans; CMBX_EINVAL otherwise. */
+int cmbx_slab_set(cmbx_slab* slab, int key, int64_t value);
+/* Observer position o in box coordinates (the length unit of dp and r); CMBX_EINVAL if not
+ * finite. Sec. II D 2 centres the h layers on the cap: o_z = (h - 1) dp / 2 - r (1 + z_min) / 2. */
+int cmbx_slab_observer(cmbx_slab* slab, double x, double y, double z);
+/* Spectrum as for cmbx_spectrum_table: host FP64 k (increasing), P_inf (>= 0), n >= 2,
+ * linear between nodes, zero outside. Builds the per-column tables (FP64, rounded once);
+ * synchronises the slab's stream. */
+int cmbx_slab_spectrum(cmbx_slab* slab, const double* k, const double* P_inf, int64_t n);
+/* Maps of the batch (realisation b uses seed + b) at the pixels: dirs device FP64
+ * [n_pix][3], out device [batch][n_pix] of the plan precision; asynchronous on the
+ * slab's stream; the layers of the last realisation stay in the workspace. Errors:
+ * CMBX_ESTATE (no spectrum), CMBX_EINVAL (r <= 0 or not finite, n_pix, NULL), CMBX_EHIP. */
+int cmbx_slab_simulate(cmbx_slab* slab, uint64_t seed, double r, const double* dirs, int64_t n_pix, void* out);
+/* Tests: the layers of realisation `seed`, real [nz][N][N] (device, plan precision); the
+ * column stage alone, unpacked: flat, the modes [N][N/2+1][M]; hybrid, the correlated
+ * columns [h][N][N/2+1] (device complex of the plan precision). */
+int cmbx_slab_debug_layers(cmbx_slab* slab, uint64_t seed, void* layers);
+int cmbx_slab_debug_columns(cmbx_slab* slab, uint64_t seed, void* cols);
+/* Hybrid slabs with a spectrum: the FP64 factor S (h x h, row-major, host) of the columns
+ * with fx^2 + fy^2 = s, as the library formed it before rounding. CMBX_EINVAL if s is not a
+ * sum of two squares of 0 .. N/2 or the slab is flat. */
+int cmbx_slab_factor(const cmbx_slab* slab, int64_t s, double* S);
+/* Layers, rows and pixels of a slab: any pointer may be NULL. */
+int cmbx_slab_info(const cmbx_slab* slab, int* N, int* M, int* nz, double* dp, void** layers);
+/* The box sizing rule of Sec. II C for a beam b (radians) and cap theta_max (radians) on a
+ * sphere of radius R: dp = 0.85 R b / 5 (0.85 of the programme's constraint spacing); N and
+ * M are size_factor times the next power of two of twice the cap's width 2 R sin(theta_max)
+ * and twice its height R (1 - cos theta_max) in points (host only). CMBX_EINVAL for
+ * non-positive or non-finite arguments. */
+int cmbx_box_size(double b, double theta_max, double size_factor, double R, int* N, int* M, double* dp);
 
 /* ---- sky pixels ----
  * HEALPix pixel centres of the cap centred on the pole (Sec. II D 1: for a cap about the
@@ -312,6 +409,27 @@ int cmbx_healpix_cap(int64_t nside, double z_min, double* dirs, int64_t capacity
  * n_pix outside [1, 1048560], lmax outside [0, 65536]), CMBX_EHIP. */
 int cmbx_pixel_covariance(const double* dirs, int64_t n_pix, const double* cl, int lmax, double* gamma,
                           void* stream);
+
+/* Whitening of maps for the covariance test (Sec. III B): with Gamma + s^2 I = L L^T, the
+ * vector x = L^-1 m of a map m (plus white noise of variance s^2) should hold independent
+ * unit normals, which the caller tests (Kolmogorov-Smirnov). FP64, device memory,
+ * row-major, enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *
+ * cmbx_cholesky: A (n x n, leading dimension lda >= n) is overwritten in its lower triangle
+ * by the factor L of A + shift I (blocked, 64-wide panels; the trailing updates on the
+ * FP64 matrix cores); the strict upper triangle is left as it was. info (device int64,
+ * may be NULL) receives 0, or the 1-based column of the first pivot that is not positive
+ * (the matrix plus shift is not positive definite; the factor then holds NaN).
+ * cmbx_whiten: every row of B (nrhs x n, leading dimension ldb >= n; one map per row) is
+ * replaced by L^-1 row, for L from cmbx_cholesky (leading dimension ldl).
+ * cmbx_gemm_nt_sub: C (m x n) -= A (m x k) B (n x k)^T, k <= 64 (the building block of both;
+ * lower != 0 writes only the entries on or below the diagonal).
+ * Errors: CMBX_EINVAL (NULL, sizes < 1, leading dimensions too short, k out of range),
+ * CMBX_EHIP. */
+int cmbx_cholesky(double* A, int64_t n, int64_t lda, double shift, int64_t* info, void* stream);
+int cmbx_whiten(const double* L, int64_t n, int64_t ldl, double* B, int64_t nrhs, int64_t ldb, void* stream);
+int cmbx_gemm_nt_sub(int64_t m, int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double* C, int64_t ldc, int lower, void* stream);
 
 /* ---- spectrum surrogate network (Sec. II B inversion, learned) ----
  * Building blocks of a small MLP that maps a C_l vector to a P_inf table. All pointers are

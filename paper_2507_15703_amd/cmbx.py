@@ -19,8 +19,10 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 F32, F64 = 1, 2
 TRILINEAR, TRICUBIC = 1, 2
 ENS_AUTO, ENS_CHAINED, ENS_PIPELINED = 0, 1, 2
+SLAB_FLAT, SLAB_HYBRID = 1, 2
 ENS_ONE_LANE, ENS_TWO_LANES, ENS_MAX_LANES = 0x100, 0x200, 4
-OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y, OPT_PRUNE = 1, 2, 3, 4, 5, 6, 7
+OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y, OPT_PRUNE, OPT_FIXED_DIRS = 1, 2, 3, 4, 5, 6, 7, 8
+OPT_PLAN_X, OPT_PLAN_Y, OPT_PLAN_Z = 9, 10, 11
 
 _DTYPES = {"f32": F32, "float32": F32, F32: F32, "f64": F64, "float64": F64, F64: F64}
 _INTERPS = {"trilinear": TRILINEAR, "tricubic": TRICUBIC, TRILINEAR: TRILINEAR, TRICUBIC: TRICUBIC}
@@ -51,6 +53,7 @@ def lib():
             "cmbx_plan_box": (I, [I, D, I, I, ctypes.POINTER(P)]),
             "cmbx_plan_destroy": (I, [P]),
             "cmbx_plan_set": (I, [P, I, I64]),
+            "cmbx_plan_get": (I, [P, I, ctypes.POINTER(I64)]),
             "cmbx_plan_observer": (I, [P, D, D, D]),
             "cmbx_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(I),
                                    ctypes.POINTER(P)]),
@@ -83,6 +86,21 @@ def lib():
             "cmbx_mlp_adam": (I, [P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, I, P, P]),
             "cmbx_bf16_round": (I, [P, P, I64, P]),
+            "cmbx_slab_create": (I, [I, I, I, I, D, I, I, ctypes.POINTER(P)]),
+            "cmbx_slab_destroy": (I, [P]),
+            "cmbx_slab_set": (I, [P, I, I64]),
+            "cmbx_slab_observer": (I, [P, D, D, D]),
+            "cmbx_slab_spectrum": (I, [P, P, P, I64]),
+            "cmbx_slab_simulate": (I, [P, U64, D, P, I64, P]),
+            "cmbx_slab_debug_layers": (I, [P, U64, P]),
+            "cmbx_slab_debug_columns": (I, [P, U64, P]),
+            "cmbx_slab_factor": (I, [P, I64, P]),
+            "cmbx_slab_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D),
+                                   ctypes.POINTER(P)]),
+            "cmbx_box_size": (I, [D, D, D, D, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]),
+            "cmbx_cholesky": (I, [P, I64, I64, D, P, P]),
+            "cmbx_whiten": (I, [P, I64, I64, P, I64, I64, P]),
+            "cmbx_gemm_nt_sub": (I, [I64, I64, I, P, I64, P, I64, P, I64, I, P]),
             "cmbx_last_error": (ctypes.c_char_p, []),
             "cmbx_version": (ctypes.c_char_p, []),
         }
@@ -137,6 +155,12 @@ def plan_destroy(h):
 
 def plan_set(h, key, value):
     return _check(lib().cmbx_plan_set(h, int(key), int(value)))
+
+
+def plan_get(h, key):
+    v = ctypes.c_int64(0)
+    _check(lib().cmbx_plan_get(h, int(key), ctypes.byref(v)))
+    return v.value
 
 
 def spectrum_table(h, k, p_inf):
@@ -207,6 +231,35 @@ def pixel_covariance(dirs, cl, out=None, stream=None):
     return out
 
 
+def cholesky(A, shift=0.0, stream=None):
+    """In place: the lower triangle of A (n x n float64 CUDA tensor) becomes the Cholesky
+    factor of A + shift I (cmbx_cholesky). Returns the device info word (int64 tensor of
+    one element): 0, or the 1-based column of the first non-positive pivot."""
+    import torch
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square matrix")
+    n = A.shape[0]
+    a = _ptr(A, n * n * 8, torch.float64, "A")
+    info = torch.zeros(1, dtype=torch.int64, device=A.device)
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().cmbx_cholesky(a, n, n, float(shift), info.data_ptr(), s))
+    return info
+
+
+def whiten(L, maps, stream=None):
+    """In place: every row m of maps (n_maps x n float64 CUDA tensor) becomes L^-1 m, L the
+    lower triangle of the n x n tensor L (cmbx_whiten)."""
+    import torch
+    n = L.shape[0]
+    if maps.dim() != 2 or maps.shape[1] != n:
+        raise ValueError("maps must be (n_maps, n)")
+    l = _ptr(L, n * n * 8, torch.float64, "L")
+    b = _ptr(maps, maps.numel() * 8, torch.float64, "maps")
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().cmbx_whiten(l, n, n, b, maps.shape[0], n, s))
+    return maps
+
+
 class Plan:
     """A box plan (N^3, side L, precision, batch) bound to a stream.
 
@@ -260,35 +313,50 @@ class Plan:
         self.prune = bool(prune)
         plan_set(self.handle, OPT_PRUNE, int(self.prune))
 
+    def set_fixed_dirs(self, fixed=True):
+        """CMBX_OPT_FIXED_DIRS: reuse the map footprint while (r, dirs, n_pix, ...) repeat; call
+        again after writing new directions into the same tensor."""
+        self.fixed_dirs = bool(fixed)
+        plan_set(self.handle, OPT_FIXED_DIRS, int(self.fixed_dirs))
+
     def set_interp(self, interp):
         self.interp = _INTERPS[interp]
         plan_set(self.handle, OPT_INTERP, self.interp)
 
-    def set_tiles(self, tile_xy=0, lines_z=0, tile_x=None, tile_y=None):
-        """Workgroup tile shapes (0 = compiled default); tile_x / tile_y override tile_xy."""
+    def set_tiles(self, tile_xy=0, lines_z=0, tile_x=None, tile_y=None, plans=None):
+        """Workgroup tile shapes (0 = compiled default); tile_x / tile_y override tile_xy;
+        plans = (x, y, z) FFT stage plans (0 or 1; plan 1 at the default tiles only)."""
         plan_set(self.handle, OPT_TILE_XY, tile_xy)
         if tile_x is not None:
             plan_set(self.handle, OPT_TILE_X, tile_x)
         if tile_y is not None:
             plan_set(self.handle, OPT_TILE_Y, tile_y)
         plan_set(self.handle, OPT_LINES_Z, lines_z)
+        for key, v in zip((OPT_PLAN_X, OPT_PLAN_Y, OPT_PLAN_Z), plans or (0, 0, 0)):
+            plan_set(self.handle, key, v)
+
+    def shapes(self):
+        """(tile_x, tile_y, lines_z, (plan_x, plan_y, plan_z)) in use."""
+        g = lambda k: plan_get(self.handle, k)  # noqa: E731
+        return g(OPT_TILE_X), g(OPT_TILE_Y), g(OPT_LINES_Z), (g(OPT_PLAN_X), g(OPT_PLAN_Y), g(OPT_PLAN_Z))
 
     def spectrum_table(self, k, p_inf):
         spectrum_table(self.handle, k, p_inf)
 
     def autotune(self, reps=5, cache_path=None, use_cache=True, r=None, dirs=None):
-        """Choose the tile shapes of the three field kernels whose x -> y -> z chain runs
-        fastest (timed on the device by cmbx_plan_autotune) and remember them in a JSON
-        cache keyed by (arch, N, precision, tuning rule). A cached entry is reused if every
-        value is still a compiled choice; otherwise the plan is re-tuned. Returns
-        dict(tile_x, tile_y, lines_z, ms) with ms the time of each pass alone.
+        """Choose the tile shapes and FFT stage plans of the three field kernels whose
+        x -> y -> z chain runs fastest (timed on the device by cmbx_plan_autotune) and
+        remember them in a JSON cache keyed by (arch, N, precision, tuning rule). A cached
+        entry is reused if every value is still a compiled choice; otherwise the plan is
+        re-tuned. Returns dict(tile_x, tile_y, lines_z, plans, ms) with ms the time of each
+        pass alone.
 
         With ``r`` and ``dirs`` (a map's pixels) a pruning plan is tuned on the passes as
         that map makes them (cmbx_plan_autotune_patch); the choice depends on the map's
         footprint, so it is not cached."""
         import json
         path = cache_path or TUNE_CACHE
-        key = f"gfx950:N{self.N}:{'f32' if self.dtype == F32 else 'f64'}:chain"
+        key = f"gfx950:N{self.N}:{'f32' if self.dtype == F32 else 'f64'}:chain+plans"
         patch = dirs is not None and self.prune
         if patch:
             if r is None:
@@ -301,16 +369,20 @@ class Plan:
         txy = tile_choices(self.dtype, self.N, 0)
         tz = tile_choices(self.dtype, self.N, 1)
         if (isinstance(ent, dict) and ent.get("tile_x") in txy and ent.get("tile_y") in txy
-                and ent.get("lines_z") in tz):
-            self.set_tiles(0, ent["lines_z"], tile_x=ent["tile_x"], tile_y=ent["tile_y"])
-            return dict(ent, cached=True)
+                and ent.get("lines_z") in tz and isinstance(ent.get("plans"), list) and len(ent["plans"]) == 3):
+            try:
+                self.set_tiles(0, ent["lines_z"], tile_x=ent["tile_x"], tile_y=ent["tile_y"], plans=ent["plans"])
+                return dict(ent, cached=True)
+            except CmbxError:
+                pass  # a plan no longer compiled: tune again
         best = (ctypes.c_int * 3)()
         ms = (ctypes.c_double * 3)()
         if patch:
             _check(lib().cmbx_plan_autotune_patch(self.handle, int(reps), float(r), d, int(dirs.shape[0]), best, ms))
         else:
             _check(lib().cmbx_plan_autotune(self.handle, int(reps), best, ms))
-        ent = {"tile_x": best[0], "tile_y": best[1], "lines_z": best[2], "ms": list(ms)}
+        tx, ty, lz, plans = self.shapes()
+        ent = {"tile_x": tx, "tile_y": ty, "lines_z": lz, "plans": list(plans), "ms": list(ms)}
         if use_cache:
             cache[key] = ent
             try:
@@ -536,3 +608,111 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+def box_size(b, theta_max, size_factor=1.0, R=1.0):
+    """The box sizing rule of Sec. II C (cmbx_box_size): (N, M, dp) for beam b and cap
+    half-angle theta_max (radians) on a sphere of radius R."""
+    n, m, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib().cmbx_box_size(float(b), float(theta_max), float(size_factor), float(R), ctypes.byref(n),
+                               ctypes.byref(m), ctypes.byref(d)))
+    return n.value, m.value, d.value
+
+
+class Slab:
+    """Stacked layers of a flat N x N x M box (cmbx_slab_*): method "flat" (the 3-D Fourier
+    method on the whole box, nz = M layers) or "hybrid" (the 2-D Fourier method, h layers).
+    Lengths (dp, r, observer) share one unit."""
+
+    _METHODS = {"flat": SLAB_FLAT, "hybrid": SLAB_HYBRID, SLAB_FLAT: SLAB_FLAT, SLAB_HYBRID: SLAB_HYBRID}
+
+    def __init__(self, method, N, M, dp, h=None, dtype="f32", batch=1, interp="trilinear", stream=None):
+        import torch
+        self.method = self._METHODS[method]
+        self.N, self.M, self.dp, self.batch = int(N), int(M), float(dp), int(batch)
+        self.dtype = _DTYPES[dtype]
+        self.torch_dtype = torch.float32 if self.dtype == F32 else torch.float64
+        hh = self.M if self.method == SLAB_FLAT else int(h)
+        handle = ctypes.c_void_p()
+        _check(lib().cmbx_slab_create(self.method, self.N, self.M, hh, self.dp, self.dtype, self.batch,
+                                      ctypes.byref(handle)))
+        self.handle = handle.value
+        try:
+            nz = ctypes.c_int()
+            _check(lib().cmbx_slab_info(self.handle, None, None, ctypes.byref(nz), None, None))
+            self.nz = nz.value
+            self.set_interp(interp)
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            self.stream = stream
+            _check(lib().cmbx_slab_set(self.handle, OPT_STREAM, stream if isinstance(stream, int) else stream.cuda_stream))
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().cmbx_slab_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_interp(self, interp):
+        self.interp = _INTERPS[interp]
+        _check(lib().cmbx_slab_set(self.handle, OPT_INTERP, self.interp))
+
+    def set_observer(self, position):
+        x, y, z = (float(v) for v in position)
+        _check(lib().cmbx_slab_observer(self.handle, x, y, z))
+        self.observer = (x, y, z)
+
+    def observer_for_cap(self, r, z_min):
+        """Sec. II D 2: the middle of the layers at the middle height of the cap about +z of
+        radius r and edge z_min, on the axis through the layers' centre."""
+        c = 0.5 * self.N * self.dp
+        return (c, c, 0.5 * (self.nz - 1) * self.dp - r * (1.0 + z_min) / 2.0)
+
+    def spectrum(self, k, p_inf):
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        p = np.ascontiguousarray(p_inf, dtype=np.float64)
+        if k.shape != p.shape or k.ndim != 1:
+            raise ValueError("k and P_inf must be 1-D arrays of equal length")
+        _check(lib().cmbx_slab_spectrum(self.handle, k.ctypes.data, p.ctypes.data, k.size))
+
+    def simulate(self, seed, r, dirs, out=None):
+        """Maps [batch, n_pix] of realisations seed .. seed + batch - 1."""
+        import torch
+        if dirs.dim() != 2 or dirs.shape[1] != 3:
+            raise ValueError("dirs must be a [n_pix, 3] float64 CUDA tensor")
+        n = dirs.shape[0]
+        if out is None:
+            out = torch.empty((self.batch, n), dtype=self.torch_dtype, device="cuda")
+        d = _ptr(dirs, n * 24, torch.float64, "dirs")
+        o = _ptr(out, self.batch * n * (4 if self.dtype == F32 else 8), self.torch_dtype, "out")
+        _check(lib().cmbx_slab_simulate(self.handle, int(seed), float(r), d, n, o))
+        return out
+
+    def debug_layers(self, seed):
+        import torch
+        out = torch.empty((self.nz, self.N, self.N), dtype=self.torch_dtype, device="cuda")
+        _check(lib().cmbx_slab_debug_layers(self.handle, int(seed), out.data_ptr()))
+        return out
+
+    def debug_columns(self, seed):
+        """Flat: the modes [N][N/2+1][M]; hybrid: the correlated columns [h][N][N/2+1]."""
+        import torch
+        ctype = torch.complex64 if self.dtype == F32 else torch.complex128
+        shape = (self.N, self.N // 2 + 1, self.M) if self.method == SLAB_FLAT else (self.nz, self.N, self.N // 2 + 1)
+        out = torch.empty(shape, dtype=ctype, device="cuda")
+        _check(lib().cmbx_slab_debug_columns(self.handle, int(seed), out.data_ptr()))
+        return out
+
+    def factor(self, s):
+        """FP64 factor S (h x h) of the columns with fx^2 + fy^2 = s (hybrid)."""
+        out = np.empty((self.nz, self.nz), dtype=np.float64)
+        _check(lib().cmbx_slab_factor(self.handle, int(s), out.ctypes.data))
+        return out

@@ -17,7 +17,10 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "linalg.hpp"
 #include "mlp.hpp"
+#include "host.hpp"
+#include "status.hpp"
 
 struct cmbx_plan {
   int N = 0;
@@ -30,6 +33,9 @@ struct cmbx_plan {
   int tile_x = 0;  // 0 = compiled default
   int tile_y = 0;
   int lines_z = 0;
+  int plan_x = 0;  // FFT stage plan per pass (1: the alternative, with the default tile only)
+  int plan_y = 0;
+  int plan_z = 0;
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   void* field = nullptr;   // batch x N^3 reals
@@ -38,6 +44,16 @@ struct cmbx_plan {
   int m_hi = 0;            // largest |f|^2 of nonzero half weight in the current table
   void* fp = nullptr;      // map footprint of the last simulate_patch call
   bool prune = true;       // maps make only the part of the field their stencils read
+  bool fixed_dirs = false; // the caller keeps the directions at a given address unchanged
+  // what fp was last made from (reused while fixed_dirs holds and every key is the same)
+  struct {
+    bool valid = false;
+    double r = 0;
+    const double* dirs = nullptr;
+    int64_t n_pix = 0;
+    int lines = 0, interp = 0;
+    double obs[3] = {0, 0, 0};
+  } fp_key;
   bool has_spectrum = false;
   size_t real_size() const { return dtype == CMBX_F32 ? 4 : 8; }
   size_t field_bytes() const { return (size_t)N * N * N * real_size(); }
@@ -60,9 +76,12 @@ struct cmbx_ensemble {
   int device = 0;
 };
 
-namespace {
+namespace cmbx {
 
-thread_local std::string g_err;
+std::string& err_msg() {
+  thread_local std::string msg;
+  return msg;
+}
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -70,20 +89,18 @@ int fail(int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_err = buf;
+  err_msg() = buf;
   return code;
 }
 
 int ok() {
-  g_err.clear();
+  err_msg().clear();
   return CMBX_OK;
 }
 
-#define HIP_TRY(call)                                                                            \
-  do {                                                                                           \
-    hipError_t e_ = (call);                                                                      \
-    if (e_ != hipSuccess) return fail(CMBX_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
+}  // namespace cmbx
+
+namespace cmbx {
 
 bool is_2a3b(int n) {
   while (n % 2 == 0) n /= 2;
@@ -97,7 +114,8 @@ void roots_of_unity(int N, std::vector<double>& re, std::vector<double>& im) {
   re.resize(N);
   im.resize(N);
   for (int m = 0; m < N; ++m) {
-    // reduce to the first octant for accuracy, exact at multiples of N/8
+    // the full angle in long double (64-bit significand) rounded once to double; the
+    // quarter turns are set exactly below
     const long double ang = two_pi * (long double)m / (long double)N;
     re[m] = (double)cosl(ang);
     im[m] = (double)sinl(ang);
@@ -122,6 +140,68 @@ double interp_p(const double* kt, const double* pt, int64_t n, double k) {
   const double prod = dp * t;
   return pt[i] + prod;
 }
+
+// Fault injection for tests of the error paths: the environment variable CMBX_FAULT holds
+// a comma-separated list of sites ("alloc": plan allocation, "capture": ensemble graph
+// capture, "launch": ensemble launch) that then fail as the runtime would.
+bool fault(const char* site) {
+  const char* e = std::getenv("CMBX_FAULT");
+  if (!e || !*e) return false;
+  const std::string list = std::string(",") + e + ",";
+  return list.find(std::string(",") + site + ",") != std::string::npos;
+}
+
+// The binary32 Box-Muller tables (layout in noise_device.hpp): each entry the binary64
+// value of its definition rounded once to binary32.
+void fill_noise_tables(float* t) {
+  for (int j = 0; j < 128; ++j) {
+    const double c = 1.0 + j / 128.0;
+    t[j] = (float)std::log(j >= 54 ? c / 2.0 : c);
+    t[128 + j] = (float)(1.0 / c);
+  }
+  const double step = 2.0 * M_PI / 256.0;
+  for (int k = 0; k < 256; ++k) {
+    const double ang = (k + 0.5) * step;
+    t[256 + k] = (float)std::sin(ang);
+    t[512 + k] = (float)std::cos(ang);
+  }
+}
+
+// Upload the tables to the current device once per process.
+hipError_t ensure_noise_tables(int device) {
+  static std::mutex mu;
+  static std::set<int> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count(device)) return hipSuccess;
+  std::vector<float> t(cmbx::kNoiseTableSize);
+  fill_noise_tables(t.data());
+  const hipError_t e = cmbx::upload_noise_tables(t.data());
+  if (e == hipSuccess) done.insert(device);
+  return e;
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  if (prev != dev) (void)hipSetDevice(dev);
+}
+
+DeviceGuard::~DeviceGuard() {
+  if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+}  // namespace cmbx
+
+namespace {
+
+using cmbx::fail;
+using cmbx::ok;
+using cmbx::DeviceGuard;
+using cmbx::ensure_noise_tables;
+using cmbx::fault;
+using cmbx::fill_noise_tables;
+using cmbx::interp_p;
+using cmbx::is_2a3b;
+using cmbx::roots_of_unity;
 
 // Returns the largest |f|^2 whose half weight is not zero: the passes skip what lies beyond.
 template <typename T>
@@ -164,6 +244,9 @@ cmbx::FieldArgs field_args(const cmbx_plan* p, uint64_t seed, void* buf) {
   a.tile_x = p->tile_x;
   a.tile_y = p->tile_y;
   a.lines_z = p->lines_z;
+  a.plan_x = p->plan_x;
+  a.plan_y = p->plan_y;
+  a.plan_z = p->plan_z;
   return a;
 }
 
@@ -236,9 +319,20 @@ int check_patch_args(const cmbx_plan* p, double r, const double* dirs, int64_t n
 // Launch the whole hot path for every realisation of the plan on stream s.
 int enqueue_patch(cmbx_plan* p, uint64_t seed, double r, const double* dirs, int64_t n_pix, void* out,
                   hipStream_t s) {
-  // the realisations share their pixels, hence one footprint
-  if (p->prune)
-    if (int rc = enqueue_footprint(p, p->fp, r, dirs, n_pix, s)) return rc;
+  // the realisations share their pixels, hence one footprint; with fixed directions it
+  // is made once and reused while the pixels' key stays the same
+  if (p->prune) {
+    const int lines = cmbx::resolve_lines_z(p->dtype, p->N, p->lines_z);
+    auto& k = p->fp_key;
+    const bool same = p->fixed_dirs && k.valid && k.r == r && k.dirs == dirs && k.n_pix == n_pix &&
+                      k.lines == lines && k.interp == p->interp && k.obs[0] == p->obs[0] &&
+                      k.obs[1] == p->obs[1] && k.obs[2] == p->obs[2];
+    if (!same) {
+      k.valid = false;
+      if (int rc = enqueue_footprint(p, p->fp, r, dirs, n_pix, s)) return rc;
+      k = {p->fixed_dirs, r, dirs, n_pix, lines, p->interp, {p->obs[0], p->obs[1], p->obs[2]}};
+    }
+  }
   for (int b = 0; b < p->batch; ++b) {
     char* buf = (char*)p->field + (size_t)b * p->field_bytes();
     int rc = enqueue_field(p, seed + (uint64_t)b, buf, s, p->prune ? p->fp : nullptr);
@@ -248,56 +342,6 @@ int enqueue_patch(cmbx_plan* p, uint64_t seed, double r, const double* dirs, int
   }
   return CMBX_OK;
 }
-
-// Fault injection for tests of the error paths: the environment variable CMBX_FAULT holds
-// a comma-separated list of sites ("alloc": plan allocation, "capture": ensemble graph
-// capture, "launch": ensemble launch) that then fail as the runtime would.
-bool fault(const char* site) {
-  const char* e = std::getenv("CMBX_FAULT");
-  if (!e || !*e) return false;
-  const std::string list = std::string(",") + e + ",";
-  return list.find(std::string(",") + site + ",") != std::string::npos;
-}
-
-// The binary32 Box-Muller tables (layout in noise_device.hpp): each entry the binary64
-// value of its definition rounded once to binary32.
-void fill_noise_tables(float* t) {
-  for (int j = 0; j < 128; ++j) {
-    const double c = 1.0 + j / 128.0;
-    t[j] = (float)std::log(j >= 54 ? c / 2.0 : c);
-    t[128 + j] = (float)(1.0 / c);
-  }
-  const double step = 2.0 * M_PI / 256.0;
-  for (int k = 0; k < 256; ++k) {
-    const double ang = (k + 0.5) * step;
-    t[256 + k] = (float)std::sin(ang);
-    t[512 + k] = (float)std::cos(ang);
-  }
-}
-
-// Upload the tables to the current device once per process.
-hipError_t ensure_noise_tables(int device) {
-  static std::mutex mu;
-  static std::set<int> done;
-  std::lock_guard<std::mutex> lock(mu);
-  if (done.count(device)) return hipSuccess;
-  std::vector<float> t(cmbx::kNoiseTableSize);
-  fill_noise_tables(t.data());
-  const hipError_t e = cmbx::upload_noise_tables(t.data());
-  if (e == hipSuccess) done.insert(device);
-  return e;
-}
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 }  // namespace
 
@@ -390,6 +434,11 @@ int cmbx_plan_set(cmbx_plan* p, int key, int64_t value) {
       if (value != 0 && value != 1) return fail(CMBX_EINVAL, "prune = %lld must be 0 or 1", (long long)value);
       p->prune = value == 1;
       return ok();
+    case CMBX_OPT_FIXED_DIRS:
+      if (value != 0 && value != 1) return fail(CMBX_EINVAL, "fixed_dirs = %lld must be 0 or 1", (long long)value);
+      p->fixed_dirs = value == 1;
+      p->fp_key.valid = false;  // setting it (again) makes the next call rebuild the footprint
+      return ok();
     case CMBX_OPT_STREAM:
       p->stream = value == -1 ? p->own_stream : (hipStream_t)(intptr_t)value;
       return ok();
@@ -401,6 +450,11 @@ int cmbx_plan_set(cmbx_plan* p, int key, int64_t value) {
         return fail(CMBX_EINVAL, "tile %lld not compiled for N = %d", (long long)value, p->N);
       if (key != CMBX_OPT_TILE_Y) p->tile_x = (int)value;
       if (key != CMBX_OPT_TILE_X) p->tile_y = (int)value;
+      // stage plan 1 exists at the default tile only: another tile takes plan 0
+      if (value != 0 && value != opts[0]) {
+        if (key != CMBX_OPT_TILE_Y) p->plan_x = 0;
+        if (key != CMBX_OPT_TILE_X) p->plan_y = 0;
+      }
       return ok();
     }
     case CMBX_OPT_LINES_Z: {
@@ -408,11 +462,44 @@ int cmbx_plan_set(cmbx_plan* p, int key, int64_t value) {
       if (value != 0 && std::find(opts, opts + n, (int)value) == opts + n)
         return fail(CMBX_EINVAL, "z lines %lld not compiled for N = %d", (long long)value, p->N);
       p->lines_z = (int)value;
+      if (value != 0 && value != opts[0]) p->plan_z = 0;  // plan 1 is compiled at the default tile only
+      return ok();
+    }
+    case CMBX_OPT_PLAN_X:
+    case CMBX_OPT_PLAN_Y:
+    case CMBX_OPT_PLAN_Z: {
+      const int which = key - CMBX_OPT_PLAN_X;
+      if (value != 0 && value != 1) return fail(CMBX_EINVAL, "stage plan %lld must be 0 or 1", (long long)value);
+      if (value == 1 && !cmbx::stage_plan_compiled(p->dtype, p->N, which))
+        return fail(CMBX_EINVAL, "N = %d has one stage plan for pass %d", p->N, which);
+      if (value == 1) {  // plan 1 is compiled at the default tile: the pass's tile becomes that
+        const int t = which == 2 ? cmbx::resolve_lines_z(p->dtype, p->N, 0) : cmbx::resolve_tile_xy(p->dtype, p->N, 0);
+        (which == 0 ? p->tile_x : which == 1 ? p->tile_y : p->lines_z) = t;
+      }
+      (which == 0 ? p->plan_x : which == 1 ? p->plan_y : p->plan_z) = (int)value;
       return ok();
     }
     default:
       return fail(CMBX_EINVAL, "unknown option key %d", key);
   }
+}
+
+int cmbx_plan_get(const cmbx_plan* p, int key, int64_t* value) {
+  if (int rc = check_plan(p)) return rc;
+  if (!value) return fail(CMBX_EINVAL, "value is NULL");
+  switch (key) {
+    case CMBX_OPT_INTERP: *value = p->interp; break;
+    case CMBX_OPT_TILE_X: *value = cmbx::resolve_tile_xy(p->dtype, p->N, p->tile_x); break;
+    case CMBX_OPT_TILE_Y: *value = cmbx::resolve_tile_xy(p->dtype, p->N, p->tile_y); break;
+    case CMBX_OPT_LINES_Z: *value = cmbx::resolve_lines_z(p->dtype, p->N, p->lines_z); break;
+    case CMBX_OPT_PRUNE: *value = p->prune ? 1 : 0; break;
+    case CMBX_OPT_FIXED_DIRS: *value = p->fixed_dirs ? 1 : 0; break;
+    case CMBX_OPT_PLAN_X: *value = p->plan_x; break;
+    case CMBX_OPT_PLAN_Y: *value = p->plan_y; break;
+    case CMBX_OPT_PLAN_Z: *value = p->plan_z; break;
+    default: return fail(CMBX_EINVAL, "option %d cannot be read back", key);
+  }
+  return ok();
 }
 
 int cmbx_plan_info(const cmbx_plan* p, int* N, double* L, int* dtype, int* batch, void** field) {
@@ -534,6 +621,28 @@ int cmbx_pixel_covariance(const double* dirs, int64_t n_pix, const double* cl, i
   return ok();
 }
 
+int cmbx_cholesky(double* A, int64_t n, int64_t lda, double shift, int64_t* info, void* stream) {
+  if (!A || n < 1 || lda < n) return fail(CMBX_EINVAL, "cholesky: need A != NULL, n >= 1, lda >= n");
+  if (!std::isfinite(shift)) return fail(CMBX_EINVAL, "cholesky: shift must be finite");
+  HIP_TRY(cmbx::launch_cholesky(A, n, lda, shift, info, (hipStream_t)stream));
+  return ok();
+}
+
+int cmbx_whiten(const double* L, int64_t n, int64_t ldl, double* B, int64_t nrhs, int64_t ldb, void* stream) {
+  if (!L || !B || n < 1 || nrhs < 1 || ldl < n || ldb < n)
+    return fail(CMBX_EINVAL, "whiten: need non-NULL L, B, n, nrhs >= 1 and leading dimensions >= n");
+  HIP_TRY(cmbx::launch_trsm_rows(L, n, ldl, B, nrhs, ldb, (hipStream_t)stream));
+  return ok();
+}
+
+int cmbx_gemm_nt_sub(int64_t m, int64_t n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double* C, int64_t ldc, int lower, void* stream) {
+  if (!A || !B || !C || m < 1 || n < 1 || k < 1 || k > cmbx::kCholPanel || lda < k || ldb < k || ldc < n)
+    return fail(CMBX_EINVAL, "gemm_nt_sub: bad sizes or NULL operand (k must be 1 .. %d)", cmbx::kCholPanel);
+  HIP_TRY(cmbx::launch_gemm_nt_sub(m, n, k, A, lda, B, ldb, C, ldc, lower ? 1 : 0, (hipStream_t)stream));
+  return ok();
+}
+
 int64_t cmbx_footprint_bytes(int N) {
   if (N < 8 || N > 1024) return fail(CMBX_EINVAL, "N = %d must be in [8, 1024]", N);
   return (int64_t)cmbx::footprint_bytes(N);
@@ -563,6 +672,7 @@ struct Item {
   void* out;
   int lane = 0;  // chained mode: the graph (and stream) the item runs in
   void* fp = nullptr;  // its map footprint if its plan prunes
+  bool fixed = false;  // its plan fixes the directions: fp is made at creation, not in the graph
 };
 
 // Interleave the roles' workgroups in proportion to their counts (largest-deficit
@@ -598,7 +708,7 @@ int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t
     for (const Item& it : gr.items) {
       if (lane >= 0 && it.lane != lane) continue;
       char* buf = (char*)it.plan->field + (size_t)it.slot * it.plan->field_bytes();
-      if (it.fp)
+      if (it.fp && !it.fixed)
         if (int rc = enqueue_footprint(it.plan, it.fp, it.r, it.dirs, it.n_pix, s)) return rc;
       if (int rc = enqueue_field(it.plan, it.seed, buf, s, it.fp)) return rc;
       if (int rc = enqueue_gather(it.plan, buf, it.r, it.dirs, it.n_pix, it.out, s)) return rc;
@@ -609,13 +719,38 @@ int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t
   int tx = 0, ty = 0, lz = 0;
   if (!cmbx::pipeline_shape(gr.dtype, gr.N, &tx, &ty, &lz)) return fail(CMBX_EUNSUPPORTED, "no pipelined kernel");
   for (const Item& it : gr.items)
-    if (it.fp)
+    if (it.fp && !it.fixed)
       if (int rc = enqueue_footprint(it.plan, it.fp, it.r, it.dirs, it.n_pix, s, lz)) return rc;
   for (size_t i = 0; i < gr.pipe.size(); ++i) {
     cmbx::PipeLaunch a = gr.pipe[i];
     a.sched = dsched + gr.sched_off[i];
     HIP_TRY(cmbx::launch_pipeline(a, s));
   }
+  return CMBX_OK;
+}
+
+// The footprints of the items whose plans fix the directions, for each group's mode (its
+// plan's z tile chained, the pipelined kernel's otherwise), made now on a stream of their
+// own and waited for: the graphs then do not remake them at every launch.
+int make_fixed_footprints(const std::vector<Group>& groups) {
+  bool any = false;
+  for (const Group& gr : groups)
+    for (const Item& it : gr.items) any = any || (it.fp && it.fixed);
+  if (!any) return CMBX_OK;
+  hipStream_t st = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  int rc = CMBX_OK;
+  for (const Group& gr : groups) {
+    int tx = 0, ty = 0, lz = 0;
+    if (gr.mode != CMBX_ENS_CHAINED && !cmbx::pipeline_shape(gr.dtype, gr.N, &tx, &ty, &lz)) lz = 0;
+    for (const Item& it : gr.items)
+      if (rc == CMBX_OK && it.fp && it.fixed)
+        rc = enqueue_footprint(it.plan, it.fp, it.r, it.dirs, it.n_pix, st, gr.mode == CMBX_ENS_CHAINED ? 0 : lz);
+  }
+  const hipError_t e = hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+  if (rc != CMBX_OK) return rc;
+  if (e != hipSuccess) return fail(CMBX_EHIP, "fixed footprints: %s", hipGetErrorString(e));
   return CMBX_OK;
 }
 
@@ -798,7 +933,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
   for (int j = 0; j < n_jobs; ++j) {
     if (!jobs[j].plan) return fail(CMBX_EINVAL, "job %d has no plan", j);
     if (int rc = check_patch_args(jobs[j].plan, jobs[j].r, jobs[j].dirs, jobs[j].n_pix, jobs[j].out)) {
-      g_err = "job " + std::to_string(j) + ": " + g_err;
+      cmbx::err_msg() = "job " + std::to_string(j) + ": " + cmbx::err_msg();
       return rc;
     }
     if (jobs[j].plan->device != jobs[0].plan->device) return fail(CMBX_EINVAL, "all jobs must be on one device");
@@ -843,7 +978,10 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
       if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "ensemble footprints");
       en->fps.push_back(f);
       it.fp = f;
+      it.fixed = it.plan->fixed_dirs;
     }
+  // fixed footprints are valid before any launch (the timing launches of auto mode included)
+  if (int rc = make_fixed_footprints(groups)) return bail(rc, cmbx::err_msg());
   std::vector<uint32_t> sched;
   if (mode != CMBX_ENS_CHAINED) {
     for (Group& gr : groups) {
@@ -923,7 +1061,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
       for (int k = 0; k < 2; ++k) {
         hipGraph_t gph = nullptr;
         hipGraphExec_t ex = nullptr;
-        if (int rc = capture(groups, dsched, (int)gi, modes[k], -1, &gph, &ex)) return bail(rc, g_err);
+        if (int rc = capture(groups, dsched, (int)gi, modes[k], -1, &gph, &ex)) return bail(rc, cmbx::err_msg());
         t[k] = time_graph(ex);
         (void)hipGraphExecDestroy(ex);
         (void)hipGraphDestroy(gph);
@@ -942,7 +1080,8 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
   };
   if (mode != CMBX_ENS_AUTO || lanes_flag != 0) {
     const int lanes = set_modes(chosen, lanes_flag > 0 ? lanes_flag : 1);
-    if (int rc = build_lanes(en, groups, dsched, lanes)) return bail(rc, g_err);
+    if (int rc = make_fixed_footprints(groups)) return bail(rc, cmbx::err_msg());
+    if (int rc = build_lanes(en, groups, dsched, lanes)) return bail(rc, cmbx::err_msg());
   } else {
     // AUTO: time the whole ensemble in each candidate -- the modes chosen per group, and
     // every group chained (the chains of different plans then overlap, which a group
@@ -976,19 +1115,20 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
     size_t best = 0;
     if (cands.size() > 1) {
       for (size_t c = 0; c < cands.size(); ++c)
-        if (int rc = time_cand(c)) return bail(rc, g_err);
+        if (int rc = time_cand(c)) return bail(rc, cmbx::err_msg());
       std::vector<size_t> order(cands.size());
       for (size_t c = 0; c < order.size(); ++c) order[c] = c;
       std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return tc[x] < tc[y]; });
       for (int round = 0; round < 2; ++round)
         for (size_t k = 0; k < 2; ++k)
-          if (int rc = time_cand(order[k])) return bail(rc, g_err);
+          if (int rc = time_cand(order[k])) return bail(rc, cmbx::err_msg());
       for (size_t c = 1; c < cands.size(); ++c)
         if (tc[c] < tc[best]) best = c;
     }
     set_modes(cands[best].modes, cands[best].lanes);
     clear_lanes(en);
-    if (int rc = build_lanes(en, groups, dsched, cands[best].lanes)) return bail(rc, g_err);
+    if (int rc = make_fixed_footprints(groups)) return bail(rc, cmbx::err_msg());
+    if (int rc = build_lanes(en, groups, dsched, cands[best].lanes)) return bail(rc, cmbx::err_msg());
   }
   bool any_pipe = false;
   for (const Group& gr : groups) {
@@ -1056,6 +1196,7 @@ int cmbx_time_passes(cmbx_plan* p, uint64_t seed, double r, const double* dirs, 
   // the passes as cmbx_simulate_patch runs them: with the map's footprint if the plan
   // prunes (made once, before the timed launches)
   if (p->prune) {
+    p->fp_key.valid = false;
     if (int rc = enqueue_footprint(p, p->fp, r, dirs, n_pix, p->stream)) return rc;
     a.fp = p->fp;
   }
@@ -1116,6 +1257,7 @@ int autotune(cmbx_plan* p, int reps, int* best, double* ms, double r, const doub
     if (!pruned) return CMBX_OK;
     const int lines = cmbx::resolve_lines_z(p->dtype, p->N, a.lines_z);
     if (lines == fp_lines) return CMBX_OK;
+    p->fp_key.valid = false;
     if (int rc = enqueue_footprint(p, p->fp, r, dirs, n_pix, p->stream, lines)) return rc;
     fp_lines = lines;
     return CMBX_OK;
@@ -1140,30 +1282,37 @@ int autotune(cmbx_plan* p, int reps, int* best, double* ms, double r, const doub
     return e == hipSuccess ? (double)t / reps : -1.0;
   };
   int* opt[3] = {&a.tile_x, &a.tile_y, &a.lines_z};
+  int* optp[3] = {&a.plan_x, &a.plan_y, &a.plan_z};
   int pick[3] = {p->tile_x, p->tile_y, p->lines_z};
+  int pickp[3] = {p->plan_x, p->plan_y, p->plan_z};
   double tbest[3] = {0, 0, 0};
   bool bad = false;
   // Each shape is judged by the whole x -> y -> z chain, not by its own kernel alone: a
   // pass's write pattern changes what the next pass pays (narrow x tiles time as fast as
-  // wide ones in isolation but slow pass y down). Coordinate descent, two sweeps.
+  // wide ones in isolation but slow pass y down). Coordinate descent, two sweeps, over each
+  // pass's compiled choices: every tile with stage plan 0, and the default tile with the
+  // alternative stage plan 1 where there is one.
   for (int sweep = 0; sweep < 2 && !bad; ++sweep) {
     for (int which = 0; which < 3 && !bad; ++which) {
       const int n = which == 2 ? nln : ntz;
+      const int* vals = which == 2 ? ln : tz;
+      const int ncand = n + (cmbx::stage_plan_compiled(p->dtype, p->N, which) ? 1 : 0);
       double best_t = 1e300;
-      for (int i = 0; i < n && !bad; ++i) {
-        for (int o = 0; o < 3; ++o) *opt[o] = pick[o];
-        *opt[which] = which == 2 ? ln[i] : tz[i];
+      for (int i = 0; i < ncand && !bad; ++i) {
+        for (int o = 0; o < 3; ++o) *opt[o] = pick[o], *optp[o] = pickp[o];
+        *opt[which] = i < n ? vals[i] : vals[0];
+        *optp[which] = i < n ? 0 : 1;
         if (prepare() != CMBX_OK) {
           bad = true;
           break;
         }
         const double t = time_passes(0, 2);
         if (t < 0) bad = true;
-        else if (t < best_t) best_t = t, pick[which] = *opt[which];
+        else if (t < best_t) best_t = t, pick[which] = *opt[which], pickp[which] = *optp[which];
       }
     }
   }
-  for (int o = 0; o < 3; ++o) *opt[o] = pick[o];
+  for (int o = 0; o < 3; ++o) *opt[o] = pick[o], *optp[o] = pickp[o];
   if (!bad && prepare() != CMBX_OK) bad = true;
   for (int which = 0; which < 3 && !bad; ++which) {
     tbest[which] = time_passes(which, which);
@@ -1175,6 +1324,9 @@ int autotune(cmbx_plan* p, int reps, int* best, double* ms, double r, const doub
   p->tile_x = pick[0];
   p->tile_y = pick[1];
   p->lines_z = pick[2];
+  p->plan_x = pickp[0];
+  p->plan_y = pickp[1];
+  p->plan_z = pickp[2];
   for (int i = 0; i < 3; ++i) {
     if (best) best[i] = pick[i];
     if (ms) ms[i] = tbest[i];
@@ -1268,7 +1420,7 @@ int cmbx_bf16_round(const float* x, uint16_t* y, int64_t n, void* stream) {
   return ok();
 }
 
-const char* cmbx_last_error(void) { return g_err.c_str(); }
+const char* cmbx_last_error(void) { return cmbx::err_msg().c_str(); }
 
 const char* cmbx_version(void) { return "cmbx 0.1.0 (gfx950)"; }
 

@@ -124,18 +124,31 @@ struct Dft<T, 16> {
 
 // ---------------------------------------------------------------- stage plans
 // Factorisation of a transform length L = 2^a 3^b into radix stages: radix-3 stages
-// first, then the power of two as radix-8 stages with one radix-16, -4 or -2 stage to
-// make up the remainder (a = 8 uses two radix-16 stages).
+// first, then the power of two. Plan P = 0 takes radix-8 stages with one radix-16, -4 or
+// -2 stage to make up the remainder (a = 8 uses two radix-16 stages); plan P = 1 is an
+// alternative ordering / split of the same power of two (e.g. 512 = 16 8 4 instead of
+// 8 8 8, 256 = 4 8 8 instead of 16 16), chosen between them by the autotuner.
+constexpr int kPlans = 2;
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 constexpr int pow3_count(int L) { return (L % 3 == 0) ? 1 + pow3_count(L / 3) : 0; }
 constexpr int pow2_part(int L) { return (L % 3 == 0) ? pow2_part(L / 3) : L; }
 
-constexpr int pow2_stage_count(int a) {
-  return a == 0 ? 0 : a <= 4 ? 1 : a == 5 ? 2 : a == 6 ? 2 : a == 7 ? 2 : a == 8 ? 2 : a == 9 ? 3 : a == 10 ? 3 : 3;
+constexpr int pow2_stage_count(int a, int P) {
+  return a == 0 ? 0
+       : a <= 4 ? 1
+       : P == 1 ? (a <= 7 ? 2 : 3)
+       : (a <= 8 ? 2 : 3);
 }
-constexpr int pow2_radix(int a, int i) {
+constexpr int pow2_radix(int a, int i, int P) {
   // a: exponent of the power of two; i: stage index within the power-of-two stages
   return a <= 4 ? (1 << a)
+       : P == 1 ? (a == 5 ? (i == 0 ? 4 : 8)
+                 : a == 6 ? (i == 0 ? 4 : 16)
+                 : a == 7 ? (i == 0 ? 8 : 16)
+                 : a == 8 ? (i == 0 ? 4 : 8)
+                 : a == 9 ? (i == 0 ? 16 : i == 1 ? 8 : 4)
+                 : a == 10 ? (i == 0 ? 4 : 16)
+                 : (i == 0 ? 8 : 16))  // a == 11
        : a == 5 ? (i == 0 ? 8 : 4)
        : a == 6 ? 8
        : a == 7 ? (i == 0 ? 16 : 8)
@@ -144,13 +157,15 @@ constexpr int pow2_radix(int a, int i) {
        : a == 10 ? (i == 0 ? 16 : 8)
        : (i < 2 ? 16 : 8);  // a == 11
 }
-constexpr int stage_count(int L) { return pow3_count(L) + pow2_stage_count(ilog2(pow2_part(L))); }
-constexpr int stage_radix(int L, int i) {
-  return i < pow3_count(L) ? 3 : pow2_radix(ilog2(pow2_part(L)), i - pow3_count(L));
+constexpr int stage_count(int L, int P = 0) { return pow3_count(L) + pow2_stage_count(ilog2(pow2_part(L)), P); }
+constexpr int stage_radix(int L, int i, int P = 0) {
+  return i < pow3_count(L) ? 3 : pow2_radix(ilog2(pow2_part(L)), i - pow3_count(L), P);
 }
-constexpr int stage_stride(int L, int i) { return i == 0 ? 1 : stage_stride(L, i - 1) * stage_radix(L, i - 1); }
-constexpr bool plan_ok(int L, int i = 0, int prod = 1) {
-  return i == stage_count(L) ? prod == L : plan_ok(L, i + 1, prod * stage_radix(L, i));
+constexpr int stage_stride(int L, int i, int P = 0) {
+  return i == 0 ? 1 : stage_stride(L, i - 1, P) * stage_radix(L, i - 1, P);
+}
+constexpr bool plan_ok(int L, int P = 0, int i = 0, int prod = 1) {
+  return i == stage_count(L, P) ? prod == L : plan_ok(L, P, i + 1, prod * stage_radix(L, i, P));
 }
 
 // ---------------------------------------------------------------- stage driver
@@ -210,9 +225,9 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ tw, Src& sr
 // it the rows spread over the G = 256 B / row bytes row positions of a bank sweep. Reads,
 // which run over consecutive rows, keep their banks. sw is the identity for a radix-3
 // first stage.
-template <typename T, int L, int NSEQ, bool SEQFAST>
+template <typename T, int L, int NSEQ, bool SEQFAST, int P = 0>
 struct LdsIO {
-  static constexpr int R0 = stage_radix(L, 0);
+  static constexpr int R0 = stage_radix(L, 0, P);
   static constexpr bool POW2 = (R0 & (R0 - 1)) == 0;
   static constexpr int BANK_CPX = 256 / (int)sizeof(cpx<T>);  // complex values in one sweep of the banks
   // measured: the line layout (the z pass) runs slower permuted, so only rows are
@@ -226,18 +241,19 @@ struct LdsIO {
   __device__ __forceinline__ void done() const { __syncthreads(); }
 };
 
-// Run all stages of a length-L transform: stage 0 reads from `first`, the last stage
-// writes to `last`, stages in between go through the LDS sequences `lds`. `tid` is the
-// thread's index in the workgroup.
-template <typename T, int L, int NSEQ, int NT, bool SEQFAST, int TWMUL, int S, class First, class Last>
+// Run all stages of a length-L transform with stage plan P: stage 0 reads from `first`,
+// the last stage writes to `last`, stages in between go through the LDS sequences `lds`
+// (laid out as LdsIO<T, L, NSEQ, SEQFAST, P>). `tid` is the thread's index in the
+// workgroup.
+template <typename T, int L, int NSEQ, int NT, bool SEQFAST, int TWMUL, int S, class First, class Last, int P = 0>
 __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* lds, First& first, Last& last,
                                         int tid) {
-  constexpr int NST = stage_count(L);
-  static_assert(plan_ok(L), "unsupported transform length");
+  constexpr int NST = stage_count(L, P);
+  static_assert(plan_ok(L, P), "unsupported transform length");
   if constexpr (S < NST) {
-    constexpr int R = stage_radix(L, S);
-    constexpr int NS = stage_stride(L, S);
-    LdsIO<T, L, NSEQ, SEQFAST> mid{lds};
+    constexpr int R = stage_radix(L, S, P);
+    constexpr int NS = stage_stride(L, S, P);
+    LdsIO<T, L, NSEQ, SEQFAST, P> mid{lds};
     if constexpr (S == 0 && NST == 1) {
       fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, last, tid);
     } else if constexpr (S == 0) {
@@ -247,7 +263,7 @@ __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* l
     } else {
       fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, mid, tid);
     }
-    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1>(tw, lds, first, last, tid);
+    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1, First, Last, P>(tw, lds, first, last, tid);
   }
 }
 

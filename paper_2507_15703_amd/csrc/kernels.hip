@@ -9,6 +9,8 @@
 //   after pass 3: real [N][N][N], z fastest -- the same bytes, in place.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "fft_device.hpp"
 #include "kernels.hpp"
 #include "noise_device.hpp"
@@ -70,9 +72,9 @@ struct KeptLinesIO {
 //   Z_k = (X_k + conj X_{M-k}) + i w^k (X_k - conj X_{M-k}),  w = exp(2 pi i / N),
 //   Z_0 = (a + b) + i (a - b)   with X_0 = a, X_{N/2} = b (column 0 holds a + i b),
 // whose inverse M-point DFT z_n gives the real outputs x_{2n} = Re z_n, x_{2n+1} = Im z_n.
-template <typename T, int M, int LINES>
+template <typename T, int M, int LINES, int P = 0>
 struct HalfToComplex {
-  using Lds = LdsIO<T, M, LINES, false>;  // the tile's layout
+  using Lds = LdsIO<T, M, LINES, false, P>;  // the tile's layout
   const cpx<T>* x;
   const cpx<T>* tw;  // N = 2M roots
   __device__ __forceinline__ cpx<T> operator()(int q, int k) const {
@@ -145,13 +147,13 @@ __device__ __forceinline__ void x_setup(cpx<T>* smem, const cpx<T>* __restrict__
 // inverse transform along x, and the rows written (with a map footprint, only the rows ix
 // of the x-planes the map's stencils read; the transform itself is whole). Needs
 // x_setup's LDS and no thread still reading the tile of an earlier call.
-template <typename T, int N, int TZ, int NT>
+template <typename T, int N, int TZ, int NT, int P = 0>
 __device__ __forceinline__ void x_tile(cpx<T>* smem, int zt, int iy, cpx<T>* __restrict__ buf,
                                        const T* __restrict__ wtab, uint32_t k0, uint32_t k1, int m_hi,
                                        const uint8_t* planes) {
   constexpr int M = N / 2;
   constexpr int PAIRS = TZ / 2;
-  using Lds = LdsIO<T, N, TZ, true>;  // the tile's layout, as the transform reads it
+  using Lds = LdsIO<T, N, TZ, true, P>;  // the tile's layout, as the transform reads it
   cpx<T>* tile = smem;
   const cpx<T>* tw = smem + XLds<T, N, TZ>::TW;
   const float* tab = tab_cpx<T>() > 0 ? reinterpret_cast<const float*>(smem + XLds<T, N, TZ>::TAB) : nullptr;
@@ -189,7 +191,7 @@ __device__ __forceinline__ void x_tile(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   __syncthreads();
   Lds first{tile};
   KeptRowsColIO<T, 0> last{{buf + (size_t)iy * M + zc0, (size_t)N * M}, planes};
-  fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, first, last, tid);
+  fft_run<T, N, TZ, NT, true, 1, 0, Lds, KeptRowsColIO<T, 0>, P>(tw, tile, first, last, tid);
 }
 
 // Largest s with s^2 <= d (d >= 0, below 2^24).
@@ -252,7 +254,7 @@ struct SupportColIO {
 
 // With a map footprint `fp`, x-planes that no stencil reads are skipped, and of the
 // others only the 8-row blocks that some stencil reads are written.
-template <typename T, int N, int TZ, int NT>
+template <typename T, int N, int TZ, int NT, int P = 0>
 __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __restrict__ buf,
                                        const cpx<T>* __restrict__ twg, int m_hi, const uint8_t* __restrict__ fp) {
   constexpr int M = N / 2;
@@ -271,7 +273,7 @@ __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __r
   GlobalColIO<T> io{buf + (size_t)ix * N * M + zt * TZ, (size_t)M};
   SupportColIO<T, N> first{io, zt * TZ, m_hi};
   KeptRowsColIO<T, 3> last{io, fp ? rows : nullptr};
-  fft_run<T, N, TZ, NT, true, 1, 0>(tw, tile, first, last, tid);
+  fft_run<T, N, TZ, NT, true, 1, 0, SupportColIO<T, N>, KeptRowsColIO<T, 3>, P>(tw, tile, first, last, tid);
 }
 
 // ------------------------------------------------------------------ pass 3: z (c2r)
@@ -283,7 +285,7 @@ __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __r
 // only the lines in 8-row blocks that some stencil reads are written (the others of a kept
 // block are transformed from whatever pass y left there, and dropped), and of those only
 // the 32-node z blocks that some stencil reads.
-template <typename T, int N, int LINES, int NT>
+template <typename T, int N, int LINES, int NT, int P = 0>
 __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict__ buf,
                                        const cpx<T>* __restrict__ twg, int m_hi, const uint8_t* __restrict__ fp) {
   constexpr int M = N / 2;
@@ -314,7 +316,7 @@ __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict
       if (!__syncthreads_or(any)) return;
     }
   }
-  using Lds = LdsIO<T, M, LINES, false>;  // the tile's layout, as the transform reads it
+  using Lds = LdsIO<T, M, LINES, false, P>;  // the tile's layout, as the transform reads it
   cpx<T>* g = buf + (size_t)blk * LINES * M;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   if constexpr (NT % M == 0) {
@@ -331,15 +333,16 @@ __device__ __forceinline__ void role_z(cpx<T>* smem, int blk, cpx<T>* __restrict
     }
   }
   __syncthreads();
-  HalfToComplex<T, M, LINES> first{tile, tw};
+  HalfToComplex<T, M, LINES, P> first{tile, tw};
   KeptLinesIO<T, M, LINES> last{g, keep, fp ? keep_lds : nullptr, zmask};
-  fft_run<T, M, LINES, NT, false, 2, 0>(tw, tile, first, last, tid);
+  fft_run<T, M, LINES, NT, false, 2, 0, HalfToComplex<T, M, LINES, P>, KeptLinesIO<T, M, LINES>, P>(tw, tile, first, last,
+                                                                                                   tid);
 }
 
 // One workgroup per tile within the spectrum's support, listed by z tile (a prefix of the
 // per-zt row counts, made in LDS; rows in the order 0 .. R, N - R .. N - 1): tiles beyond
 // the support get no workgroup at all.
-template <typename T, int N, int TZ>
+template <typename T, int N, int TZ, int P = 0>
 __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __restrict__ buf,
                                                                  const T* __restrict__ wtab,
                                                                  const cpx<T>* __restrict__ twg,
@@ -373,10 +376,10 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __re
   }
   const int k = e - start[lo], R = radius[lo];
   const int iy = k <= R ? k : N - (start[lo + 1] - start[lo] - k);
-  x_tile<T, N, TZ, NT>(smem, lo, iy, buf, wtab, k0, k1, m_hi, fp ? planes : nullptr);
+  x_tile<T, N, TZ, NT, P>(smem, lo, iy, buf, wtab, k0, k1, m_hi, fp ? planes : nullptr);
 }
 
-template <typename T, int N, int TZ>
+template <typename T, int N, int TZ, int P = 0>
 __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __restrict__ buf,
                                                                  const cpx<T>* __restrict__ twg, int m_hi,
                                                                  const uint8_t* __restrict__ fp) {
@@ -402,7 +405,7 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __re
   }
   for (int e = e0; e < count; e += step) {
     const int zt = e % tiles, ix = plist ? (int)plist[e / tiles] : e / tiles;
-    role_y<T, N, TZ, XYShape<T, N, TZ>::NT>(smem, zt, ix, buf, twg, m_hi, fp);
+    role_y<T, N, TZ, XYShape<T, N, TZ>::NT, P>(smem, zt, ix, buf, twg, m_hi, fp);
     __syncthreads();  // the tile is reused by the next pair
   }
 }
@@ -413,7 +416,7 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __re
 // line by line).
 constexpr int kZGrid = 1024;  // the y pass's walking grid (its tiles fit 2-4 per CU)
 
-template <typename T, int N, int LINES>
+template <typename T, int N, int LINES, int P = 0>
 __global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __restrict__ buf,
                                                                    const cpx<T>* __restrict__ twg, int m_hi,
                                                                    const uint8_t* __restrict__ fp) {
@@ -426,7 +429,7 @@ __global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __
   const int count = !fp ? (int)blockIdx.x + 1 : listed ? (int)hdr[1] : NBLK;
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
     const int blk = listed ? (int)hdr[kFootprintHeader + e] : e;
-    role_z<T, N, LINES, ZShape<T, N, LINES>::NT>(smem, blk, buf, twg, m_hi, fp);
+    role_z<T, N, LINES, ZShape<T, N, LINES>::NT, P>(smem, blk, buf, twg, m_hi, fp);
     __syncthreads();  // the tile and the line flags are reused by the next block
   }
 }
@@ -781,10 +784,10 @@ inline int x_tiles_in_support(int N, int TZ, int m_hi) {
   return total > 0 ? total : 1;
 }
 
-template <typename T, int N, int TZ>
+template <typename T, int N, int TZ, int P = 0>
 hipError_t run_x(const FieldArgs& a, hipStream_t s) {
   dim3 grid(x_tiles_in_support(N, TZ, a.m_hi));
-  hipLaunchKernelGGL((k_pass_x<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
+  hipLaunchKernelGGL((k_pass_x<T, N, TZ, P>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
                      (const T*)a.wtab, (const cpx<T>*)a.tw, a.k0, a.k1, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
 }
@@ -800,23 +803,44 @@ int resident_grid(K kernel, int threads) {
   return per > 0 && cus > 0 ? per * cus : 1024;
 }
 
-template <typename T, int N, int TZ>
+template <typename T, int N, int TZ, int P = 0>
 hipError_t run_y(const FieldArgs& a, hipStream_t s) {
   constexpr int NWG = N / 2 / TZ * N;
   const dim3 grid = a.fp ? dim3(NWG > kZGrid ? kZGrid : NWG) : dim3(N / 2 / TZ, N);
-  hipLaunchKernelGGL((k_pass_y<T, N, TZ>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
+  hipLaunchKernelGGL((k_pass_y<T, N, TZ, P>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
                      (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
   return hipGetLastError();
 }
-template <typename T, int N, int LINES>
+template <typename T, int N, int LINES, int P = 0>
 hipError_t run_z(const FieldArgs& a, hipStream_t s) {
   constexpr int NBLK = N * N / LINES;
   // a walking grid of what the device holds at once: a fixed one ran a second, partial
   // round of workgroups for blocks of 16 and 32 lines
-  static const int resident = resident_grid(k_pass_z<T, N, LINES>, ZShape<T, N, LINES>::NT);
+  static const int resident = resident_grid(k_pass_z<T, N, LINES, P>, ZShape<T, N, LINES>::NT);
   dim3 grid(a.fp && NBLK > resident ? resident : NBLK);
-  hipLaunchKernelGGL((k_pass_z<T, N, LINES>), grid, dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf,
+  hipLaunchKernelGGL((k_pass_z<T, N, LINES, P>), grid, dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf,
                      (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
+  return hipGetLastError();
+}
+
+// The x and y transforms of stacked layers (the 2-D passes of flat boxes): the y-pass
+// kernel on `nlayers` planes (a transform along the middle axis of each), then the z-pass
+// kernel on their nlayers N contiguous lines; neither skips anything.
+using LayersFn = hipError_t (*)(void* buf, const void* tw, int nlayers, hipStream_t s);
+
+template <typename T, int N, int TZ>
+hipError_t run_y_layers(void* buf, const void* tw, int nlayers, hipStream_t s) {
+  hipLaunchKernelGGL((k_pass_y<T, N, TZ>), dim3(N / 2 / TZ, nlayers), dim3(XYShape<T, N, TZ>::NT), 0, s,
+                     (cpx<T>*)buf, (const cpx<T>*)tw, INT_MAX, (const uint8_t*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int LINES>
+hipError_t run_z_layers(void* buf, const void* tw, int nlayers, hipStream_t s) {
+  const int64_t lines = (int64_t)nlayers * N;
+  if (lines % LINES) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_pass_z<T, N, LINES>), dim3((unsigned)(lines / LINES)), dim3(ZShape<T, N, LINES>::NT), 0, s,
+                     (cpx<T>*)buf, (const cpx<T>*)tw, INT_MAX, (const uint8_t*)nullptr);
   return hipGetLastError();
 }
 
@@ -865,9 +889,34 @@ struct Entry {
   PassFn x[kChoices], y[kChoices];
   int lines[kChoices];
   PassFn z[kChoices];
+  PassFn x1, y1, z1;     // the alternative stage plan (P = 1) at the default tiles, or nullptr
+
   int ptx, pty, plz;
   PipeFn pipe;
+  LayersFn ylay;                   // layers' first transform, default column tile
+  LayersFn zlay[kChoices + 1];     // layers' c2r, per z tile (lines[i]), then a tile dividing N
 };
+
+constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+
+// Lengths with a second stage plan: a power-of-two part of at least 32 (smaller ones are
+// one stage, whatever the plan).
+constexpr bool alt_plan(int L) { return ilog2(pow2_part(L)) >= 5; }
+template <typename T, int N, int TZ>
+constexpr PassFn alt_x() {
+  if constexpr (alt_plan(N)) return &run_x<T, N, TZ, 1>;
+  else return nullptr;
+}
+template <typename T, int N, int TZ>
+constexpr PassFn alt_y() {
+  if constexpr (alt_plan(N)) return &run_y<T, N, TZ, 1>;
+  else return nullptr;
+}
+template <typename T, int N, int LINES>
+constexpr PassFn alt_z() {
+  if constexpr (alt_plan(N / 2)) return &run_z<T, N, LINES, 1>;
+  else return nullptr;
+}
 
 template <typename T, int N>
 constexpr Entry make_entry() {
@@ -882,10 +931,16 @@ constexpr Entry make_entry() {
                {&run_y<T, N, t0>, &run_y<T, N, t1>, &run_y<T, N, t2>},
                {l0, l1, l2},
                {&run_z<T, N, l0>, &run_z<T, N, l1>, &run_z<T, N, l2>},
+               alt_x<T, N, t0>(),
+               alt_y<T, N, t0>(),
+               alt_z<T, N, l0>(),
                px,
                px,
                pz,
-               &run_pipe<T, N, px, px, pz>};
+               &run_pipe<T, N, px, px, pz>,
+               &run_y_layers<T, N, t0>,
+               {&run_z_layers<T, N, l0>, &run_z_layers<T, N, l1>, &run_z_layers<T, N, l2>,
+                &run_z_layers<T, N, gcd_int(l0, N)>}};
 }
 
 #define CMBX_SIZES(T)                                                                                     \
@@ -933,23 +988,33 @@ int lines_z_choices(int dtype, int N, int* out) {
   return e ? distinct(e->lines, out) : 0;
 }
 
+// The pass kernel for a tile choice and stage plan: plan 1 exists at the default tile only.
+PassFn choose(const PassFn* fns, PassFn alt, int i, int plan) {
+  if (i < 0) return nullptr;
+  if (plan == 0) return fns[i];
+  return i == 0 ? alt : nullptr;
+}
+
 hipError_t launch_pass_x(const FieldArgs& a, hipStream_t s) {
   const Entry* e = find(a.dtype, a.N);
-  const int i = e ? pick(e->tz, a.tile_x) : -1;
-  if (i < 0) return hipErrorInvalidValue;
-  return e->x[i](a, s);
+  const PassFn f = e ? choose(e->x, e->x1, pick(e->tz, a.tile_x), a.plan_x) : nullptr;
+  return f ? f(a, s) : hipErrorInvalidValue;
 }
 hipError_t launch_pass_y(const FieldArgs& a, hipStream_t s) {
   const Entry* e = find(a.dtype, a.N);
-  const int i = e ? pick(e->tz, a.tile_y) : -1;
-  if (i < 0) return hipErrorInvalidValue;
-  return e->y[i](a, s);
+  const PassFn f = e ? choose(e->y, e->y1, pick(e->tz, a.tile_y), a.plan_y) : nullptr;
+  return f ? f(a, s) : hipErrorInvalidValue;
 }
 hipError_t launch_pass_z(const FieldArgs& a, hipStream_t s) {
   const Entry* e = find(a.dtype, a.N);
-  const int i = e ? pick(e->lines, a.lines_z) : -1;
-  if (i < 0) return hipErrorInvalidValue;
-  return e->z[i](a, s);
+  const PassFn f = e ? choose(e->z, e->z1, pick(e->lines, a.lines_z), a.plan_z) : nullptr;
+  return f ? f(a, s) : hipErrorInvalidValue;
+}
+
+bool stage_plan_compiled(int dtype, int N, int which) {
+  const Entry* e = find(dtype, N);
+  if (!e) return false;
+  return (which == 0 ? e->x1 : which == 1 ? e->y1 : e->z1) != nullptr;
 }
 
 bool pipeline_shape(int dtype, int N, int* tx, int* ty, int* lz) {
@@ -965,6 +1030,29 @@ hipError_t launch_pipeline(const PipeLaunch& a, hipStream_t s) {
   const Entry* e = find(a.dtype, a.N);
   if (!e || a.nblocks < 1) return hipErrorInvalidValue;
   return e->pipe(a, s);
+}
+
+hipError_t launch_layers_c2c(int dtype, int N, void* buf, const void* tw, int nlayers, hipStream_t s) {
+  const Entry* e = find(dtype, N);
+  if (!e || nlayers < 1) return hipErrorInvalidValue;
+  return e->ylay(buf, tw, nlayers, s);
+}
+
+hipError_t launch_layers_c2r(int dtype, int N, void* buf, const void* tw, int nlayers, hipStream_t s) {
+  const Entry* e = find(dtype, N);
+  if (!e || nlayers < 1) return hipErrorInvalidValue;
+  for (int i = 0; i < kChoices; ++i)  // the first z tile that divides the layers' lines
+    if (((int64_t)nlayers * N) % e->lines[i] == 0) return e->zlay[i](buf, tw, nlayers, s);
+  return e->zlay[kChoices](buf, tw, nlayers, s);  // a tile that divides N
+}
+
+bool layers_supported(int dtype, int N, int nlayers) { return find(dtype, N) != nullptr && nlayers >= 1; }
+
+hipError_t noise_table_address(const float** out) {
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_bm_tab));
+  *out = static_cast<const float*>(p);
+  return e;
 }
 
 hipError_t upload_noise_tables(const float* host) {
@@ -998,6 +1086,12 @@ hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_zlist, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, (uint8_t*)a.fp, a.N,
                      a.lines);
   return hipGetLastError();
+}
+
+int resolve_tile_xy(int dtype, int N, int tile) {
+  const Entry* e = find(dtype, N);
+  const int i = e ? pick(e->tz, tile) : -1;
+  return i < 0 ? 0 : e->tz[i];
 }
 
 int resolve_lines_z(int dtype, int N, int lines_z) {

@@ -49,6 +49,8 @@ hipError_t launch_footprint(const FootprintArgs& a, hipStream_t s);
 // Lines per z workgroup that launch_pass_z uses for (dtype, N) and a lines_z option
 // (0 = default); 0 if not compiled.
 int resolve_lines_z(int dtype, int N, int lines_z);
+// Columns per x/y workgroup for a tile option (0 = default); 0 if not compiled.
+int resolve_tile_xy(int dtype, int N, int tile);
 
 struct FieldArgs {
   int dtype, N;
@@ -59,7 +61,10 @@ struct FieldArgs {
   int m_hi;            // largest |f|^2 of nonzero weight: the passes skip what lies beyond
   const void* fp;      // map footprint: only what it marks is made (NULL = the whole field)
   int tile_x, tile_y, lines_z;  // 0 = compiled default
+  int plan_x, plan_y, plan_z;   // FFT stage plan of each pass: 0, or 1 (the default tile only)
 };
+// Whether pass `which` (0 x, 1 y, 2 z) of (dtype, N) has the alternative stage plan 1.
+bool stage_plan_compiled(int dtype, int N, int which);
 
 // Pass 1: noise + weights + Hermitian planes + inverse FFT along x.
 hipError_t launch_pass_x(const FieldArgs& a, hipStream_t s);
@@ -67,6 +72,17 @@ hipError_t launch_pass_x(const FieldArgs& a, hipStream_t s);
 hipError_t launch_pass_y(const FieldArgs& a, hipStream_t s);
 // Pass 3: complex-to-real inverse FFT along z (unpacks the iz = 0 / N/2 column).
 hipError_t launch_pass_z(const FieldArgs& a, hipStream_t s);
+
+// Stacked layers [nlayers][N][N/2] complex (plan precision), in place: c2c transforms
+// along the middle axis of every layer (launch_layers_c2c), then c2r transforms of the
+// nlayers N contiguous lines of N/2 complex, column 0 packing the rows of frequency 0 and
+// N/2, into N reals each (launch_layers_c2r). tw: the N roots exp(2 pi i m / N).
+// layers_supported: N is compiled (any nlayers >= 1).
+hipError_t launch_layers_c2c(int dtype, int N, void* buf, const void* tw, int nlayers, hipStream_t s);
+hipError_t launch_layers_c2r(int dtype, int N, void* buf, const void* tw, int nlayers, hipStream_t s);
+bool layers_supported(int dtype, int N, int nlayers);
+// Device address of the binary32 Box-Muller tables on the current device.
+hipError_t noise_table_address(const float** out);
 
 // Number of binary32 Box-Muller table entries and their upload to the current device
 // (before the first single-precision field there; the values never change).

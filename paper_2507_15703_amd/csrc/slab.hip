@@ -1,0 +1,429 @@
+// Column stage of flat boxes and the gather from stacked layers, for gfx950.
+//
+// Flat box N x N x M (Sec. II C, eq. finalpbox): the 3-D Fourier method (Sec. II D 1) draws
+// every mode of the half grid in y and transforms along z first (this file), then along x
+// and y (the layer passes of kernels.hip). The 2-D (hybrid) Fourier method (Sec. II D 2)
+// draws, for every column (k_x, k_y), h correlated values S g at heights z_0 .. z_{h-1}
+// from one precomputed factor S with S S^T = Gamma (this file), then runs the same x and y
+// passes on its h layers.
+#include <hip/hip_runtime.h>
+
+#include "fft_device.hpp"
+#include "noise_device.hpp"
+#include "slab.hpp"
+
+namespace cmbx {
+namespace {
+
+__device__ __forceinline__ int fq(int i, int n) { return i <= n - i ? i : n - i; }
+
+constexpr int slab_nt(int work) { return work >= 4096 ? 512 : work >= 2048 ? 256 : work >= 1024 ? 128 : 64; }
+constexpr int kTabFloats = 768;  // binary32 Box-Muller tables (noise_device.hpp layout)
+
+template <typename T>
+__device__ __forceinline__ const float* stage_tab(float* lds, const float* __restrict__ g, int tid, int nt) {
+  if constexpr (sizeof(T) == 4) {
+    for (int i = tid; i < kTabFloats; i += nt) lds[i] = g[i];
+    return lds;
+  } else {
+    return nullptr;
+  }
+}
+
+// ------------------------------------------------------------------ flat box modes
+// Mode (ix, iy, iz), iy = 0 .. N/2, of the half grid in y: Philox counter (iz >> 1, iy, ix, 2),
+// words (x0, x1) for even iz and (x2, x3) for odd; generic modes half[row(s)][|fz|] (g_re + i g_im);
+// on the planes iy = 0 and N/2 the mode and (-ix, -iz) are conjugate, the smaller ix M + iz
+// drawn; the self-conjugate modes are real, full[2 c + (iz == M/2)] g_re with c the number
+// of x, y indices equal to N/2. Zero weight: +0 (then conjugated like any value).
+template <typename T>
+__device__ __forceinline__ cpx<T> flat_mode(int N, int MZ, int ix, int iy, int iz, uint32_t k0, uint32_t k1,
+                                            const int* __restrict__ sidx, const T* __restrict__ half,
+                                            const T* __restrict__ full, const float* __restrict__ tab) {
+  const int fx = fq(ix, N), fy = fq(iy, N), fz = fq(iz, MZ);
+  int dx = ix, dz = iz;
+  bool cj = false, self = false;
+  if (iy == 0 || iy == N / 2) {
+    const int px = ix == 0 ? 0 : N - ix, pz = iz == 0 ? 0 : MZ - iz;
+    const int own = ix * MZ + iz, par = px * MZ + pz;
+    if (own == par) {
+      self = true;
+    } else if (own > par) {
+      dx = px;
+      dz = pz;
+      cj = true;
+    }
+  }
+  const T w = self ? full[2 * ((ix == N / 2) + (iy == N / 2)) + (iz == MZ / 2)]
+                   : half[(size_t)sidx[fx * fx + fy * fy] * (MZ / 2 + 1) + fz];
+  if (w == T(0)) {
+    const cpx<T> z = {T(0), T(0)};
+    return cj ? conj(z) : z;
+  }
+  const uint2 wd = [&] {
+    const uint4 q = philox4x32_10(make_uint4((uint32_t)dz >> 1, (uint32_t)iy, (uint32_t)dx, 2u), k0, k1);
+    return (dz & 1) ? make_uint2(q.z, q.w) : make_uint2(q.x, q.y);
+  }();
+  T gr, gi;
+  normal_pair(wd.x, wd.y, gr, gi, tab);
+  if (self) return {w * gr, T(0)};
+  const cpx<T> v = {w * gr, w * gi};
+  return cj ? conj(v) : v;
+}
+
+// Element n of column q at p[n * stride + q] (the layers: n is the layer, q the packed y
+// column), for the first ncols columns (a ragged last tile).
+template <typename T>
+struct ColumnWriter {
+  cpx<T>* p;
+  size_t stride;
+  int ncols;
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const {
+    if (q < ncols) p[(size_t)n * stride + q] = v;
+  }
+  __device__ __forceinline__ void done() const {}
+};
+
+// Workgroup = (ix, C consecutive packed y columns; the last tile of a row may hold fewer,
+// the rest transform zeros and are not written): the C x MZ modes into LDS (one Philox
+// call per pair of neighbouring iz; column 0 packs the planes iy = 0 and N/2 as A + i B),
+// the length-MZ inverse transform along z, and layer n of every column written (C
+// consecutive complex per layer).
+template <typename T, int MZ, int C>
+__global__ __launch_bounds__(slab_nt(MZ * C)) void k_flat_columns(cpx<T>* __restrict__ buf, int N,
+                                                                  const int* __restrict__ sidx,
+                                                                  const T* __restrict__ half,
+                                                                  const T* __restrict__ full,
+                                                                  const cpx<T>* __restrict__ twz, uint32_t k0,
+                                                                  uint32_t k1, const float* __restrict__ bmg) {
+  constexpr int NT = slab_nt(MZ * C);
+  __shared__ cpx<T> tile[C * MZ];
+  __shared__ cpx<T> tw[MZ];
+  __shared__ float tabl[sizeof(T) == 4 ? kTabFloats : 1];
+  using Lds = LdsIO<T, MZ, C, true>;
+  const int tid = threadIdx.x;
+  const int M2 = N / 2;
+  const int tiles = (M2 + C - 1) / C;
+  const int ix = blockIdx.x / tiles;
+  const int c0 = (blockIdx.x % tiles) * C;
+  const int ncols = M2 - c0 < C ? M2 - c0 : C;
+  for (int i = tid; i < MZ; i += NT) tw[i] = twz[i];
+  const float* tab = stage_tab<T>(tabl, bmg, tid, NT);
+  __syncthreads();
+  const int fx = fq(ix, N);
+  for (int s = tid; s < C * (MZ / 2); s += NT) {
+    const int q = s % C, pz = s / C;
+    const int iyc = c0 + q, iz0 = 2 * pz;
+    cpx<T> v[2];
+    if (q >= ncols) {
+      v[0] = v[1] = {T(0), T(0)};
+    } else if (iyc == 0) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const cpx<T> a = flat_mode<T>(N, MZ, ix, 0, iz0 + t, k0, k1, sidx, half, full, tab);
+        const cpx<T> b = flat_mode<T>(N, MZ, ix, M2, iz0 + t, k0, k1, sidx, half, full, tab);
+        v[t] = {a.x - b.y, a.y + b.x};
+      }
+    } else {
+      const T* row = half + (size_t)sidx[fx * fx + iyc * iyc] * (MZ / 2 + 1);
+      const uint4 w = philox4x32_10(make_uint4((uint32_t)pz, (uint32_t)iyc, (uint32_t)ix, 2u), k0, k1);
+      v[0] = weighted<T>(row[fq(iz0, MZ)], w.x, w.y, tab);
+      v[1] = weighted<T>(row[fq(iz0 + 1, MZ)], w.z, w.w, tab);
+    }
+    tile[Lds::index(q, iz0)] = v[0];
+    tile[Lds::index(q, iz0 + 1)] = v[1];
+  }
+  __syncthreads();
+  Lds first{tile};
+  ColumnWriter<T> last{buf + (size_t)ix * M2 + c0, (size_t)N * M2, ncols};
+  fft_run<T, MZ, C, NT, true, 1, 0>(tw, tile, first, last, tid);
+}
+
+// Unpacked modes [N][N/2+1][M] (tests): one thread per mode.
+template <typename T>
+__global__ __launch_bounds__(256) void k_flat_modes_debug(cpx<T>* __restrict__ out, int N, int MZ,
+                                                          const int* __restrict__ sidx, const T* __restrict__ half,
+                                                          const T* __restrict__ full, uint32_t k0, uint32_t k1,
+                                                          const float* __restrict__ bmg) {
+  __shared__ float tabl[sizeof(T) == 4 ? kTabFloats : 1];
+  const float* tab = stage_tab<T>(tabl, bmg, threadIdx.x, 256);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)N * (N / 2 + 1) * MZ;
+  if (i >= total) return;
+  const int iz = (int)(i % MZ);
+  const int64_t t = i / MZ;
+  const int iy = (int)(t % (N / 2 + 1));
+  const int ix = (int)(t / (N / 2 + 1));
+  out[i] = flat_mode<T>(N, MZ, ix, iy, iz, k0, k1, sidx, half, full, tab);
+}
+
+// ------------------------------------------------------------------ hybrid columns
+// Column (ix, iy), iy = 0 .. N/2: h unit normal pairs from Philox counter (j >> 1, iy, ix, 1)
+// (words (x0, x1) for even layers j, (x2, x3) for odd), times the factor: v = F g with F
+// the row's S / sqrt2 for a generic column, the real part only with S for the four
+// self-conjugate columns; on the rows iy = 0 and N/2 the column (ix) and (-ix) are
+// conjugate, the smaller ix drawn. Sums over m in order, in T.
+template <typename T, int HMAX>
+__device__ __forceinline__ void hybrid_column(int N, int h, int ix, int iy, uint32_t k0, uint32_t k1,
+                                              const int* __restrict__ sidx, const T* __restrict__ S,
+                                              const T* __restrict__ Sfull, const float* __restrict__ tab,
+                                              T (&vr)[HMAX], T (&vi)[HMAX]) {
+  const int M2 = N / 2;
+  const bool row = iy == 0 || iy == M2;
+  const int px = ix == 0 ? 0 : N - ix;
+  const bool self = row && ix == px;
+  const bool flip = row && ix > px;
+  const int dx = flip ? px : ix;
+  T gr[HMAX], gi[HMAX];
+#pragma unroll
+  for (int q = 0; q < HMAX / 2; ++q) {
+    if (2 * q < h) {
+      const uint4 w = philox4x32_10(make_uint4((uint32_t)q, (uint32_t)iy, (uint32_t)dx, 1u), k0, k1);
+      normal_pair(w.x, w.y, gr[2 * q], gi[2 * q], tab);
+      normal_pair(w.z, w.w, gr[2 * q + 1], gi[2 * q + 1], tab);
+    } else {
+      gr[2 * q] = gi[2 * q] = gr[2 * q + 1] = gi[2 * q + 1] = T(0);
+    }
+  }
+  const int fx = fq(ix, N), fy = fq(iy, N);
+  const T* F = self ? Sfull + (size_t)((ix == M2) + (iy == M2)) * h * h : S + (size_t)sidx[fx * fx + fy * fy] * h * h;
+#pragma unroll
+  for (int j = 0; j < HMAX; ++j) {
+    T ar = T(0), ai = T(0);
+    if (j < h) {
+#pragma unroll
+      for (int m = 0; m < HMAX; ++m) {
+        if (m < h) {
+          const T f = F[j * h + m];
+          ar += f * gr[m];
+          ai += f * gi[m];
+        }
+      }
+    }
+    vr[j] = ar;
+    vi[j] = self ? T(0) : (flip ? -ai : ai);
+  }
+}
+
+// One thread per packed column (ix, iyc), iyc < N/2 (column 0 packs the rows iy = 0 and
+// N/2 as A + i B); with `unpacked`, one per column (ix, iy), iy <= N/2, into [h][N][N/2+1].
+template <typename T, int HMAX>
+__global__ __launch_bounds__(256) void k_hybrid_columns(cpx<T>* __restrict__ buf, int N, int h,
+                                                        const int* __restrict__ sidx, const T* __restrict__ S,
+                                                        const T* __restrict__ Sfull, uint32_t k0, uint32_t k1,
+                                                        const float* __restrict__ bmg, int unpacked) {
+  __shared__ float tabl[sizeof(T) == 4 ? kTabFloats : 1];
+  const float* tab = stage_tab<T>(tabl, bmg, threadIdx.x, 256);
+  __syncthreads();
+  const int M2 = N / 2;
+  const int W = unpacked ? M2 + 1 : M2;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)N * W) return;
+  const int ix = (int)(t / W), iyc = (int)(t % W);
+  T ar[HMAX], ai[HMAX];
+  hybrid_column<T, HMAX>(N, h, ix, iyc, k0, k1, sidx, S, Sfull, tab, ar, ai);
+  if (unpacked) {
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j)
+      if (j < h) buf[((size_t)j * N + ix) * (M2 + 1) + iyc] = {ar[j], ai[j]};
+    return;
+  }
+  if (iyc == 0) {
+    T br[HMAX], bi[HMAX];
+    hybrid_column<T, HMAX>(N, h, ix, M2, k0, k1, sidx, S, Sfull, tab, br, bi);
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j)
+      if (j < h) buf[((size_t)j * N + ix) * M2] = {ar[j] - bi[j], ai[j] + br[j]};
+  } else {
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j)
+      if (j < h) buf[((size_t)j * N + ix) * M2 + iyc] = {ar[j], ai[j]};
+  }
+}
+
+// ------------------------------------------------------------------ layer gather
+template <typename T>
+__device__ __forceinline__ void keys_or_linear(T f, T* w, bool cubic) {
+  if (cubic) {  // Keys cubic convolution, a = -1/2, at distances 1 + f, f, 1 - f, 2 - f
+    w[0] = f * (T(-0.5) + f * (T(1.0) - T(0.5) * f));
+    w[1] = T(1.0) + f * f * (T(-2.5) + T(1.5) * f);
+    w[2] = f * (T(0.5) + f * (T(2.0) - T(1.5) * f));
+    w[3] = f * f * (T(-0.5) + T(0.5) * f);
+  } else {
+    w[0] = T(1.0) - f;
+    w[1] = f;
+  }
+}
+
+__device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <typename T, int K>
+struct SlabTaps {
+  typedef T vec __attribute__((ext_vector_type(K), aligned(sizeof(T))));
+};
+
+// One thread per pixel: p = (r n + o) (1 / dp) in FP64, floor(p) picks the stencil; x and y
+// wrap modulo N; z wraps modulo nz, or (non-periodic layers) the pixel is NaN when its
+// stencil leaves [0, nz). Weights and sums in T; the K taps along y (contiguous) are one
+// vector load unless they wrap.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_slab_gather(const T* __restrict__ field, int N, int nz, int periodic,
+                                                     double scale, double3 obs, double r,
+                                                     const double* __restrict__ dirs, int64_t npix,
+                                                     T* __restrict__ out) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npix) return;
+  const double o[3] = {obs.x, obs.y, obs.z};
+  int i0[3];
+  T w[3][4];
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double p = (r * dirs[3 * i + d] + o[d]) * scale;
+    if (!(p > -1.0e9 && p < 1.0e9)) p = 0.0;
+    const double fl = floor(p);
+    const int n = d < 2 ? N : nz;
+    if (d < 2 || periodic) {
+      int base = (int)fl % n;
+      base = base < 0 ? base + n : base;
+      i0[d] = base - (K == 4 ? 1 : 0);
+    } else {
+      i0[d] = (int)fl - (K == 4 ? 1 : 0);
+      inside = i0[d] >= 0 && i0[d] + K <= nz;
+    }
+    keys_or_linear<T>((T)(p - fl), w[d], K == 4);
+  }
+  if (!inside) {
+    out[i] = __builtin_nan("");
+    return;
+  }
+  const bool contiguous = i0[1] >= 0 && i0[1] + K <= N;
+  T acc = T(0);
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const int iz = periodic ? wrapn(i0[2] + c, nz) : i0[2] + c;
+    T accz = T(0);
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      const T* row = field + ((size_t)iz * N + wrapn(i0[0] + a, N)) * N;
+      T q[K];
+      if (contiguous) {
+        const typename SlabTaps<T, K>::vec v = *reinterpret_cast<const typename SlabTaps<T, K>::vec*>(row + i0[1]);
+#pragma unroll
+        for (int b = 0; b < K; ++b) q[b] = v[b];
+      } else {
+#pragma unroll
+        for (int b = 0; b < K; ++b) q[b] = row[wrapn(i0[1] + b, N)];
+      }
+      T s = T(0);
+#pragma unroll
+      for (int b = 0; b < K; ++b) s += w[1][b] * q[b];
+      accz += w[0][a] * s;
+    }
+    acc += w[2][c] * accz;
+  }
+  out[i] = acc;
+}
+
+// ------------------------------------------------------------------ dispatch
+template <typename T, int MZ>
+constexpr int flat_cols() {
+  // columns per workgroup: 16 (FP32) / 8 (FP64) while the tile stays within 64 KB
+  int c = sizeof(T) == 4 ? 16 : 8;
+  while (c > 1 && c * MZ * (int)sizeof(cpx<T>) > 65536) c /= 2;
+  return c;
+}
+
+template <typename T, int MZ>
+hipError_t run_flat(const SlabColumnsArgs& a, hipStream_t s) {
+  constexpr int C = flat_cols<T, MZ>();
+  const int tiles = (a.N / 2 + C - 1) / C;
+  const T* half = (const T*)a.table;
+  const T* full = half + (size_t)a.rows * (MZ / 2 + 1);
+  hipLaunchKernelGGL((k_flat_columns<T, MZ, C>), dim3((unsigned)(a.N * tiles)), dim3(slab_nt(MZ * C)), 0, s,
+                     (cpx<T>*)a.buf, a.N, a.sidx, half, full, (const cpx<T>*)a.twz, a.k0, a.k1, a.bm_tab);
+  return hipGetLastError();
+}
+
+using FlatFn = hipError_t (*)(const SlabColumnsArgs&, hipStream_t);
+struct FlatEntry {
+  int M;
+  FlatFn f32, f64;
+};
+#define CMBX_FLAT(MZ) FlatEntry{MZ, &run_flat<float, MZ>, &run_flat<double, MZ>}
+const FlatEntry kFlat[] = {CMBX_FLAT(8),   CMBX_FLAT(12),  CMBX_FLAT(16),  CMBX_FLAT(24),  CMBX_FLAT(32),
+                           CMBX_FLAT(48),  CMBX_FLAT(64),  CMBX_FLAT(96),  CMBX_FLAT(128), CMBX_FLAT(192),
+                           CMBX_FLAT(256), CMBX_FLAT(384), CMBX_FLAT(512)};
+#undef CMBX_FLAT
+
+const FlatEntry* find_flat(int M) {
+  for (const FlatEntry& e : kFlat)
+    if (e.M == M) return &e;
+  return nullptr;
+}
+
+template <typename T>
+hipError_t run_hybrid(const SlabColumnsArgs& a, int unpacked, hipStream_t s) {
+  const T* S = (const T*)a.table;
+  const T* Sfull = S + (size_t)a.rows * a.h * a.h;
+  const int64_t threads = (int64_t)a.N * (unpacked ? a.N / 2 + 1 : a.N / 2);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (a.h <= 16)
+    hipLaunchKernelGGL((k_hybrid_columns<T, 16>), grid, dim3(256), 0, s, (cpx<T>*)a.buf, a.N, a.h, a.sidx, S, Sfull,
+                       a.k0, a.k1, a.bm_tab, unpacked);
+  else
+    hipLaunchKernelGGL((k_hybrid_columns<T, kSlabMaxLayers>), grid, dim3(256), 0, s, (cpx<T>*)a.buf, a.N, a.h, a.sidx,
+                       S, Sfull, a.k0, a.k1, a.bm_tab, unpacked);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool slab_depth_compiled(int M) { return find_flat(M) != nullptr; }
+
+hipError_t launch_slab_columns(const SlabColumnsArgs& a, hipStream_t s) {
+  if (a.method == kSlabHybrid) {
+    if (a.h < 1 || a.h > kSlabMaxLayers) return hipErrorInvalidValue;
+    return a.dtype == 1 ? run_hybrid<float>(a, 0, s) : run_hybrid<double>(a, 0, s);
+  }
+  const FlatEntry* e = find_flat(a.M);
+  if (!e) return hipErrorInvalidValue;
+  return a.dtype == 1 ? e->f32(a, s) : e->f64(a, s);
+}
+
+hipError_t launch_slab_columns_debug(const SlabColumnsArgs& a, hipStream_t s) {
+  if (a.method == kSlabHybrid) {
+    if (a.h < 1 || a.h > kSlabMaxLayers) return hipErrorInvalidValue;
+    return a.dtype == 1 ? run_hybrid<float>(a, 1, s) : run_hybrid<double>(a, 1, s);
+  }
+  const int64_t total = (int64_t)a.N * (a.N / 2 + 1) * a.M;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  const size_t hs = (size_t)a.rows * (a.M / 2 + 1);
+  if (a.dtype == 1)
+    hipLaunchKernelGGL(k_flat_modes_debug<float>, grid, dim3(256), 0, s, (cpx<float>*)a.buf, a.N, a.M, a.sidx,
+                       (const float*)a.table, (const float*)a.table + hs, a.k0, a.k1, a.bm_tab);
+  else
+    hipLaunchKernelGGL(k_flat_modes_debug<double>, grid, dim3(256), 0, s, (cpx<double>*)a.buf, a.N, a.M, a.sidx,
+                       (const double*)a.table, (const double*)a.table + hs, a.k0, a.k1, a.bm_tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_gather(const SlabGatherArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n_pix + 255) / 256));
+  const double3 o = make_double3(a.obs[0], a.obs[1], a.obs[2]);
+  const bool cubic = a.interp == 2;
+  if (a.dtype == 1) {
+    auto k = cubic ? k_slab_gather<float, 4> : k_slab_gather<float, 2>;
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const float*)a.field, a.N, a.nz, a.periodic_z, a.scale, o, a.r,
+                       a.dirs, a.n_pix, (float*)a.out);
+  } else {
+    auto k = cubic ? k_slab_gather<double, 4> : k_slab_gather<double, 2>;
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const double*)a.field, a.N, a.nz, a.periodic_z, a.scale, o, a.r,
+                       a.dirs, a.n_pix, (double*)a.out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cmbx

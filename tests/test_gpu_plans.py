@@ -1,0 +1,96 @@
+"""FFT stage plans (CMBX_OPT_PLAN_X/Y/Z): every compiled plan gives the oracle's field and
+map, the autotuner chooses among tiles and plans, and the options read back as set."""
+import numpy as np
+import pytest
+
+from oracle import field as ofield
+from oracle import gather as ogather
+from oracle import noise as onoise
+from paper_2507_15703_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL = {"f32": 1e-5, "f64": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def cmbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_15703_amd import cmbx as c
+    c.lib()
+    return c
+
+
+def _pow2_part(n):
+    return n & -n
+
+
+def _rel(a, b):
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(np.asarray(a, dtype=np.float64) - b)) / np.sqrt(np.mean(b**2)))
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N", [64, 96, 128, 192])
+def test_every_plan_matches_oracle(cmbx, N, dt):
+    """Lengths whose power-of-two part is at least 32 have a second plan: x and y at
+    64 = 8 8 | 4 16, 96 = 3 8 4 | 3 4 8, 128 = 16 8 | 8 16, 192 = 3 8 8 | 3 4 16; z (length
+    N/2) at 32, 64 and 96, not at 48 = 3 16, where asking for plan 1 is an error."""
+    has = [_pow2_part(N) >= 32, _pow2_part(N) >= 32, _pow2_part(N // 2) >= 32]
+    k, pk = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N // 4)
+    p = cmbx.Plan(N, 1.0, dt, interp="tricubic")
+    p.spectrum_table(k, pk)
+    ref = ofield.field(onoise.halfgrid(N, 1.0, 8, k, pk))
+    dirs_np = workloads.cap_directions(25.0, 24, 80)
+    dirs = torch.tensor(dirs_np, device="cuda")
+    mref = ogather.gather(ref, 1.0, 0.45, dirs_np, "tricubic")
+    for which in range(3):
+        if not has[which]:
+            with pytest.raises(cmbx.CmbxError):
+                cmbx.plan_set(p.handle, cmbx.OPT_PLAN_X + which, 1)
+    for plans in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1)]:
+        plans = tuple(v if has[i] else 0 for i, v in enumerate(plans))
+        p.set_tiles(0, 0, plans=plans)
+        assert p.shapes()[3] == plans
+        assert _rel(p.debug_field(8).cpu().numpy(), ref) <= TOL[dt], plans
+        assert _rel(p.simulate_patch(8, 0.45, dirs).cpu().numpy()[0], mref) <= TOL[dt], plans
+    p.close()
+
+
+def test_plan_options_and_tiles(cmbx):
+    N = 128
+    p = cmbx.Plan(N, 1.0, "f32")
+    tiles = cmbx.tile_choices("f32", N, 0)
+    lines = cmbx.tile_choices("f32", N, 1)
+    p.set_tiles(0, 0, tile_x=tiles[1])
+    assert p.shapes()[0] == tiles[1]
+    cmbx.plan_set(p.handle, cmbx.OPT_PLAN_X, 1)          # plan 1 moves x to its default tile
+    assert p.shapes()[0] == tiles[0] and p.shapes()[3][0] == 1
+    cmbx.plan_set(p.handle, cmbx.OPT_TILE_X, tiles[1])   # another tile takes plan 0
+    assert p.shapes()[3][0] == 0
+    cmbx.plan_set(p.handle, cmbx.OPT_PLAN_Z, 1)
+    assert p.shapes()[2] == lines[0] and p.shapes()[3][2] == 1
+    with pytest.raises(cmbx.CmbxError):
+        cmbx.plan_set(p.handle, cmbx.OPT_PLAN_Y, 2)
+    p.close()
+    q = cmbx.Plan(16, 1.0, "f32")                           # 16 is one stage: no second plan
+    with pytest.raises(cmbx.CmbxError):
+        cmbx.plan_set(q.handle, cmbx.OPT_PLAN_X, 1)
+    q.close()
+
+
+def test_autotune_records_plans(cmbx, tmp_path):
+    N = 128
+    k, pk = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N // 4)
+    p = cmbx.Plan(N, 1.0, "f32")
+    p.spectrum_table(k, pk)
+    cache = str(tmp_path / "tune.json")
+    t = p.autotune(reps=2, cache_path=cache)
+    assert len(t["plans"]) == 3 and all(v in (0, 1) for v in t["plans"])
+    assert tuple(t["plans"]) == p.shapes()[3]
+    ref = ofield.field(onoise.halfgrid(N, 1.0, 2, k, pk))
+    assert _rel(p.debug_field(2).cpu().numpy(), ref) <= 1e-5
+    again = p.autotune(reps=2, cache_path=cache)
+    assert again["cached"] and again["plans"] == t["plans"]
+    p.close()

@@ -1,0 +1,208 @@
+"""Flat N x N x M boxes and the 2-D (hybrid) Fourier method on the GPU against the FP64
+oracle (``oracle.slab``), through the C ABI (cmbx_slab_*).
+
+Bars. Flat boxes (3-D method): the modes bit-identical (noise of the plan precision,
+weights rounded once), layers and maps within 1e-5 (FP32) and 1e-12 (FP64) of
+max |d| / rms. Hybrid: the factor S is the library's own FP64 eigendecomposition and the
+oracle's LAPACK one, so they agree to rounding times the conditioning of Gamma; the tests
+use spectra whose column covariances have condition numbers 300 - 1200 (bars 1e-5 FP32,
+1e-11 FP64: eps kappa with kappa <= 1e4 and the h-term sums) and, separately, a spectrum
+from the paper's programme (ill-conditioned Gamma: the symmetric root's error is then
+bounded by sqrt(eps) of the largest eigenvalue, 1e-7 relative for FP64; FP32 stays at 1e-5).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import inversion as oinv
+from oracle import slab as oslab
+from paper_2507_15703_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NPDT = {"f32": np.float32, "f64": np.float64}
+
+
+@pytest.fixture(scope="module")
+def cmbx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_15703_amd import cmbx as c
+    c.lib()
+    return c
+
+
+def _rel(a, b):
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(np.asarray(a, dtype=np.float64) - b)) / np.sqrt(np.mean(np.abs(b) ** 2)))
+
+
+def _bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint32 if a.dtype in (np.float32, np.complex64) else np.uint64)
+
+
+def _gauss(dp, cells):
+    """P_inf = exp(-(k/k_c)^2), k_c = 2 pi / (cells dp): a Gaussian covariance of width ~cells dp."""
+    kc = 2 * math.pi / (cells * dp)
+    k = np.linspace(0.0, 5.0 * kc, 3000)
+    return k, np.exp(-((k / kc) ** 2))
+
+
+# ------------------------------------------------------------------ flat box, 3-D method
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N,M", [(16, 8), (32, 12), (24, 16)])
+def test_flat_modes_bit_exact(cmbx, N, M, dt):
+    dp = 0.05
+    k, p = _gauss(dp, 2.0)
+    s = cmbx.Slab("flat", N, M, dp, dtype=dt)
+    s.spectrum(k, p)
+    for seed in (0, 9, 2**64 - 1):
+        got = s.debug_columns(seed).cpu().numpy()
+        ref = oslab.flat_halfgrid(N, M, dp, seed, k, p, dtype=NPDT[dt])
+        assert np.array_equal(_bits(got), _bits(ref)), (N, M, dt, seed)
+    s.close()
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f64", 1e-12)])
+@pytest.mark.parametrize("N,M", [(32, 16), (64, 24), (48, 32)])
+def test_flat_layers(cmbx, N, M, dt, tol):
+    dp = 0.03
+    k, p = _gauss(dp, 3.0)
+    s = cmbx.Slab("flat", N, M, dp, dtype=dt)
+    s.spectrum(k, p)
+    got = s.debug_layers(4).cpu().numpy()
+    ref = oslab.flat_layers(oslab.flat_halfgrid(N, M, dp, 4, k, p, dtype=NPDT[dt]))
+    assert _rel(got, ref) <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f64", 1e-12)])
+@pytest.mark.parametrize("interp", ["trilinear", "tricubic"])
+def test_flat_maps(cmbx, dt, tol, interp):
+    """A 15-degree cap on the unit sphere in a 96 x 96 x 24 box centred on the cap
+    (Sec. II D 1, Fig. 2a), batch of two; z wraps modulo M."""
+    N, M, dp, r = 96, 24, 0.0064, 1.0
+    k, p = _gauss(dp, 2.5)
+    s = cmbx.Slab("flat", N, M, dp, dtype=dt, batch=2, interp=interp)
+    s.spectrum(k, p)
+    z_min = math.cos(math.radians(15.0))
+    obs = s.observer_for_cap(r, z_min)
+    s.set_observer(obs)
+    dirs = workloads.cap_directions(15.0, 40, 96)
+    out = s.simulate(11, r, torch.tensor(dirs, device="cuda")).cpu().numpy()
+    for b in range(2):
+        lay = oslab.flat_layers(oslab.flat_halfgrid(N, M, dp, 11 + b, k, p))
+        ref = oslab.gather_layers(lay, dp, r, dirs, interp, obs, periodic_z=True)
+        assert _rel(out[b], ref) <= tol, b
+    s.close()
+
+
+# ------------------------------------------------------------------ hybrid (2-D method)
+def _cond(N, M, h, dp, k, p):
+    xi = oslab.column_xi(N, M, dp, k, p, h)
+    f = np.arange(N // 2 + 1)
+    s = np.unique((f[:, None] ** 2 + f[None, :] ** 2).ravel())
+    w = np.linalg.eigvalsh(np.stack([oslab.gamma(xi[v]) for v in s]))
+    return float(np.max(w[:, -1] / w[:, 0]))
+
+
+@pytest.mark.parametrize("N,M,h", [(32, 16, 6), (48, 24, 9)])
+def test_hybrid_factors_match_oracle(cmbx, N, M, h):
+    dp = 0.04
+    k, p = _gauss(dp, 6.0)
+    assert _cond(N, M, h, dp, k, p) < 1e4
+    s = cmbx.Slab("hybrid", N, M, dp, h=h, dtype="f64")
+    s.spectrum(k, p)
+    S = oslab.hybrid_factors(N, M, h, dp, k, p)
+    for v in (0, 1, 2, 5, 8, (N // 2) ** 2, 2 * (N // 2) ** 2):
+        got = s.factor(v)
+        assert np.allclose(got, got.T, rtol=0, atol=1e-15 * np.abs(got).max())
+        assert np.max(np.abs(got - S[v])) <= 1e-12 * np.abs(S[v]).max(), v
+    with pytest.raises(cmbx.CmbxError):
+        s.factor(3)   # not a sum of two squares
+    s.close()
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f64", 1e-11)])
+def test_hybrid_columns_and_layers(cmbx, dt, tol):
+    N, M, h, dp = 32, 16, 6, 0.04
+    k, p = _gauss(dp, 6.0)
+    s = cmbx.Slab("hybrid", N, M, dp, h=h, dtype=dt)
+    s.spectrum(k, p)
+    for seed in (2, 2**40 + 3):
+        cols = s.debug_columns(seed).cpu().numpy()
+        ref = oslab.hybrid_columns(N, M, h, dp, seed, k, p, dtype=NPDT[dt])
+        assert _rel(cols, ref) <= tol, seed
+        lay = s.debug_layers(seed).cpu().numpy()
+        assert _rel(lay, oslab.hybrid_layers(ref)) <= tol, seed
+    s.close()
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f64", 1e-11)])
+@pytest.mark.parametrize("interp", ["trilinear", "tricubic"])
+def test_hybrid_maps_on_a_cap(cmbx, dt, tol, interp):
+    """A 10-degree cap of the unit sphere sampled from h = 6 layers of a 64 x 64 x 16 box,
+    the layers centred on the cap (Sec. II D 2, Fig. 2b); pixels below the cap, whose
+    stencils leave the layers, are NaN on both sides."""
+    N, M, h, dp, r = 64, 16, 6, 0.011, 1.0
+    k, p = _gauss(dp, 6.0)
+    s = cmbx.Slab("hybrid", N, M, dp, h=h, dtype=dt, batch=2, interp=interp)
+    s.spectrum(k, p)
+    z_min = math.cos(math.radians(10.0))
+    obs = s.observer_for_cap(r, z_min)
+    s.set_observer(obs)
+    dirs = np.concatenate([workloads.cap_directions(10.0, 24, 64), workloads.cap_directions(25.0, 2, 8)[-8:]])
+    out = s.simulate(21, r, torch.tensor(dirs, device="cuda")).cpu().numpy()
+    for b in range(2):
+        ref = oslab.gather_layers(oslab.hybrid_layers(oslab.hybrid_columns(N, M, h, dp, 21 + b, k, p)), dp, r, dirs,
+                                  interp, obs, periodic_z=False)
+        inside = np.isfinite(ref)
+        assert inside[: 24 * 64].all() and not inside[-8:].any()
+        assert np.array_equal(np.isnan(out[b]), ~inside)
+        assert _rel(out[b][inside], ref[inside]) <= tol, b
+    s.close()
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f64", 1e-7)])
+def test_hybrid_programme_spectrum(cmbx, dt, tol):
+    """The paper's setting on the unit sphere: C_l of the synthetic family with a Gaussian
+    beam b = 0.02 rad (eq. cl), the programme's P_inf for a 12-degree cap (Sec. II B), h = 8
+    layers of a 64 x 64 x 32 box spaced dp = 0.85 b / 5 x 2. Its column covariances are
+    ill-conditioned (the paper's reason for the eigendecomposition)."""
+    N, M, h, b, r = 64, 32, 8, 0.02, 1.0
+    dp = 2 * 0.85 * b / 5
+    lmax = int(4.0 / b)
+    cl = workloads.synthetic_cl(lmax, ld=1.0 / b)
+    _, bb, k, A, c = oinv.programme(cl, r, math.radians(12.0), b, math.pi / dp)
+    _, p = oinv.solve(A, bb, c)
+    s = cmbx.Slab("hybrid", N, M, dp, h=h, dtype=dt, interp="tricubic")
+    s.spectrum(k, p)
+    z_min = math.cos(math.radians(12.0))
+    obs = s.observer_for_cap(r, z_min)
+    s.set_observer(obs)
+    dirs = workloads.cap_directions(12.0, 24, 64)
+    got = s.simulate(5, r, torch.tensor(dirs, device="cuda")).cpu().numpy()[0]
+    ref = oslab.gather_layers(oslab.hybrid_layers(oslab.hybrid_columns(N, M, h, dp, 5, k, p)), dp, r, dirs,
+                              "tricubic", obs, periodic_z=False)
+    assert np.all(np.isfinite(ref))
+    assert _rel(got, ref) <= tol
+    s.close()
+
+
+def test_slab_errors(cmbx):
+    with pytest.raises(cmbx.CmbxError):
+        cmbx.Slab("hybrid", 32, 16, 0.1, h=33)      # h beyond 32
+    with pytest.raises(cmbx.CmbxError):
+        cmbx.Slab("hybrid", 32, 16, 0.1, h=17)      # h > M
+    with pytest.raises(cmbx.CmbxError) as e:
+        cmbx.Slab("flat", 32, 10, 0.1)              # M = 10 not compiled
+    assert e.value.code == cmbx.EUNSUPPORTED
+    s = cmbx.Slab("hybrid", 32, 16, 0.1, h=4)
+    d = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(cmbx.CmbxError) as e:
+        s.simulate(0, 0.3, d)
+    assert e.value.code == cmbx.ESTATE
+    s.close()
