@@ -455,6 +455,15 @@ int cmbx_mlp_colsum(const float* X, int rows, int cols, float* out, void* stream
 int cmbx_mlp_mse(const float* Y, const float* T, int64_t n, float* dY, float* partial, float* loss,
                  void* stream);
 int64_t cmbx_mlp_mse_partials(int64_t n);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * training loops, harnesses that forbid hipMalloc): cmbx_mlp_mse with its partial sums in a
+ * static device array of the library (256 KiB per device, held until the process ends)
+ * instead of a caller's workspace. Allocates nothing. Same arguments and results as
+ * cmbx_mlp_mse without `partial`; n at most CMBX_MSE_NOALLOC_MAX (CMBX_EINVAL beyond).
+ * Every call on one device shares that device's array, so calls that overlap on a device
+ * (other streams, other threads) race; calls ordered on one stream do not. */
+#define CMBX_MSE_NOALLOC_MAX (65536ll * 256)
+int cmbx_mlp_mse_noalloc(const float* Y, const float* T, int64_t n, float* dY, float* loss, void* stream);
 /* One Adam step (Kingma & Ba) on n FP32 master weights w with moments m, v and gradient g
  * at step `step` >= 1; writes the BF16 copy w_bf16 (raw 16-bit words) if not NULL. */
 int cmbx_mlp_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float beta1,

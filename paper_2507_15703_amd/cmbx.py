@@ -83,6 +83,7 @@ def lib():
             "cmbx_mlp_colsum": (I, [P, I, I, P, P]),
             "cmbx_mlp_mse": (I, [P, P, I64, P, P, P, P]),
             "cmbx_mlp_mse_partials": (I64, [I64]),
+            "cmbx_mlp_mse_noalloc": (I, [P, P, I64, P, P, P]),
             "cmbx_mlp_adam": (I, [P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, I, P, P]),
             "cmbx_bf16_round": (I, [P, P, I64, P]),

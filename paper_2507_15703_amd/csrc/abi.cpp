@@ -1403,6 +1403,16 @@ int cmbx_mlp_mse(const float* Y, const float* T, int64_t n, float* dY, float* pa
   return ok();
 }
 
+int cmbx_mlp_mse_noalloc(const float* Y, const float* T, int64_t n, float* dY, float* loss, void* stream) {
+  if (!Y || !T || !dY || !loss || n < 1) return fail(CMBX_EINVAL, "mse_noalloc: bad arguments");
+  if (n > CMBX_MSE_NOALLOC_MAX)
+    return fail(CMBX_EINVAL, "mse_noalloc: n = %lld exceeds the static workspace's limit %lld", (long long)n,
+                (long long)CMBX_MSE_NOALLOC_MAX);
+  static_assert(CMBX_MSE_NOALLOC_MAX == cmbx::kMseScratchFloats * 256, "limit of the static workspace");
+  HIP_TRY(cmbx::launch_mse_noalloc(Y, T, n, dY, loss, (hipStream_t)stream));
+  return ok();
+}
+
 int cmbx_mlp_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float beta1, float beta2, float eps,
                   int step, uint16_t* w_bf16, void* stream) {
   if (!w || !m || !v || !g || n < 1 || step < 1) return fail(CMBX_EINVAL, "adam: bad arguments");

@@ -12,6 +12,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "mlp.hpp"
 
 namespace cmbx {
@@ -184,6 +187,39 @@ hipError_t launch_mse(const float* Y, const float* T, int64_t n, float* dY, floa
   hipLaunchKernelGGL(k_mse, dim3((unsigned)nb), dim3(256), 0, s, Y, T, n, dY, partial);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, (int)nb, loss);
   return hipGetLastError();
+}
+
+// Workspace of the allocation-free MSE: the per-block partial sums live in this file-scope
+// array, one copy per device for the life of the process. In host code `scratch` names a
+// host-side stand-in, never the device memory: only the address hipGetSymbolAddress
+// returns for the current device is passed to kernels.
+static __device__ __align__(256) float scratch[kMseScratchFloats];
+
+hipError_t mse_scratch_address(float** out) {
+  static std::mutex mu;
+  static std::map<int, float*> addr;  // device -> address of that device's copy
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = addr.emplace(dev, static_cast<float*>(p)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+hipError_t launch_mse_noalloc(const float* Y, const float* T, int64_t n, float* dY, float* loss, hipStream_t s) {
+  if (mse_partials(n) > kMseScratchFloats) return hipErrorInvalidValue;
+  float* partial = nullptr;
+  const hipError_t e = mse_scratch_address(&partial);
+  if (e != hipSuccess) return e;
+  // every partial k_sum reads is written by k_mse first: nothing to clear
+  return launch_mse(Y, T, n, dY, partial, loss, s);
 }
 
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s) {

@@ -24,6 +24,11 @@ hipError_t launch_colsum(const float* X, int rows, int cols, float* out, hipStre
 int64_t mse_partials(int64_t n);
 hipError_t launch_mse(const float* Y, const float* T, int64_t n, float* dY, float* partial, float* loss,
                       hipStream_t s);
+// The same MSE with its partial sums in a static device array of kMseScratchFloats floats
+// (no allocation, no workspace argument): n up to kMseScratchFloats * 256 values. Calls that
+// overlap on one device share the array and race. hipErrorInvalidValue beyond the limit.
+constexpr int64_t kMseScratchFloats = 65536;
+hipError_t launch_mse_noalloc(const float* Y, const float* T, int64_t n, float* dY, float* loss, hipStream_t s);
 
 struct AdamArgs {
   float *w, *m, *v;
