@@ -6,7 +6,11 @@ Sec. II A-B of the paper:
 * xi_inf(r) = 4 pi int_0^inf k^2 P_inf(k) j0(k r) dk                       (eq. xiinfpinf)
 * the programme min c.x s.t. A x >= b, x >= 0 with c_j = sum_i A_ij       (eq. sumconstraint)
   on constraints r_i = i dr (dr = R b / 5, up to r_max = 2 R sin(theta_max)) and unknowns
-  x_j = P_inf(k_j), k_j = j dk (dk = 2 pi / (3 r_max)), A_ij = 4 pi k_j^2 j0(k_j r_i) dk.
+  x_j = P_inf(k_j), k_j = j dk (dk = 2 pi / (3 r_max)). The box reads the table as linear
+  between nodes and zero beyond the last, P_inf = sum_j x_j phi_j with phi_j the hat of
+  node j, so A_ij = 4 pi int k^2 j0(k r_i) phi_j(k) dk: the rising half of the hat on
+  [k_{j-1}, k_j] and the falling half on [k_j, k_{j+1}] (none after the last node), each
+  integrated by a 16-point Gauss-Legendre rule (SciPy's nodes and weights).
 * C_l of the box field sampled on a full shell of radius R:
   C_l^box = 4 pi sum_{f != 0} P_box(|k_f|) j_l(|k_f| R)^2 (expand e^{i k.R n} in spherical
   harmonics and average |a_lm|^2 over m).
@@ -55,11 +59,29 @@ def programme(cl, R, theta_max, beam, k_max):
     dk = 2.0 * math.pi / (3.0 * r_max)
     n_k = int(math.floor(k_max / dk + 1e-9)) + 1
     k = np.array([j * dk for j in range(n_k)])
-    A = np.empty((n_r, n_k))
-    for j in range(n_k):
-        A[:, j] = 4.0 * math.pi * k[j] ** 2 * scipy.special.spherical_jn(0, k[j] * r) * dk
+    A = hat_integrals(r, k)
     c = A.sum(axis=0)
     return r, b, k, A, c
+
+
+def hat_integrals(r, k):
+    """A[i, j] = 4 pi int k^2 j0(k r_i) phi_j(k) dk over the two halves of each hat."""
+    r = np.atleast_1d(np.asarray(r, dtype=np.float64))
+    x, w = scipy.special.roots_legendre(16)
+    A = np.zeros((r.size, k.size))
+
+    def half(a, c, rising):
+        t = 0.5 * (c - a) * x + 0.5 * (c + a)
+        phi = (t - a) / (c - a) if rising else (c - t) / (c - a)
+        f = 4.0 * math.pi * t**2 * phi * (0.5 * (c - a) * w)
+        return scipy.special.spherical_jn(0, np.outer(r, t)) @ f
+
+    for j in range(k.size):
+        if j > 0:
+            A[:, j] += half(k[j - 1], k[j], True)
+        if j + 1 < k.size:
+            A[:, j] += half(k[j], k[j + 1], False)
+    return A
 
 
 def solve(A, b, c):
@@ -106,12 +128,10 @@ def cl_box(N, L, R, k_tab, p_tab, lmax):
 
 
 def xi_inf_of(k, p, r):
-    """xi_inf(r) of a tabulated P_inf through the programme's quadrature (eq. xiinfpinf):
-    4 pi sum_j k_j^2 P_j j0(k_j r) dk for a uniform node spacing dk."""
+    """xi_inf(r) of a tabulated P_inf, read as linear between its nodes (eq. xiinfpinf
+    through the programme's hat integrals)."""
     k = np.asarray(k, dtype=np.float64)
-    dk = k[1] - k[0]
-    r = np.asarray(r, dtype=np.float64)
-    return 4 * math.pi * (scipy.special.spherical_jn(0, np.outer(r, k)) * (k**2 * p)).sum(axis=1) * dk
+    return hat_integrals(r, k) @ np.asarray(p, dtype=np.float64)
 
 
 def cap_pair_weight(theta, theta_cap):

@@ -5,9 +5,17 @@ xi_sph(theta) = sum_l (2l+1) C_l P_l(cos theta) / (4 pi) (eq. harmonics); two po
 sphere of radius R at angle theta are a chord r = 2 R sin(theta/2) apart (eq. rtheta); an
 isotropic 3-D spectrum gives xi_inf(r) = 4 pi int k^2 P_inf(k) j0(k r) dk (eq. xiinfpinf).
 Matching xi_inf to xi_sph at chords up to r_max, with P_inf >= 0, is a linear programme:
-minimise c.x subject to A x >= b, x >= 0, where x_j = P_inf(k_j), b_i = xi_sph(theta_i),
-A_ij = 4 pi k_j^2 j0(k_j r_i) dk and c_j = sum_i A_ij, so that c.x = sum_i (A x)_i is
-smallest when every constraint holds with equality (eq. sumconstraint).
+minimise c.x subject to A x >= b, x >= 0, where x_j = P_inf(k_j), b_i = xi_sph(theta_i)
+and c_j = sum_i A_ij, so that c.x = sum_i (A x)_i is smallest when every constraint holds
+with equality (eq. sumconstraint).
+
+The box reads the table as piecewise linear in k (zero beyond its last node), so A is the
+integral of eq. xiinfpinf for that reading: P_inf = sum_j x_j phi_j with phi_j the hat
+function of node j (1 at k_j, linear to 0 at its neighbours; the last node's hat ends at
+k_j), A_ij = 4 pi int k^2 j0(k r_i) phi_j(k) dk, by Gauss-Legendre on each interval
+between nodes. Then A x is exactly the correlation of the spectrum the box samples; the
+plain node sum 4 pi k_j^2 j0(k_j r_i) dk is not (for the programme's sparse solutions it
+put the box's xi(0) 4 % high and its correlations at half the cap's width 30 % low).
 
 Discretisation (Sec. II B): constraints at r_i = i dr, dr = R b / 5, up to
 r_max = 2 R sin(theta_max) (the widest chord of a cap of polar angle theta_max; theta_max
@@ -46,6 +54,40 @@ def _j0(x):
     return np.where(x == 0.0, 1.0, np.sin(safe) / safe)
 
 
+_GL_X, _GL_W = np.polynomial.legendre.leggauss(12)
+
+
+def hat_kernel(r, k, chunk=256):
+    """A[i, j] = 4 pi int k^2 j0(k r_i) phi_j(k) dk for the hat functions phi_j of the
+    uniform nodes k (last node's hat ending at it), so that xi_inf(r_i) = sum_j A_ij P_j for
+    the piecewise-linear P_inf through the nodes (eq. xiinfpinf). Twelve Gauss-Legendre
+    points on each interval between nodes: over one interval k r changes by at most
+    dk r_max = 2 pi / 3, where that rule is exact to rounding."""
+    r = np.atleast_1d(np.asarray(r, dtype=np.float64))
+    k = np.asarray(k, dtype=np.float64)
+    lo, hi = k[:-1], k[1:]
+    h = hi - lo
+    t = 0.5 * (lo + hi)[:, None] + 0.5 * h[:, None] * _GL_X[None, :]  # (intervals, 12)
+    f = 4.0 * math.pi * t * t * (0.5 * h[:, None] * _GL_W[None, :])
+    rise = (t - lo[:, None]) / h[:, None]  # hat of the interval's right node; 1 - rise: left node
+    A = np.zeros((r.size, k.size))
+    for i0 in range(0, r.size, chunk):
+        J = _j0(r[i0:i0 + chunk, None, None] * t[None, :, :])
+        A[i0:i0 + chunk, 1:] += np.einsum("rim,im->ri", J, f * rise)
+        A[i0:i0 + chunk, :-1] += np.einsum("rim,im->ri", J, f * (1.0 - rise))
+    return A
+
+
+def hat_masses(k):
+    """4 pi int k^2 phi_j(k) dk: the share of xi(0) that P_inf = 1 at node j alone carries."""
+    return hat_kernel(np.zeros(1), k)[0]
+
+
+def xi_of_table(r, k, p):
+    """xi_inf at separations r of the piecewise-linear P_inf through the table (k, p)."""
+    return hat_kernel(r, k) @ np.asarray(p, dtype=np.float64)
+
+
 def lp_problem(cl, R, theta_max, beam, k_max):
     """The discretised programme: dict(r, theta, b, k, A, c)."""
     th = min(float(theta_max), 0.5 * math.pi)
@@ -58,7 +100,7 @@ def lp_problem(cl, R, theta_max, beam, k_max):
     dk = 2.0 * math.pi / (3.0 * r_max)
     n_k = int(math.floor(k_max / dk + 1e-9)) + 1
     k = dk * np.arange(n_k)
-    A = 4.0 * math.pi * (k[None, :] ** 2) * _j0(k[None, :] * r[:, None]) * dk
+    A = hat_kernel(r, k)
     c = A.sum(axis=0)
     return dict(r=r, theta=theta, b=b, k=k, A=A, c=c, dr=dr, dk=dk, r_max=r_max)
 
@@ -75,12 +117,12 @@ def invert(cl, R, theta_max, beam, N=None, L=1.0, k_max=None):
     pr = lp_problem(cl, R, theta_max, beam, k_max)
     A, b = pr["A"], pr["b"]
     # The same programme in well-scaled units (HiGHS tolerances are absolute): constraints
-    # divided by xi_sph(0) and unknowns by their column norms 4 pi k^2 dk, so that the
+    # divided by xi_sph(0) and unknowns by their hat masses (row r = 0 of A), so that the
     # scaled unknown y_j is the fraction of xi(0) carried by node j.
     xi0 = float(b[0])
     if not xi0 > 0.0:
         raise ValueError("xi_sph(0) must be positive")
-    col = 4.0 * math.pi * pr["k"] ** 2 * pr["dk"]
+    col = A[0].copy()
     col[0] = 1.0
     As = A / col[None, :]
     bs = b / xi0
@@ -191,14 +233,10 @@ class CapPseudoCl:
         return self.of_xi(xi)
 
     def of_table(self, k, p, R):
-        """For a tabulated P_inf on uniform nodes k (eq. xiinfpinf as the programme's sum),
-        xi at the chord 2 R sin(theta / 2) of each node."""
-        k = np.asarray(k, dtype=np.float64)
-        p = np.asarray(p, dtype=np.float64)
-        dk = k[1] - k[0]
+        """For a tabulated P_inf on uniform nodes k (piecewise linear, eq. xiinfpinf), xi at
+        the chord 2 R sin(theta / 2) of each node."""
         r = 2.0 * R * np.sin(0.5 * self.theta)
-        xi = _j0(np.outer(r, k)) @ (4.0 * math.pi * k * k * p * dk)
-        return self.of_xi(xi)
+        return self.of_xi(xi_of_table(r, k, p))
 
 
 def band_deviation(a, b, lmin=2, width=10):

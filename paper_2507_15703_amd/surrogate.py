@@ -11,20 +11,24 @@ independent of R, so the network predicts the programme's own unknowns on that f
 
 * input (130): log10 of D_l = l(l+1) C_l / 2 pi at 128 log-spaced multipoles in [2, l_max]
   (linear in log l between integer l), shifted by +10; then N / 256 and 2 r / L.
-* output (256): y_j = 100 x P_inf(k_j) 4 pi k_j^2 dk / xi_sph(0) for j = 1..256, the
-  percentage of xi(0) carried by node j (the programme is homogeneous in C_l, so y does
-  not depend on the amplitude); nodes above the box's band limit are zero.
+* output (256): y_j = 100 x P_inf(k_j) m_j / xi_sph(0) for j = 1..256, m_j the hat mass of
+  node j (``spectrum.hat_masses``): the percentage of xi(0) carried by node j (the
+  programme is homogeneous in C_l, so y does not depend on the amplitude); nodes above the
+  box's band limit are zero.
 
 The network's answer then gets the smallest multiplicative correction (``project_bands``)
 that makes the expected pseudo-C_l on the cap (``spectrum.CapPseudoCl``) match the target
 C_l's in every band of Delta l = 10 from l = 2 to l_max: a linear problem with one row per
-band, solved in a few milliseconds on the host. The answer is accepted only if both checks
-pass: those bands within tol (1 %) of the target's, and the correlations the programme
-constrains (chords up to 2 R sin THETA_MAX) within res_tol (0.2 % of xi(0)). The band
-projection alone cannot supply the second: started from a spectrum-independent guess it
-leaves several times larger correlation errors, which is what the network removes.
-Otherwise, and for geometries outside the training domain, the plain inversion runs
-(fallback).
+band, solved in a few milliseconds on the host. The answer is accepted only if every check
+passes: those bands within tol (1 %) of the target's, and at the correlations the
+programme constrains (chords up to 2 R sin THETA_MAX) no deficit beyond res_tol (0.2 % of
+xi(0)) and no excess beyond exc_tol (2 % of xi(0)). The programme itself meets its
+constraints as inequalities, A x >= b: with the table read as linear between nodes it
+cannot meet them with equality at the cap's widest chords, and leaves up to about 1.4 %
+of xi(0) there on this family, hence the one-sided bars. The band projection alone cannot
+supply the correlation checks: started from a spectrum-independent guess it leaves
+several times larger correlation errors, which is what the network removes. Otherwise,
+and for geometries outside the training domain, the plain inversion runs (fallback).
 """
 import ctypes
 import functools
@@ -67,10 +71,10 @@ def features(cl, N, r_over_L):
 def label_from_solution(k, p, cl, R):
     """The network target from a programme solution (k, P_inf)."""
     xi0 = spectrum.xi_sph(np.array([0.0]), cl)[0]
-    dk = k[1] - k[0]
+    m = spectrum.hat_masses(k)
     y = np.zeros(N_OUT)
     n = min(N_OUT, k.size - 1)
-    y[:n] = 100.0 * p[1:n + 1] * 4 * math.pi * k[1:n + 1] ** 2 * dk / xi0
+    y[:n] = 100.0 * p[1:n + 1] * m[1:n + 1] / xi0
     return y.astype(np.float32)
 
 
@@ -89,7 +93,7 @@ def table_from_output(y, cl, N, r_over_L):
     xi0 = _xi0(cl)
     k = dk * np.arange(n + 1)
     p = np.zeros(n + 1)
-    p[1:] = np.maximum(np.asarray(y[:n], dtype=np.float64), 0.0) / 100.0 * xi0 / (4 * math.pi * k[1:] ** 2 * dk)
+    p[1:] = np.maximum(np.asarray(y[:n], dtype=np.float64), 0.0) / 100.0 * xi0 / spectrum.hat_masses(k)[1:]
     return k, p
 
 
@@ -113,11 +117,13 @@ class _Geometry:
         R = r_over_L * L_BOX
         dk = math.pi / (3.0 * math.sin(THETA_MAX)) / R
         self.n = min(N_OUT, int(math.floor(math.pi * N / L_BOX / dk + 1e-9)))
-        k = dk * np.arange(1, self.n + 1)
+        k = dk * np.arange(self.n + 1)
+        m = spectrum.hat_masses(k)[1:]
         self.chk = _cap_check(lmax)
         # expected pseudo-C_l per unit output, over xi(0): y_j carries y_j / 100 of xi(0)
-        # at node k_j, i.e. xi(chord) = xi(0) sum_j y_j j0(k_j chord) / 100
-        J = spectrum._j0(np.outer(2.0 * R * np.sin(0.5 * self.chk.theta), k))
+        # in the hat of node k_j, i.e. xi(chord) = xi(0) sum_j y_j K_j(chord) / 100 with
+        # K_j = (hat integral of j0 at that chord) / m_j
+        J = spectrum.hat_kernel(2.0 * R * np.sin(0.5 * self.chk.theta), k)[:, 1:] / m
         starts = np.arange(2, lmax - 10 + 2, 10)
         B = np.zeros((starts.size, lmax + 1))
         for i, l0 in enumerate(starts):
@@ -126,7 +132,7 @@ class _Geometry:
         self.G = B @ (self.chk.K @ J) / 100.0
         # the programme's constraints (beam 1 / (0.6 l_max)) in the same units
         pr = spectrum.lp_problem(np.zeros(2), R, THETA_MAX, 1.0 / (0.6 * lmax), math.pi * N / L_BOX)
-        self.C = spectrum._j0(np.outer(pr["r"], k)) / 100.0
+        self.C = spectrum.hat_kernel(pr["r"], k)[:, 1:] / m / 100.0
         # (2l + 1) P_l(cos theta_i) / 4 pi at the constraint angles, for xi_sph there
         x = np.cos(pr["theta"])
         P = np.empty((lmax + 1, x.size))
@@ -159,8 +165,10 @@ class _Geometry:
         return y
 
     def checks(self, y, t, xi_r):
-        """(largest band deviation, largest in-cap correlation error over xi(0))."""
-        return float(np.max(np.abs(self.G @ y / t - 1.0))), float(np.max(np.abs(self.C @ y - xi_r)))
+        """(largest band deviation, largest in-cap correlation deficit, largest excess), the
+        last two over xi(0)."""
+        d = self.C @ y - xi_r
+        return (float(np.max(np.abs(self.G @ y / t - 1.0))), float(max(0.0, -d.min())), float(max(0.0, d.max())))
 
 
 @functools.lru_cache(maxsize=32)
@@ -169,7 +177,7 @@ def _geometry(N, r_over_L, lmax):
 
 
 def project_bands(y, cl, N, r_over_L):
-    """The network output y (256) after the band projection, and its two check values."""
+    """The network output y (256) after the band projection, and its check values."""
     cl = np.asarray(cl, dtype=np.float64)
     g = _geometry(int(N), float(r_over_L), cl.size - 1)
     t, xi_r = g.targets(cl)
@@ -180,11 +188,13 @@ def project_bands(y, cl, N, r_over_L):
 
 
 def cap_residual(k, p, cl, N, r_over_L):
-    """max_i |(A x)_i - b_i| / xi_sph(0) on the programme's constraints for this spectrum."""
+    """(largest deficit, largest excess) of (A x)_i against b_i, over xi_sph(0), on the
+    programme's constraints for this spectrum."""
     lmax = np.asarray(cl).size - 1
     pr = spectrum.lp_problem(cl, r_over_L * L_BOX, THETA_MAX, 1.0 / (0.6 * lmax), math.pi * N / L_BOX)
     x = np.interp(pr["k"], k, p, right=0.0)
-    return float(np.max(np.abs(pr["A"] @ x - pr["b"])) / pr["b"][0])
+    d = (pr["A"] @ x - pr["b"]) / pr["b"][0]
+    return float(max(0.0, -d.min())), float(max(0.0, d.max()))
 
 
 # ---------------------------------------------------------------------------- data
@@ -203,8 +213,10 @@ def cl_of(prm):
 
 
 def plain_inversion(prm, cl=None):
+    """The programme for these parameters, with the beam every part of the surrogate uses
+    (1 / (0.6 l_max): the constraint spacing of the checks and of the fallback)."""
     cl = cl_of(prm) if cl is None else cl
-    return spectrum.invert(cl, prm["r"] * L_BOX, THETA_MAX, 1.0 / prm["ld"], N=prm["N"], L=L_BOX)
+    return spectrum.invert(cl, prm["r"] * L_BOX, THETA_MAX, 1.0 / (0.6 * (cl.size - 1)), N=prm["N"], L=L_BOX)
 
 
 def _pair(seed):
@@ -425,14 +437,17 @@ DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data
 class Surrogate:
     """C_l -> (k, P_inf) through the network, with the plain inversion as fallback."""
 
-    def __init__(self, mlp, tol=0.01, res_tol=0.002, project=True):
-        self.mlp, self.tol, self.res_tol, self.project = mlp, tol, res_tol, project
+    def __init__(self, mlp, tol=0.01, res_tol=0.002, exc_tol=0.02, project=True, y_prior=None):
+        self.mlp, self.tol, self.res_tol, self.exc_tol, self.project = mlp, tol, res_tol, exc_tol, project
+        # the mean training target, if the checkpoint carries it: the network-free answer
+        self.y_prior = None if y_prior is None else np.asarray(y_prior, dtype=np.float64)
         self.stats = dict(accepted=0, fallback=0)
 
     @classmethod
     def load(cls, path=DEFAULT_WEIGHTS, **kw):
         """The surrogate with a checkpoint's weights. A checkpoint that is missing, corrupt
         (CRC) or of the wrong shapes gives a surrogate that always falls back, with a warning."""
+        st = {}
         try:
             st = read_checkpoint(path)
             mlp = MLP()
@@ -440,13 +455,13 @@ class Surrogate:
         except ValueError as e:
             warnings.warn(f"{e}; every spectrum will use the plain inversion")
             mlp = None
-        return cls(mlp, **kw)
+        return cls(mlp, y_prior=st.get("y_prior") if mlp is not None else None, **kw)
 
     def in_domain(self, N, r_over_L):
         return self.mlp is not None and N in (128, 256) and 0.35 <= r_over_L <= 0.45
 
     def spectrum(self, cl, N, r_over_L, beam=None):
-        """Returns (k, P_inf, used_fallback, (band deviation, correlation error))."""
+        """Returns (k, P_inf, used_fallback, (band deviation, correlation deficit, excess))."""
         return self.spectra([(cl, N, r_over_L)], beam)[0]
 
     def answer(self, y, cl, N, r_over_L):
@@ -470,7 +485,7 @@ class Surrogate:
             Y = self.mlp.predict(np.stack([features(*items[i]) for i in live]))
             for i, y in zip(live, Y):
                 k, p, chk = self.answer(y, *items[i])
-                if chk[0] <= self.tol and chk[1] <= self.res_tol:
+                if chk[0] <= self.tol and chk[1] <= self.res_tol and chk[2] <= self.exc_tol:
                     self.stats["accepted"] += 1
                     out[i] = (k, p, False, chk)
         for i, (cl, N, r) in enumerate(items):
@@ -479,5 +494,5 @@ class Surrogate:
                 lmax = np.asarray(cl).size - 1
                 b = beam if beam is not None else 1.0 / (0.6 * lmax)
                 k, p, _ = spectrum.invert(cl, r * L_BOX, THETA_MAX, b, N=N, L=L_BOX)
-                out[i] = (k, p, True, (cl_check(k, p, cl, r), cap_residual(k, p, cl, N, r)))
+                out[i] = (k, p, True, (cl_check(k, p, cl, r),) + cap_residual(k, p, cl, N, r))
         return out

@@ -1,6 +1,6 @@
 """The paper's decisive validation (Sec. III B) on this build's maps: the added-noise sweep.
 
-    python tests/covariance_study.py --nside 32 --cap 20 --beam-deg 1.72 --maps 1000
+    python tests/covariance_study.py --nside 32 --cap 20 --beam-deg 1.72 --maps 1000 [--m-factor 4]
 
 On the unit sphere: C_l of the synthetic family smoothed by a Gaussian beam b (eq. cl,
 l(l+1) C_l / 2 pi = 1e-10 (1 + 0.3 cos(pi l / 220)) exp(-(b l)^2), l <= 5 / b), the
@@ -12,6 +12,12 @@ For every noise level (fractions of the map rms) the maps plus white noise are w
 the Cholesky factor of Gamma + s^2 I on the device and KS-tested on the host
 (``paper_2507_15703_amd.covtest``). Control: maps drawn exactly from Gamma (on the host,
 Cholesky of Gamma plus 1e-12 of its diagonal) must pass at the smallest level.
+
+The box is periodic along z with period M dp. The rule's M (twice the cap's depth) puts
+the first periodic images of a pixel within the cap's widest chord, so correlations that
+reach that far add to the variance: --m-factor multiplies M (the rule's N is kept). The
+expected variance of the box's field, sum P_box over the lattice (oracle ``p_box_flat``),
+is printed against xi(0) for each M as the prediction the maps' rms is checked against.
 
 Prints one line per level and method, then one JSON line.
 """
@@ -31,7 +37,19 @@ if ROOT not in sys.path:
 LEVELS = [0.0, 1e-4, 3e-4, 1e-3, 2e-3, 5e-3, 1e-2, 2e-2, 5e-2, 0.1]
 
 
-def run(nside=32, cap_deg=20.0, beam_deg=1.72, n_maps=1000, size_factor=1.0, seed=0, levels=LEVELS, log=True):
+def lattice_variance(N, M, dp, k, p):
+    """sum of P_box over the N x N x M lattice (eq. finalpbox): the field's variance."""
+    from oracle import slab as oslab
+    P = oslab.p_box_flat(N, M, dp, k, p)                 # [s][fz], fz = 0 .. M/2
+    f = np.arange(-N // 2, N // 2)
+    cnt = np.bincount((f[:, None] ** 2 + f[None, :] ** 2).ravel(), minlength=P.shape[0])
+    wz = np.full(M // 2 + 1, 2.0)
+    wz[0] = wz[-1] = 1.0
+    return float(np.sum(cnt[:, None] * P[: cnt.size] * wz[None, :]))
+
+
+def run(nside=32, cap_deg=20.0, beam_deg=1.72, n_maps=1000, size_factor=1.0, seed=0, levels=LEVELS, log=True,
+        m_factor=1):
     import torch
 
     from paper_2507_15703_amd import cmbx, covtest, spectrum, workloads
@@ -48,14 +66,19 @@ def run(nside=32, cap_deg=20.0, beam_deg=1.72, n_maps=1000, size_factor=1.0, see
     lmax = int(math.ceil(5.0 / b))
     cl = workloads.synthetic_cl(lmax, ld=1.0 / b)
     N, M, dp = cmbx.box_size(b, theta, size_factor)
+    M *= int(m_factor)
     # layers: the cap's height plus the tricubic stencil's two nodes each side
     h = min(M, int(math.ceil((1.0 - z_min) / dp)) + 5)
     k, p, info = spectrum.invert(cl, 1.0, theta, b, k_max=math.pi / dp)
-    say(f"box N={N} M={M} h={h} dp={dp:.5g}; programme {info['n_r']}x{info['n_k']}")
+    xi0_sph = float(spectrum.xi_sph(np.zeros(1), cl)[0])
+    var_box = lattice_variance(N, M, dp, k, p)
+    say(f"box N={N} M={M} h={h} dp={dp:.5g}; programme {info['n_r']}x{info['n_k']}, largest excess "
+        f"{info['max_rel_excess']:.4f} of xi(0); lattice variance / xi(0) = {var_box / xi0_sph:.4f}")
     dirs = cmbx.healpix_cap(nside, z_min)
     n_pix = dirs.shape[0]
     res = {"nside": nside, "cap_deg": cap_deg, "beam_deg": beam_deg, "n_pix": n_pix, "n_maps": n_maps,
-           "N": N, "M": M, "h": h, "dp": dp, "lmax": lmax, "levels": list(levels)}
+           "N": N, "M": M, "m_factor": int(m_factor), "h": h, "dp": dp, "lmax": lmax, "levels": list(levels),
+           "lattice_var_over_xi0": var_box / xi0_sph, "programme_max_excess": info["max_rel_excess"]}
     batch = 50
     for method in ("hybrid", "flat"):
         slab = cmbx.Slab(method, N, M, dp, h=h, dtype="f32", batch=batch, interp="tricubic")
@@ -97,8 +120,9 @@ def main():
     ap.add_argument("--maps", type=int, default=1000)
     ap.add_argument("--size-factor", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--m-factor", type=int, default=1)
     a = ap.parse_args()
-    res = run(a.nside, a.cap, a.beam_deg, a.maps, a.size_factor, a.seed)
+    res = run(a.nside, a.cap, a.beam_deg, a.maps, a.size_factor, a.seed, m_factor=a.m_factor)
     print(json.dumps(res), flush=True)
 
 
