@@ -873,7 +873,7 @@ int launch_lanes(cmbx_ensemble* en, hipStream_t s) {
   return CMBX_OK;
 }
 
-// Average milliseconds of an ensemble's launch over eight launches after two warm-ups
+// Average milliseconds of an ensemble's launch over 16 launches after three warm-ups
 // (-1 on error).
 double time_ensemble(cmbx_ensemble* en) {
   hipStream_t s = nullptr;
@@ -882,13 +882,13 @@ double time_ensemble(cmbx_ensemble* en) {
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
       hipEventCreate(&e1) == hipSuccess) {
     int rc = CMBX_OK;
-    for (int i = 0; rc == CMBX_OK && i < 2; ++i) rc = launch_lanes(en, s);
+    for (int i = 0; rc == CMBX_OK && i < 3; ++i) rc = launch_lanes(en, s);
     hipError_t e = rc == CMBX_OK ? hipEventRecord(e0, s) : hipErrorUnknown;
-    for (int i = 0; e == hipSuccess && rc == CMBX_OK && i < 8; ++i) rc = launch_lanes(en, s);
+    for (int i = 0; e == hipSuccess && rc == CMBX_OK && i < 16; ++i) rc = launch_lanes(en, s);
     if (e == hipSuccess && rc == CMBX_OK) e = hipEventRecord(e1, s);
     if (e == hipSuccess && rc == CMBX_OK) e = hipEventSynchronize(e1);
     float t = 0.f;
-    if (e == hipSuccess && rc == CMBX_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / 8.0;
+    if (e == hipSuccess && rc == CMBX_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / 16.0;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -1099,9 +1099,9 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
         if (got == want && !(m == &all_chained && want == 1)) cands.push_back({*m, want});
       }
     }
-    // one sweep over the candidates, then the two fastest twice more, alternating, each
-    // keeping its best time: the candidates are a few percent apart, as much as the clock
-    // drifts over a sweep
+    // three sweeps over every candidate, each keeping its best time: the candidates are a
+    // few percent apart, as much as the clock drifts over a sweep (re-timing only the two
+    // fastest of the first sweep had kept a candidate that lost by 5 % in steady state)
     std::vector<double> tc(cands.size(), 1e300);
     auto time_cand = [&](size_t c) -> int {
       set_modes(cands[c].modes, cands[c].lanes);
@@ -1114,14 +1114,9 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
     };
     size_t best = 0;
     if (cands.size() > 1) {
-      for (size_t c = 0; c < cands.size(); ++c)
-        if (int rc = time_cand(c)) return bail(rc, cmbx::err_msg());
-      std::vector<size_t> order(cands.size());
-      for (size_t c = 0; c < order.size(); ++c) order[c] = c;
-      std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return tc[x] < tc[y]; });
-      for (int round = 0; round < 2; ++round)
-        for (size_t k = 0; k < 2; ++k)
-          if (int rc = time_cand(order[k])) return bail(rc, cmbx::err_msg());
+      for (int round = 0; round < 3; ++round)
+        for (size_t c = 0; c < cands.size(); ++c)
+          if (int rc = time_cand(round % 2 ? cands.size() - 1 - c : c)) return bail(rc, cmbx::err_msg());
       for (size_t c = 1; c < cands.size(); ++c)
         if (tc[c] < tc[best]) best = c;
     }

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <cmath>
 
 #include "fft_device.hpp"
 #include "kernels.hpp"
@@ -172,21 +173,32 @@ __device__ __forceinline__ void x_tile(cpx<T>* smem, int zt, int iy, cpx<T>* __r
   }
   // every other pair of columns (2p, 2p + 1) holds two generic modes drawn from one
   // Philox call
-  for (int s = tid; s < N * PAIRS; s += NT) {
-    const int pr = s % PAIRS;
-    const int ix = s / PAIRS;
-    const int zc = zc0 + 2 * pr;
-    if (zc == 0) continue;
-    const int m0 = freq2(ix, N) + fy2 + zc * zc;
+  auto pair = [&](int pr, int ix, int zc, int m0) {
     if (m0 > m_hi) {  // both modes beyond the spectrum's support: +0, no draw, no load
       tile[Lds::index(2 * pr, ix)] = {T(0), T(0)};
       tile[Lds::index(2 * pr + 1, ix)] = {T(0), T(0)};
-      continue;
+      return;
     }
     const int m1 = m0 + 2 * zc + 1;
     const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
     tile[Lds::index(2 * pr, ix)] = weighted<T>(wtab[m0], w.x, w.y, tab);
     tile[Lds::index(2 * pr + 1, ix)] = weighted<T>(wtab[m1], w.z, w.w, tab);
+  };
+  if constexpr (NT % PAIRS == 0) {
+    // a thread keeps its pair of columns over the rows it visits
+    const int pr = tid % PAIRS;
+    const int zc = zc0 + 2 * pr;
+    if (zc != 0) {
+      const int base = fy2 + zc * zc;
+      for (int ix = tid / PAIRS; ix < N; ix += NT / PAIRS) pair(pr, ix, zc, freq2(ix, N) + base);
+    }
+  } else {
+    for (int s = tid; s < N * PAIRS; s += NT) {
+      const int pr = s % PAIRS;
+      const int ix = s / PAIRS;
+      const int zc = zc0 + 2 * pr;
+      if (zc != 0) pair(pr, ix, zc, freq2(ix, N) + fy2 + zc * zc);
+    }
   }
   __syncthreads();
   Lds first{tile};
@@ -1055,8 +1067,13 @@ hipError_t noise_table_address(const float** out) {
   return e;
 }
 
+// The device copy of the tables: the reciprocals 1 / c_j times 2^-23 (exact), which
+// box_muller_f32 multiplies by the integer mi mod 2^16 instead of by m - c_j.
 hipError_t upload_noise_tables(const float* host) {
-  return hipMemcpyToSymbol(HIP_SYMBOL(g_bm_tab), host, sizeof(float) * bmf::kTabSize, 0, hipMemcpyHostToDevice);
+  float dev[bmf::kTabSize];
+  for (int i = 0; i < bmf::kTabSize; ++i) dev[i] = host[i];
+  for (int j = 0; j < 128; ++j) dev[bmf::kTabInv + j] = std::ldexp(host[bmf::kTabInv + j], -23);
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_bm_tab), dev, sizeof(float) * bmf::kTabSize, 0, hipMemcpyHostToDevice);
 }
 
 hipError_t launch_noise_debug(int dtype, int N, void* out, const void* wtab, uint32_t k0, uint32_t k1,

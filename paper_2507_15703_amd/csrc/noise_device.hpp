@@ -135,7 +135,8 @@ constexpr float kSixth = 0x1.555556p-3f;     // 1/6 rounded to binary32
 constexpr uint32_t kRsqrtMagic = 0x5F3759DFu;  // the binary32 fast-inverse-square-root seed (Lomont 2003)
 constexpr uint32_t kFoldJ = 54;              // entries with c_j = 1 + j/128 >= sqrt 2 hold ln(c_j / 2)
 // table layout (binary32): ln c_j (or ln(c_j / 2)) and 1 / c_j for j = 0..127, then
-// sin and cos of (k + 1/2) 2 pi / 256 for k = 0..255
+// sin and cos of (k + 1/2) 2 pi / 256 for k = 0..255. The device copy holds the
+// reciprocals times 2^-23 (exact), see box_muller_f32.
 constexpr int kTabLn = 0, kTabInv = 128, kTabSin = 256, kTabCos = 512, kTabSize = 768;
 }  // namespace bmf
 
@@ -154,13 +155,17 @@ __device__ __forceinline__ void box_muller_f32(uint32_t a, uint32_t b, float& g_
                                                const float* __restrict__ tab) {
 #pragma clang fp contract(off)
   using namespace bmf;
-  const uint64_t v = (uint64_t)a + 1ull;
-  const int e0 = 63 - __clzll((long long)v);
-  const uint32_t mi = e0 >= 23 ? (uint32_t)(v >> (e0 - 23)) : (uint32_t)(v << (23 - e0));
+  // a + 1 in 32 bits wraps to 0 only for a = 2^32 - 1, where a + 1 = 2^32: mi = 2^23, e0 = 32
+  const uint32_t v = a + 1u;
+  const bool wrap = v == 0u;
+  const int lz = __clz((int)v);
+  const uint32_t mi = wrap ? (1u << 23) : ((v << (lz & 31)) >> 8);  // leading 24 bits, truncated
+  const int e0 = wrap ? 32 : 31 - lz;
   const uint32_t j = (mi >> 16) & 127u;
-  const float m = (float)mi * 0x1p-23f;            // exact
-  const float c = (float)(j + 128u) * 0x1p-7f;     // exact
-  const float r = (m - c) * tab[kTabInv + j];
+  // m - c_j = (mi mod 2^16) 2^-23 exactly (c_j = 1 + j/128 is m's leading 8 bits), and the
+  // device table holds 2^-23 / c_j: the product is the binary32 number (m - c_j) (1 / c_j)
+  // rounded once, scaled exactly by a power of two on one side instead of the other
+  const float r = (float)(mi & 0xFFFFu) * tab[kTabInv + j];
   const float q = r * kThird - 0.5f;
   const float lp = r * (q * r + 1.0f);
   const float lnm = tab[kTabLn + j] + lp;
