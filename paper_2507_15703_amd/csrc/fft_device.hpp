@@ -164,6 +164,10 @@ constexpr int stage_radix(int L, int i, int P = 0) {
 constexpr int stage_stride(int L, int i, int P = 0) {
   return i == 0 ? 1 : stage_stride(L, i - 1, P) * stage_radix(L, i - 1, P);
 }
+constexpr int max_radix(int L, int P = 0, int i = 0) {
+  return i == stage_count(L, P) ? 1
+         : (stage_radix(L, i, P) > max_radix(L, P, i + 1) ? stage_radix(L, i, P) : max_radix(L, P, i + 1));
+}
 constexpr bool plan_ok(int L, int P = 0, int i = 0, int prod = 1) {
   return i == stage_count(L, P) ? prod == L : plan_ok(L, P, i + 1, prod * stage_radix(L, i, P));
 }
@@ -225,7 +229,15 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ tw, Src& sr
 // it the rows spread over the G = 256 B / row bytes row positions of a bank sweep. Reads,
 // which run over consecutive rows, keep their banks. sw is the identity for a radix-3
 // first stage.
-template <typename T, int L, int NSEQ, bool SEQFAST, int P = 0>
+// Workgroup barrier for LDS only: waits for the wave's own LDS accesses and then for the
+// other waves, but not for its global memory operations, so that loads streaming into
+// another LDS buffer (global_load_lds) stay in flight across it. (__syncthreads also
+// waits for those.) The memory clobber keeps the compiler from moving memory accesses
+// across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// LB: done() is lds_barrier instead of __syncthreads.
+template <typename T, int L, int NSEQ, bool SEQFAST, int P = 0, bool LB = false>
 struct LdsIO {
   static constexpr int R0 = stage_radix(L, 0, P);
   static constexpr bool POW2 = (R0 & (R0 - 1)) == 0;
@@ -238,14 +250,18 @@ struct LdsIO {
   cpx<T>* p;
   __device__ __forceinline__ cpx<T> operator()(int q, int n) const { return p[index(q, n)]; }
   __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const { p[index(q, n)] = v; }
-  __device__ __forceinline__ void done() const { __syncthreads(); }
+  __device__ __forceinline__ void done() const {
+    if constexpr (LB) lds_barrier();
+    else __syncthreads();
+  }
 };
 
 // Run all stages of a length-L transform with stage plan P: stage 0 reads from `first`,
 // the last stage writes to `last`, stages in between go through the LDS sequences `lds`
-// (laid out as LdsIO<T, L, NSEQ, SEQFAST, P>). `tid` is the thread's index in the
-// workgroup.
-template <typename T, int L, int NSEQ, int NT, bool SEQFAST, int TWMUL, int S, class First, class Last, int P = 0>
+// (laid out as LdsIO<T, L, NSEQ, SEQFAST, P>; LB: their barriers are lds_barrier). `tid`
+// is the thread's index in the workgroup.
+template <typename T, int L, int NSEQ, int NT, bool SEQFAST, int TWMUL, int S, class First, class Last, int P = 0,
+          bool LB = false>
 __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* lds, First& first, Last& last,
                                         int tid) {
   constexpr int NST = stage_count(L, P);
@@ -253,7 +269,7 @@ __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* l
   if constexpr (S < NST) {
     constexpr int R = stage_radix(L, S, P);
     constexpr int NS = stage_stride(L, S, P);
-    LdsIO<T, L, NSEQ, SEQFAST, P> mid{lds};
+    LdsIO<T, L, NSEQ, SEQFAST, P, LB> mid{lds};
     if constexpr (S == 0 && NST == 1) {
       fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, last, tid);
     } else if constexpr (S == 0) {
@@ -263,7 +279,7 @@ __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* l
     } else {
       fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, mid, tid);
     }
-    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1, First, Last, P>(tw, lds, first, last, tid);
+    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1, First, Last, P, LB>(tw, lds, first, last, tid);
   }
 }
 

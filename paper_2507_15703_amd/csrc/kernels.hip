@@ -446,6 +446,134 @@ __global__ __launch_bounds__((ZShape<T, N, LINES>::NT)) void k_pass_z(cpx<T>* __
   }
 }
 
+// ------------------------------------------------------------------ pass 3, streamed
+// The z pass over a map footprint's block list with the next block's loads in flight
+// while the current block is transformed: two LDS tiles, the next block copied from
+// global memory straight into the idle one (global_load_lds, 16 B per lane, no
+// registers), the transform's barriers LDS-only so that those copies are not waited for
+// until the next block starts. Same arithmetic and outputs as k_pass_z.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// First stage as HalfToComplex, on a tile copied whole: columns beyond the support hold
+// whatever an earlier block left there and read as zero (what k_pass_z stores for them).
+template <typename T, int M, int LINES, int P = 0>
+struct HalfToComplexMasked {
+  using Lds = LdsIO<T, M, LINES, false, P>;
+  const cpx<T>* x;
+  const cpx<T>* tw;
+  int m_hi;
+  __device__ __forceinline__ cpx<T> at(int q, int k) const {
+    return k * k > m_hi ? cpx<T>{T(0), T(0)} : x[Lds::index(q, k)];
+  }
+  __device__ __forceinline__ cpx<T> operator()(int q, int k) const {
+    const cpx<T> xk = at(q, k);
+    if (k == 0) return {xk.x + xk.y, xk.x - xk.y};
+    const cpx<T> xc = conj(at(q, M - k));
+    return (xk + xc) + mul_i(cmul(tw[k], xk - xc));
+  }
+  __device__ __forceinline__ void done() const { lds_barrier(); }
+};
+
+// Binary32 transforms without a radix-16 stage only: those keep four waves per SIMD in
+// registers (94 VGPRs at N = 512 with 4 x 8 x 8). Radix 16 or binary64 needed 160 and more
+// and, held to 128, spilled: the streamed pass then ran at half the speed of k_pass_z.
+template <typename T, int N, int LINES, int P>
+constexpr bool z_streamable() {
+  return sizeof(T) == 4 && max_radix(N / 2, P) <= 8 && LINES <= 64 &&
+         ((size_t)LINES * (N / 2) * sizeof(cpx<T>)) % 1024 == 0;
+}
+
+// One block (LINES lines of M complex, contiguous in global memory and, in the same order,
+// in the tile) into LDS: 1 KiB per wave instruction, 16 B per lane; a lane whose first
+// column lies beyond the support loads nothing.
+template <typename T, int M, int LINES, int NT>
+__device__ __forceinline__ void z_block_to_lds(cpx<T>* tile, const cpx<T>* g, int m_hi) {
+  constexpr int PER_LANE = 16 / (int)sizeof(cpx<T>);  // complex values per lane
+  constexpr int PER_CHUNK = 64 * PER_LANE;
+  constexpr int CHUNKS = LINES * M / PER_CHUNK;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < CHUNKS; c += NT / 64) {
+    const int e = c * PER_CHUNK + lane * PER_LANE;
+    const int col = e % M;
+    if (col * col <= m_hi)
+      __builtin_amdgcn_global_load_lds((const void*)(g + e), (lds_void_t*)(tile + c * PER_CHUNK), 16, 0, 0);
+  }
+}
+
+// State of a workgroup's walk over the list: list entry e, its block, the next block and
+// the flags of the current block's lines (lane q < LINES: line q).
+struct ZWalk {
+  int e, blk, blk1;
+  uint32_t flag;  // the footprint byte of line lane (lanes past the block's lines: its last line)
+};
+
+// The footprint byte of line q of block blk (q < LINES), for the keep mask of the block.
+template <int N, int LINES>
+__device__ __forceinline__ uint32_t z_line_flag(const uint8_t* __restrict__ fp, int blk, int q) {
+  constexpr int NB = footprint_blocks(N);
+  const int l = blk * LINES + (q < LINES ? q : LINES - 1);
+  return fp[N + (l / N) * NB + ((l % N) >> 3)];
+}
+
+// One block on `cur` (its copy issued by the previous step) while the next one streams
+// into `nxt`. Returns false when the walk is over.
+template <typename T, int N, int LINES, int P>
+__device__ __forceinline__ bool z_stream_step(cpx<T>* cur, cpx<T>* nxt, const cpx<T>* tw, cpx<T>* __restrict__ buf,
+                                              const uint8_t* __restrict__ fp, const uint32_t* hdr, bool listed,
+                                              int count, int m_hi, uint64_t zmask, ZWalk& w) {
+  constexpr int M = N / 2, NT = ZShape<T, N, LINES>::NT;
+  const int lane = threadIdx.x & 63;
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this block's copy, flags and list entry are in
+  lds_barrier();                       // ... in every wave, and no wave still reads nxt
+  const uint64_t keep = __ballot(lane < LINES && w.flag != 0);
+  const int en = w.e + (int)gridDim.x;
+  const bool more = en < count;
+  int blk2 = 0;
+  uint32_t fn = 0;
+  if (more) {
+    if (en + (int)gridDim.x < count) blk2 = listed ? (int)hdr[kFootprintHeader + en + gridDim.x] : en + (int)gridDim.x;
+    fn = z_line_flag<N, LINES>(fp, w.blk1, lane);  // read at the next step, after its wait
+    z_block_to_lds<T, M, LINES, NT>(nxt, buf + (size_t)w.blk1 * LINES * M, m_hi);
+  }
+  HalfToComplexMasked<T, M, LINES, P> first{cur, tw, m_hi};
+  KeptLinesIO<T, M, LINES> last{buf + (size_t)w.blk * LINES * M, keep, nullptr, zmask};
+  fft_run<T, M, LINES, NT, false, 2, 0, HalfToComplexMasked<T, M, LINES, P>, KeptLinesIO<T, M, LINES>, P, true>(
+      tw, cur, first, last, threadIdx.x);
+  w = {en, w.blk1, blk2, fn};
+  return more;
+}
+
+template <typename T, int N, int LINES, int P = 0>
+__global__ __launch_bounds__((ZShape<T, N, LINES>::NT), 4) void k_pass_z_stream(cpx<T>* __restrict__ buf,
+                                                                          const cpx<T>* __restrict__ twg, int m_hi,
+                                                                          const uint8_t* __restrict__ fp) {
+  constexpr int M = N / 2, NT = ZShape<T, N, LINES>::NT;
+  constexpr int NBLK = N * N / LINES;
+  static_assert(z_streamable<T, N, LINES, P>(), "block of whole 1 KiB chunks, line flags in one wave");
+  __shared__ __align__(16) cpx<T> tile0[LINES * M];
+  __shared__ __align__(16) cpx<T> tile1[LINES * M];
+  __shared__ cpx<T> tw[N];
+  const uint32_t* hdr = reinterpret_cast<const uint32_t*>(fp + footprint_list_offset(N));
+  const bool listed = hdr[0] == (uint32_t)LINES;  // else every block, each written line by line
+  const int count = listed ? (int)hdr[1] : NBLK;
+  ZWalk w;
+  w.e = blockIdx.x;
+  if (w.e >= count) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t zmask = __ballot(lane < footprint_zblocks(N) && fp[footprint_z_offset(N) + lane] != 0);
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
+  w.blk = listed ? (int)hdr[kFootprintHeader + w.e] : w.e;
+  const int e1 = w.e + (int)gridDim.x;
+  w.blk1 = e1 < count ? (listed ? (int)hdr[kFootprintHeader + e1] : e1) : 0;
+  w.flag = z_line_flag<N, LINES>(fp, w.blk, lane);
+  z_block_to_lds<T, M, LINES, NT>(tile0, buf + (size_t)w.blk * LINES * M, m_hi);
+  // two steps per turn, so that each names its tiles statically: the compiler then sees
+  // that the copies into one tile never alias the transform on the other
+  while (z_stream_step<T, N, LINES, P>(tile0, tile1, tw, buf, fp, hdr, listed, count, m_hi, zmask, w) &&
+         z_stream_step<T, N, LINES, P>(tile1, tile0, tw, buf, fp, hdr, listed, count, m_hi, zmask, w)) {
+  }
+}
+
 // ------------------------------------------------------------------ debug noise
 template <typename T>
 __global__ void k_noise_debug(cpx<T>* __restrict__ out, int N, const T* __restrict__ wtab, uint32_t k0,
@@ -826,6 +954,16 @@ hipError_t run_y(const FieldArgs& a, hipStream_t s) {
 template <typename T, int N, int LINES, int P = 0>
 hipError_t run_z(const FieldArgs& a, hipStream_t s) {
   constexpr int NBLK = N * N / LINES;
+  if constexpr (z_streamable<T, N, LINES, P>()) {
+    // with a footprint: the streamed walk, as many workgroups as the device holds at once
+    if (a.fp) {
+      static const int resident = resident_grid(k_pass_z_stream<T, N, LINES, P>, ZShape<T, N, LINES>::NT);
+      hipLaunchKernelGGL((k_pass_z_stream<T, N, LINES, P>), dim3(NBLK > resident ? resident : NBLK),
+                         dim3(ZShape<T, N, LINES>::NT), 0, s, (cpx<T>*)a.buf, (const cpx<T>*)a.tw, a.m_hi,
+                         (const uint8_t*)a.fp);
+      return hipGetLastError();
+    }
+  }
   // a walking grid of what the device holds at once: a fixed one ran a second, partial
   // round of workgroups for blocks of 16 and 32 lines
   static const int resident = resident_grid(k_pass_z<T, N, LINES, P>, ZShape<T, N, LINES>::NT);

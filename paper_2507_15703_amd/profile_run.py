@@ -27,6 +27,8 @@ def main():
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--tile-xy", type=int, default=0)
     ap.add_argument("--lines-z", type=int, default=0)
+    ap.add_argument("--plans", default=None, help="FFT stage plans of x, y, z as 'a,b,c' (with given tiles)")
+    ap.add_argument("--tile-y", type=int, default=None)
     ap.add_argument("--spectrum", default="lp", choices=["lp", "powerlaw"])
     args = ap.parse_args()
 
@@ -43,8 +45,9 @@ def main():
         k, p = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N / 4)
     plan.spectrum_table(k, p)
     dirs = torch.tensor(workloads.cap_directions(job["theta_deg"], job["n_ring"], job["n_phi"]), device="cuda")
-    if args.tile_xy or args.lines_z:
-        plan.set_tiles(args.tile_xy, args.lines_z)
+    if args.tile_xy or args.lines_z or args.plans:
+        plans = tuple(int(v) for v in args.plans.split(",")) if args.plans else None
+        plan.set_tiles(args.tile_xy, args.lines_z, tile_y=args.tile_y, plans=plans)
     else:
         plan.autotune(reps=10, r=job["r_over_L"], dirs=dirs)  # as bench.py tunes
     out = torch.empty((1, dirs.shape[0]), dtype=plan.torch_dtype, device="cuda")
@@ -57,6 +60,7 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"N": N, "dtype": args.dtype, "reps": args.reps, "pixels": int(dirs.shape[0]),
+                      "shapes": plan.shapes(),
                       "ms": {"pass_x": ms[0], "pass_y": ms[1], "pass_z": ms[2], "gather": ms[3]},
                       "copy_bytes": 2 * 512 * 2**20}), flush=True)
     plan.close()
