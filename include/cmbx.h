@@ -111,6 +111,12 @@ int cmbx_plan_destroy(cmbx_plan* plan);
  * at height r (1 + z_min) / 2 is the observer at (L/2, L/2, L/2 - r (1 + z_min) / 2); any
  * position is reduced modulo the periodic box. CMBX_EINVAL for a non-finite coordinate. */
 int cmbx_plan_observer(cmbx_plan* plan, double x, double y, double z);
+/* The observer that places the plan's box about a cap (Sec. II D 1, Fig. 2a): the cap about
+ * +z at radius r > 0 with edge z_min = cos(theta_max) in [-1, 1], the box centre on its
+ * axis at height r (1 + z_min) / 2, i.e. xyz = (L/2, L/2, L/2 - r (1 + z_min) / 2). Writes
+ * the three coordinates to xyz (host) and changes nothing (pass them to cmbx_plan_observer).
+ * CMBX_EINVAL for a bad r, z_min or NULL xyz. */
+int cmbx_plan_cap_observer(const cmbx_plan* plan, double r, double z_min, double* xyz);
 
 /* Set a plan option (CMBX_OPT_*). CMBX_EINVAL for an unknown key or a bad value. */
 int cmbx_plan_set(cmbx_plan* plan, int key, int64_t value);
@@ -354,6 +360,11 @@ int cmbx_slab_set(cmbx_slab* slab, int key, int64_t value);
 /* Observer position o in box coordinates (the length unit of dp and r); CMBX_EINVAL if not
  * finite. Sec. II D 2 centres the h layers on the cap: o_z = (h - 1) dp / 2 - r (1 + z_min) / 2. */
 int cmbx_slab_observer(cmbx_slab* slab, double x, double y, double z);
+/* The observer that centres the slab's nz layers on a cap (Sec. II D 2, Fig. 2b): the cap
+ * about +z at radius r > 0 with edge z_min in [-1, 1]; xyz = (N dp / 2, N dp / 2,
+ * (nz - 1) dp / 2 - r (1 + z_min) / 2), written to xyz (host); nothing changes. CMBX_EINVAL
+ * for a bad r, z_min or NULL xyz. */
+int cmbx_slab_cap_observer(const cmbx_slab* slab, double r, double z_min, double* xyz);
 /* Spectrum as for cmbx_spectrum_table: host FP64 k (increasing), P_inf (>= 0), n >= 2,
  * linear between nodes, zero outside. Builds the per-column tables (FP64, rounded once);
  * synchronises the slab's stream. */

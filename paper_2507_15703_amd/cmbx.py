@@ -55,6 +55,7 @@ def lib():
             "cmbx_plan_set": (I, [P, I, I64]),
             "cmbx_plan_get": (I, [P, I, ctypes.POINTER(I64)]),
             "cmbx_plan_observer": (I, [P, D, D, D]),
+            "cmbx_plan_cap_observer": (I, [P, D, D, ctypes.POINTER(D)]),
             "cmbx_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(I),
                                    ctypes.POINTER(P)]),
             "cmbx_spectrum_table": (I, [P, P, P, I64]),
@@ -91,6 +92,7 @@ def lib():
             "cmbx_slab_destroy": (I, [P]),
             "cmbx_slab_set": (I, [P, I, I64]),
             "cmbx_slab_observer": (I, [P, D, D, D]),
+            "cmbx_slab_cap_observer": (I, [P, D, D, ctypes.POINTER(D)]),
             "cmbx_slab_spectrum": (I, [P, P, P, I64]),
             "cmbx_slab_simulate": (I, [P, U64, D, P, I64, P]),
             "cmbx_slab_debug_layers": (I, [P, U64, P]),
@@ -306,9 +308,10 @@ class Plan:
 
     def observer_for_cap(self, r, z_min):
         """The position that centres the box on the cap about +z at radius r whose edge is
-        z_min (Sec. II D 1: box centre at r (1 + z_min) / 2 on the cap's axis)."""
-        h = 0.5 * self.L
-        return (h, h, h - r * (1.0 + z_min) / 2.0)
+        z_min (cmbx_plan_cap_observer)."""
+        xyz = (ctypes.c_double * 3)()
+        _check(lib().cmbx_plan_cap_observer(self.handle, float(r), float(z_min), xyz))
+        return tuple(xyz)
 
     def set_prune(self, prune):
         self.prune = bool(prune)
@@ -672,10 +675,11 @@ class Slab:
         self.observer = (x, y, z)
 
     def observer_for_cap(self, r, z_min):
-        """Sec. II D 2: the middle of the layers at the middle height of the cap about +z of
-        radius r and edge z_min, on the axis through the layers' centre."""
-        c = 0.5 * self.N * self.dp
-        return (c, c, 0.5 * (self.nz - 1) * self.dp - r * (1.0 + z_min) / 2.0)
+        """The middle of the layers at the middle height of the cap about +z of radius r and
+        edge z_min (cmbx_slab_cap_observer)."""
+        xyz = (ctypes.c_double * 3)()
+        _check(lib().cmbx_slab_cap_observer(self.handle, float(r), float(z_min), xyz))
+        return tuple(xyz)
 
     def spectrum(self, k, p_inf):
         k = np.ascontiguousarray(k, dtype=np.float64)

@@ -422,6 +422,18 @@ int cmbx_plan_observer(cmbx_plan* p, double x, double y, double z) {
   return ok();
 }
 
+int cmbx_plan_cap_observer(const cmbx_plan* p, double r, double z_min, double* xyz) {
+  if (int rc = check_plan(p)) return rc;
+  if (!xyz) return fail(CMBX_EINVAL, "xyz is NULL");
+  if (!(r > 0.0) || !std::isfinite(r)) return fail(CMBX_EINVAL, "r = %g must be positive and finite", r);
+  if (!(z_min >= -1.0 && z_min <= 1.0)) return fail(CMBX_EINVAL, "z_min = %g must lie in [-1, 1]", z_min);
+  const double h = 0.5 * p->L;
+  xyz[0] = h;
+  xyz[1] = h;
+  xyz[2] = h - r * (1.0 + z_min) / 2.0;
+  return ok();
+}
+
 int cmbx_plan_set(cmbx_plan* p, int key, int64_t value) {
   if (int rc = check_plan(p)) return rc;
   int opts[4];

@@ -315,6 +315,18 @@ int cmbx_slab_observer(cmbx_slab* p, double x, double y, double z) {
   return ok();
 }
 
+int cmbx_slab_cap_observer(const cmbx_slab* p, double r, double z_min, double* xyz) {
+  if (int rc = check(p)) return rc;
+  if (!xyz) return fail(CMBX_EINVAL, "xyz is NULL");
+  if (!(r > 0.0) || !std::isfinite(r)) return fail(CMBX_EINVAL, "r = %g must be positive and finite", r);
+  if (!(z_min >= -1.0 && z_min <= 1.0)) return fail(CMBX_EINVAL, "z_min = %g must lie in [-1, 1]", z_min);
+  const double c = 0.5 * p->N * p->dp;
+  xyz[0] = c;
+  xyz[1] = c;
+  xyz[2] = 0.5 * (p->nz - 1) * p->dp - r * (1.0 + z_min) / 2.0;
+  return ok();
+}
+
 int cmbx_slab_spectrum(cmbx_slab* p, const double* k, const double* P, int64_t n) {
   if (int rc = check(p)) return rc;
   if (!k || !P) return fail(CMBX_EINVAL, "k and P_inf must be non-NULL host arrays");

@@ -129,3 +129,26 @@ def test_ensemble_modes_follow_moved_observer(env, mode):
     ens.close()
     for j in jobs:
         j["plan"].close()
+
+
+def test_cap_observer_centres_the_cap(env):
+    """cmbx_plan_cap_observer / cmbx_slab_cap_observer (Sec. II D 1-2): with that observer the
+    cap's z range, o_z + r [z_min, 1], is centred on the box's centre (cubic box) or on the
+    middle of the slab's layers, and its axis runs through the centre in x and y."""
+    cmbx, torch = env
+    plan = cmbx.Plan(32, 2.0, "f32")
+    for r, z_min in ((0.7, math.cos(math.radians(20.0))), (0.9, 0.0), (0.5, -0.5)):
+        o = plan.observer_for_cap(r, z_min)
+        assert o[0] == 1.0 and o[1] == 1.0
+        assert (o[2] + r * z_min + o[2] + r) / 2 == pytest.approx(1.0, abs=1e-15)
+    for bad in ((0.0, 0.5), (1.0, 1.5), (float("nan"), 0.5)):
+        with pytest.raises(cmbx.CmbxError):
+            plan.observer_for_cap(*bad)
+    plan.close()
+    s = cmbx.Slab("hybrid", 32, 16, 0.01, h=6, dtype="f32")
+    o = s.observer_for_cap(0.2, 0.9)
+    assert o[0] == o[1] == pytest.approx(0.16, abs=1e-15)
+    assert (2 * o[2] + 0.2 * 0.9 + 0.2) / 2 == pytest.approx(2.5 * 0.01, abs=1e-15)   # middle of layers 0 .. 5
+    with pytest.raises(cmbx.CmbxError):
+        s.observer_for_cap(-1.0, 0.5)
+    s.close()
