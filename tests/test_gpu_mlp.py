@@ -67,7 +67,30 @@ def _net(seed, sizes=(130, 64, 48, 256)):
     return surrogate.MLP(sizes=sizes, seed=seed)
 
 
+def test_forward_layers_match_oracle_on_their_own_inputs(cmbx):
+    """Each layer against the oracle fed the GPU's own input of that layer: z = bf16(a)
+    bf16(W) + b with FP32 accumulation over K <= 130 terms, within 2e-6 sqrt(K) / 8 of
+    rms(z) as for the product kernel alone, and the GELU of it within 5e-6."""
+    net = _net(3)
+    X = np.random.default_rng(4).standard_normal((37, 130)).astype(np.float32)
+    out, cache = net.forward(torch.tensor(X, device="cuda"))
+    torch.cuda.synchronize()
+    for li, (a, z) in enumerate(cache):
+        a64 = a.cpu().numpy().astype(np.float64)
+        W = omlp.bf16(net.W[li].cpu().numpy())
+        zref = omlp.bf16(a64) @ W + net.b[li].cpu().numpy().astype(np.float64)
+        K = a64.shape[1]
+        assert _rel(z.cpu().numpy(), zref) < 2e-6 * max(1.0, np.sqrt(K) / 8), li
+        if li + 1 < len(cache):
+            assert _rel(cache[li + 1][0].cpu().numpy(), omlp.gelu(zref)) < 5e-6 * max(1.0, np.sqrt(K) / 8), li
+
+
 def test_forward_backward_match_oracle(cmbx):
+    """End to end against the oracle run on its own activations. The bars are wider than
+    per layer: every GEMM rounds its activation operand to BF16, and an FP32 difference of
+    one ulp at a BF16 rounding boundary moves that operand by a BF16 ulp (2^-8 relative),
+    which the later layers carry to the outputs (observed 1e-4 .. 1e-3 of rms); the
+    gradients pass through two more such roundings per layer."""
     net = _net(0)
     rng = np.random.default_rng(1)
     X = rng.standard_normal((37, 130)).astype(np.float32)

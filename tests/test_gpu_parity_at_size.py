@@ -5,6 +5,8 @@
   pruned to their footprint, tiles tuned on each map's pixels, run as one chained
   ensemble on four lanes; every pixel of every map against the oracle, on two replays.
 * 384^3 (radix-3 transform lengths at size), FP32 and FP64, every pixel.
+* The flat-box methods at the benchmark's size (N = 512, M = 32, h = 14): the 2-D (hybrid)
+  method and the 3-D method on the flat box, every pixel of a HEALPix cap.
 * The precision study at 1024^3 (40-degree cap, 4096 x 2048 pixels): FP32 and FP64 plans
   against one FP64 oracle map, per pixel and per recovered-C_l band.
 
@@ -124,6 +126,41 @@ def test_map_384_every_pixel(cmbx, dt, tol):
     err = _rel(got, ref)
     _say(f"384^3 {dt}: {d_np.shape[0]} px, max|d|/rms = {err:.3e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("method", ["hybrid", "flat"])
+def test_slab_methods_at_the_benchmark_size(cmbx, method):
+    """The flat-box methods as the benchmark times them: beam b = 0.01 rad, 10-degree cap on
+    the unit sphere, the Sec. II C box (N = 512, M = 32, dp = 0.0017), h = 14 layers for the
+    2-D method, the oracle programme's P_inf, FP32, tricubic, every pixel of the HEALPix cap
+    at nside 64 against the FP64 oracle (oracle.slab), two realisations."""
+    from oracle import healpix as ohp
+    from oracle import slab as oslab
+    b, theta = 0.01, math.radians(10.0)
+    z_min = math.cos(theta)
+    N, M, dp = oslab.box_size(b, theta)
+    assert (N, M) == (512, 32)
+    h = min(M, int(math.ceil((1.0 - z_min) / dp)) + 5)
+    cl = workloads.synthetic_cl(int(math.ceil(5.0 / b)), ld=1.0 / b)
+    _, bb, k, A, c = oinv.programme(cl, 1.0, theta, b, math.pi / dp)
+    _, p = oinv.solve(A, bb, c)
+    d_np = ohp.cap_directions(64, z_min)
+    s = cmbx.Slab(method, N, M, dp, h=h, dtype="f32", batch=2, interp="tricubic")
+    s.spectrum(k, p)
+    obs = s.observer_for_cap(1.0, z_min)
+    s.set_observer(obs)
+    got = s.simulate(77, 1.0, torch.tensor(d_np, device="cuda")).cpu().numpy()
+    s.close()
+    for i in range(2):
+        if method == "hybrid":
+            lay = oslab.hybrid_layers(oslab.hybrid_columns(N, M, h, dp, 77 + i, k, p))
+        else:
+            lay = oslab.flat_layers(oslab.flat_halfgrid(N, M, dp, 77 + i, k, p))
+        ref = oslab.gather_layers(lay, dp, 1.0, d_np, "tricubic", obs, periodic_z=method == "flat")
+        assert np.all(np.isfinite(ref))
+        err = _rel(got[i], ref)
+        _say(f"{method} N={N} M={M} h={h}: {d_np.shape[0]} px, realisation {i}, max|d|/rms = {err:.3e}")
+        assert err <= 1e-5
 
 
 @pytest.mark.timeout(900)
