@@ -146,6 +146,14 @@ def invert(cl, R, theta_max, beam, N=None, L=1.0, k_max=None):
     return pr["k"], x, info
 
 
+def spectrum_from_cl(cl, b, theta_max, N, L, r):
+    """(k, P_inf) for the target C_l: the programme (invert) with beam b, a cap of polar
+    angle theta_max (radians) on the shell of radius r, unknowns up to the band limit of an
+    N^3 box of side L (pi N / L)."""
+    k, p, _ = invert(cl, r, theta_max, b, N=N, L=L)
+    return k, p
+
+
 def synthetic_job_spectrum(N, L, r, theta_max_deg, amp=1.0):
     """(k, P_inf) of an ensemble job: the programme's solution for the synthetic C_l family
     (l_max = floor(0.8 pi r N / L), l_d = 0.6 l_max, beam 1 / l_d) scaled by ``amp``, on a

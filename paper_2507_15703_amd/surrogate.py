@@ -496,3 +496,17 @@ class Surrogate:
                 k, p, _ = spectrum.invert(cl, r * L_BOX, THETA_MAX, b, N=N, L=L_BOX)
                 out[i] = (k, p, True, (cl_check(k, p, cl, r),) + cap_residual(k, p, cl, N, r))
         return out
+
+
+_shipped = None
+
+
+def surrogate_spectrum(cl, N, r_over_L):
+    """(k, P_inf, used_fallback) for the target C_l from the shipped network (its band
+    projection and checks, the programme when it falls back or the geometry is outside its
+    domain). Needs the library (the network runs in its kernels)."""
+    global _shipped
+    if _shipped is None:
+        _shipped = Surrogate.load()
+    k, p, fb, _ = _shipped.spectrum(np.asarray(cl, dtype=np.float64), int(N), float(r_over_L))
+    return k, p, fb

@@ -36,3 +36,19 @@ def test_surrogate_gain_over_plain_inversion():
     # of 128 maps): every band within 1 % up to three standard errors of the paired means
     assert res["recovered_ratio_max_beyond_3sigma"] <= 0.01
     assert res["speedup"] >= 20
+
+
+def test_surrogate_spectrum_entry():
+    """The survey's name for the surrogate: (k, P_inf, used_fallback) for an in-domain target
+    answered by the network, and the programme's answer outside the domain (N = 192)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import numpy as np
+    from paper_2507_15703_amd import surrogate
+    prm = surrogate.sample_params(np.random.default_rng(5001))
+    prm["N"], prm["r"] = 256, 0.45
+    cl = surrogate.cl_of(prm)
+    k, p, fb = surrogate.surrogate_spectrum(cl, 256, 0.45)
+    assert not fb and k.shape == p.shape and np.all(p >= 0)
+    k2, p2, fb2 = surrogate.surrogate_spectrum(cl, 192, 0.45)
+    assert fb2

@@ -91,3 +91,12 @@ def test_checkpoint_crc(tmp_path):
         f.write(data[: len(data) // 2])
     with pytest.raises(ValueError):
         surrogate.read_checkpoint(str(tmp_path / "cut.npz"))
+
+
+def test_spectrum_from_cl_is_the_programme():
+    prm = _prm(11)
+    cl = surrogate.cl_of(prm)
+    b = 1.0 / (0.6 * (cl.size - 1))
+    k, p = spectrum.spectrum_from_cl(cl, b, surrogate.THETA_MAX, prm["N"], 1.0, prm["r"])
+    k2, p2, _ = surrogate.plain_inversion(prm, cl)
+    assert np.array_equal(k, k2) and np.allclose(p, p2, rtol=1e-9, atol=1e-12 * p2.max())
