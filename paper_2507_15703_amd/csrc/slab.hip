@@ -159,87 +159,83 @@ __global__ __launch_bounds__(256) void k_flat_modes_debug(cpx<T>* __restrict__ o
 }
 
 // ------------------------------------------------------------------ hybrid columns
-// Column (ix, iy), iy = 0 .. N/2: h unit normal pairs from Philox counter (j >> 1, iy, ix, 1)
-// (words (x0, x1) for even layers j, (x2, x3) for odd), times the factor: v = F g with F
-// the row's S / sqrt2 for a generic column, the real part only with S for the four
-// self-conjugate columns; on the rows iy = 0 and N/2 the column (ix) and (-ix) are
-// conjugate, the smaller ix drawn. Sums over m in order, in T.
-template <typename T, int HMAX>
-__device__ __forceinline__ void hybrid_column(int N, int h, int ix, int iy, uint32_t k0, uint32_t k1,
-                                              const int* __restrict__ sidx, const T* __restrict__ S,
-                                              const T* __restrict__ Sfull, const float* __restrict__ tab,
-                                              T (&vr)[HMAX], T (&vi)[HMAX]) {
-  const int M2 = N / 2;
-  const bool row = iy == 0 || iy == M2;
-  const int px = ix == 0 ? 0 : N - ix;
-  const bool self = row && ix == px;
-  const bool flip = row && ix > px;
-  const int dx = flip ? px : ix;
-  T gr[HMAX], gi[HMAX];
-#pragma unroll
-  for (int q = 0; q < HMAX / 2; ++q) {
-    if (2 * q < h) {
-      const uint4 w = philox4x32_10(make_uint4((uint32_t)q, (uint32_t)iy, (uint32_t)dx, 1u), k0, k1);
-      normal_pair(w.x, w.y, gr[2 * q], gi[2 * q], tab);
-      normal_pair(w.z, w.w, gr[2 * q + 1], gi[2 * q + 1], tab);
-    } else {
-      gr[2 * q] = gi[2 * q] = gr[2 * q + 1] = gi[2 * q + 1] = T(0);
-    }
-  }
-  const int fx = fq(ix, N), fy = fq(iy, N);
-  const T* F = self ? Sfull + (size_t)((ix == M2) + (iy == M2)) * h * h : S + (size_t)sidx[fx * fx + fy * fy] * h * h;
-#pragma unroll
-  for (int j = 0; j < HMAX; ++j) {
-    T ar = T(0), ai = T(0);
-    if (j < h) {
-#pragma unroll
-      for (int m = 0; m < HMAX; ++m) {
-        if (m < h) {
-          const T f = F[j * h + m];
-          ar += f * gr[m];
-          ai += f * gi[m];
-        }
-      }
-    }
-    vr[j] = ar;
-    vi[j] = self ? T(0) : (flip ? -ai : ai);
-  }
-}
-
-// One thread per packed column (ix, iyc), iyc < N/2 (column 0 packs the rows iy = 0 and
-// N/2 as A + i B); with `unpacked`, one per column (ix, iy), iy <= N/2, into [h][N][N/2+1].
+// Column (ix, iy), iy = 0 .. N/2, of the 2-D method: h unit normal pairs, layer j from the
+// Philox counter (j >> 1, iy, ix, 1) (words (x0, x1) for even j, (x2, x3) for odd), times
+// the factor: v = F g with F the row's S / sqrt2 for a generic column, the real part only
+// with S for the four self-conjugate columns; on the rows iy = 0 and N/2 the columns (ix)
+// and (-ix) are conjugate, the smaller ix drawn. Sums over m in order, in T.
+//
+// One thread per (column, layer): WG = C = 256 / HMAX columns x HMAX layers. Thread (q, c)
+// first draws the normal pair of layer q of column c into LDS, then forms row q of the
+// column's factor times the pair vector (a column's h x h products spread over h threads).
+// Columns: with `unpacked` every (ix, iy), iy <= N/2,
+// each written to its place; otherwise first the N pairs (ix, 0), (ix, N/2), neighbours in
+// one workgroup, which write their packed sum A + i B to column 0, then (ix, iy) for
+// 1 <= iy < N/2.
 template <typename T, int HMAX>
 __global__ __launch_bounds__(256) void k_hybrid_columns(cpx<T>* __restrict__ buf, int N, int h,
                                                         const int* __restrict__ sidx, const T* __restrict__ S,
                                                         const T* __restrict__ Sfull, uint32_t k0, uint32_t k1,
                                                         const float* __restrict__ bmg, int unpacked) {
+  constexpr int C = 256 / HMAX;
+  static_assert(C % 2 == 0, "the pairs of column 0 share a workgroup");
   __shared__ float tabl[sizeof(T) == 4 ? kTabFloats : 1];
+  __shared__ T gr[HMAX][C], gi[HMAX][C];
   const float* tab = stage_tab<T>(tabl, bmg, threadIdx.x, 256);
-  __syncthreads();
   const int M2 = N / 2;
-  const int W = unpacked ? M2 + 1 : M2;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)N * W) return;
-  const int ix = (int)(t / W), iyc = (int)(t % W);
-  T ar[HMAX], ai[HMAX];
-  hybrid_column<T, HMAX>(N, h, ix, iyc, k0, k1, sidx, S, Sfull, tab, ar, ai);
-  if (unpacked) {
+  const int64_t pairs = unpacked ? 0 : 2 * (int64_t)N;  // packed: (ix, 0), (ix, N/2) first
+  const int per_row = unpacked ? M2 + 1 : M2 - 1;         // the other columns per ix
+  const int64_t ncols = pairs + (int64_t)N * per_row;
+  const int q = threadIdx.x / C, c = threadIdx.x % C;
+  const int64_t u = (int64_t)blockIdx.x * C + c;
+  const bool live = u < ncols && q < h;
+  const bool pair = u < pairs;
+  const int64_t v = u - pairs;
+  const int ix = pair ? (int)(u >> 1) : (int)(v / per_row);
+  const int iy = pair ? ((u & 1) ? M2 : 0) : (int)(v % per_row) + (unpacked ? 0 : 1);
+  const bool row = iy == 0 || iy == M2;
+  const int px = ix == 0 ? 0 : N - ix;
+  const bool self = row && ix == px;
+  const bool flip = row && ix > px;
+  __syncthreads();  // the staged tables
+  T a = T(0), b = T(0);
+  if (live) {
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)(q >> 1), (uint32_t)iy, (uint32_t)(flip ? px : ix), 1u), k0, k1);
+    if (q & 1) normal_pair(w.z, w.w, a, b, tab);
+    else normal_pair(w.x, w.y, a, b, tab);
+  }
+  gr[q][c] = a;
+  gi[q][c] = b;
+  __syncthreads();
+  T ar = T(0), ai = T(0);
+  if (live) {
+    const int fx = fq(ix, N), fy = fq(iy, N);
+    const T* F = (self ? Sfull + (size_t)((ix == M2) + (iy == M2)) * h * h : S + (size_t)sidx[fx * fx + fy * fy] * h * h) +
+                 (size_t)q * h;
 #pragma unroll
-    for (int j = 0; j < HMAX; ++j)
-      if (j < h) buf[((size_t)j * N + ix) * (M2 + 1) + iyc] = {ar[j], ai[j]};
+    for (int m = 0; m < HMAX; ++m) {
+      if (m < h) {
+        const T f = F[m];
+        ar += f * gr[m][c];
+        ai += f * gi[m][c];
+      }
+    }
+  }
+  const T vi = self ? T(0) : (flip ? -ai : ai);
+  const size_t at = ((size_t)q * N + ix) * (unpacked ? M2 + 1 : M2) + iy;
+  if ((int64_t)blockIdx.x * C >= pairs) {  // no pair in this workgroup (uniform)
+    if (live) buf[at] = {ar, vi};
     return;
   }
-  if (iyc == 0) {
-    T br[HMAX], bi[HMAX];
-    hybrid_column<T, HMAX>(N, h, ix, M2, k0, k1, sidx, S, Sfull, tab, br, bi);
-#pragma unroll
-    for (int j = 0; j < HMAX; ++j)
-      if (j < h) buf[((size_t)j * N + ix) * M2] = {ar[j] - bi[j], ai[j] + br[j]};
-  } else {
-#pragma unroll
-    for (int j = 0; j < HMAX; ++j)
-      if (j < h) buf[((size_t)j * N + ix) * M2 + iyc] = {ar[j], ai[j]};
-  }
+  // column 0 packs A = (ix, 0) (even c) and B = (ix, N/2) (odd c), neighbours in this
+  // workgroup (pairs start at column 0 and C is even): A + i B
+  __syncthreads();  // every thread has read the normals: gr, gi take the results
+  gr[q][c] = ar;
+  gi[q][c] = vi;
+  __syncthreads();
+  if (!live) return;
+  if (!pair) buf[at] = {ar, vi};
+  else if ((c & 1) == 0) buf[((size_t)q * N + ix) * M2] = {ar - gi[q][c + 1], vi + gr[q][c + 1]};
 }
 
 // ------------------------------------------------------------------ layer gather
@@ -364,19 +360,21 @@ const FlatEntry* find_flat(int M) {
   return nullptr;
 }
 
-template <typename T>
-hipError_t run_hybrid(const SlabColumnsArgs& a, int unpacked, hipStream_t s) {
+template <typename T, int HMAX>
+hipError_t run_hybrid_h(const SlabColumnsArgs& a, int unpacked, hipStream_t s) {
   const T* S = (const T*)a.table;
   const T* Sfull = S + (size_t)a.rows * a.h * a.h;
-  const int64_t threads = (int64_t)a.N * (unpacked ? a.N / 2 + 1 : a.N / 2);
-  const dim3 grid((unsigned)((threads + 255) / 256));
-  if (a.h <= 16)
-    hipLaunchKernelGGL((k_hybrid_columns<T, 16>), grid, dim3(256), 0, s, (cpx<T>*)a.buf, a.N, a.h, a.sidx, S, Sfull,
-                       a.k0, a.k1, a.bm_tab, unpacked);
-  else
-    hipLaunchKernelGGL((k_hybrid_columns<T, kSlabMaxLayers>), grid, dim3(256), 0, s, (cpx<T>*)a.buf, a.N, a.h, a.sidx,
-                       S, Sfull, a.k0, a.k1, a.bm_tab, unpacked);
+  constexpr int C = 256 / HMAX;
+  const int M2 = a.N / 2;
+  const int64_t ncols = (unpacked ? 0 : 2 * (int64_t)a.N) + (int64_t)a.N * (unpacked ? M2 + 1 : M2 - 1);
+  hipLaunchKernelGGL((k_hybrid_columns<T, HMAX>), dim3((unsigned)((ncols + C - 1) / C)), dim3(256), 0, s,
+                     (cpx<T>*)a.buf, a.N, a.h, a.sidx, S, Sfull, a.k0, a.k1, a.bm_tab, unpacked);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_hybrid(const SlabColumnsArgs& a, int unpacked, hipStream_t s) {
+  return a.h <= 16 ? run_hybrid_h<T, 16>(a, unpacked, s) : run_hybrid_h<T, kSlabMaxLayers>(a, unpacked, s);
 }
 
 }  // namespace
