@@ -165,38 +165,57 @@ __global__ __launch_bounds__(256) void k_flat_modes_debug(cpx<T>* __restrict__ o
 // with S for the four self-conjugate columns; on the rows iy = 0 and N/2 the columns (ix)
 // and (-ix) are conjugate, the smaller ix drawn. Sums over m in order, in T.
 //
-// One thread per (column, layer): WG = C = 256 / HMAX columns x HMAX layers. Thread (q, c)
-// first draws the normal pair of layer q of column c into LDS, then forms row q of the
-// column's factor times the pair vector (a column's h x h products spread over h threads).
-// Columns: with `unpacked` every (ix, iy), iy <= N/2,
-// each written to its place; otherwise first the N pairs (ix, 0), (ix, N/2), neighbours in
-// one workgroup, which write their packed sum A + i B to column 0, then (ix, iy) for
-// 1 <= iy < N/2.
+// One thread per (column, layer). Workgroup = the rows ix = g and N - g (one row for g = 0
+// and N/2) and CB consecutive columns of the order iy = 0, N/2, 1, 2, ..., N/2 - 1. The
+// two rows share |k_x| and so every column's factor: the CB factors are first copied into
+// LDS (a group of 2 HMAX threads per factor, contiguous reads) and read only there. Thread
+// (q, r, c) then draws the normal pair of layer q of column c in row r into LDS and forms
+// row q of the factor times the column's pair vector. With `unpacked` every (ix, iy) is
+// written to its place; otherwise (ix, 0) and (ix, N/2), the first two of the first
+// block, write their packed sum A + i B to column 0.
 template <typename T, int HMAX>
-__global__ __launch_bounds__(256) void k_hybrid_columns(cpx<T>* __restrict__ buf, int N, int h,
+struct HybridShape {
+  static constexpr int NT = 512;
+  static constexpr int CB = NT / (2 * HMAX);  // columns per workgroup
+  static constexpr int FS = HMAX * HMAX + 1;  // largest LDS stride of a factor
+  static_assert(CB >= 2, "the pairs of column 0 share a workgroup");
+};
+
+template <typename T, int HMAX>
+__global__ __launch_bounds__(512) void k_hybrid_columns(cpx<T>* __restrict__ buf, int N, int h,
                                                         const int* __restrict__ sidx, const T* __restrict__ S,
                                                         const T* __restrict__ Sfull, uint32_t k0, uint32_t k1,
                                                         const float* __restrict__ bmg, int unpacked) {
-  constexpr int C = 256 / HMAX;
-  static_assert(C % 2 == 0, "the pairs of column 0 share a workgroup");
+  using Sh = HybridShape<T, HMAX>;
+  constexpr int NT = Sh::NT, CB = Sh::CB;
   __shared__ float tabl[sizeof(T) == 4 ? kTabFloats : 1];
-  __shared__ T gr[HMAX][C], gi[HMAX][C];
-  const float* tab = stage_tab<T>(tabl, bmg, threadIdx.x, 256);
+  __shared__ T fac[CB * Sh::FS];
+  __shared__ T gr[HMAX][2][CB], gi[HMAX][2][CB];
+  const int tid = threadIdx.x;
+  const float* tab = stage_tab<T>(tabl, bmg, tid, NT);
   const int M2 = N / 2;
-  const int64_t pairs = unpacked ? 0 : 2 * (int64_t)N;  // packed: (ix, 0), (ix, N/2) first
-  const int per_row = unpacked ? M2 + 1 : M2 - 1;         // the other columns per ix
-  const int64_t ncols = pairs + (int64_t)N * per_row;
-  const int q = threadIdx.x / C, c = threadIdx.x % C;
-  const int64_t u = (int64_t)blockIdx.x * C + c;
-  const bool live = u < ncols && q < h;
-  const bool pair = u < pairs;
-  const int64_t v = u - pairs;
-  const int ix = pair ? (int)(u >> 1) : (int)(v / per_row);
-  const int iy = pair ? ((u & 1) ? M2 : 0) : (int)(v % per_row) + (unpacked ? 0 : 1);
-  const bool row = iy == 0 || iy == M2;
+  const int g = blockIdx.y;
+  const int hh = h * h, fs = hh | 1;  // odd stride: the CB factors start in different banks
+  {
+    const int cc = tid / (2 * HMAX), li = tid % (2 * HMAX);
+    const int j = blockIdx.x * CB + cc;
+    if (j <= M2) {
+      const int iy = j == 0 ? 0 : (j == 1 ? M2 : j - 1);
+      // self-conjugate columns: iy and ix = g both 0 or N/2
+      const bool self = (iy == 0 || iy == M2) && (g == 0 || g == M2);
+      const T* src = self ? Sfull + (size_t)((g == M2) + (iy == M2)) * hh : S + (size_t)sidx[g * g + iy * iy] * hh;
+      for (int e = li; e < hh; e += 2 * HMAX) fac[cc * fs + e] = src[e];
+    }
+  }
+  const int c = tid % CB, r = (tid / CB) & 1, q = tid / (2 * CB);
+  const int j = blockIdx.x * CB + c;
+  const int iy = j == 0 ? 0 : (j == 1 ? M2 : j - 1);
+  const int ix = r ? N - g : g;
+  const bool live = j <= M2 && (r == 0 || (g > 0 && g < M2)) && q < h;
+  const bool rowc = iy == 0 || iy == M2;
   const int px = ix == 0 ? 0 : N - ix;
-  const bool self = row && ix == px;
-  const bool flip = row && ix > px;
+  const bool self = rowc && ix == px;
+  const bool flip = rowc && ix > px;
   __syncthreads();  // the staged tables
   T a = T(0), b = T(0);
   if (live) {
@@ -204,38 +223,35 @@ __global__ __launch_bounds__(256) void k_hybrid_columns(cpx<T>* __restrict__ buf
     if (q & 1) normal_pair(w.z, w.w, a, b, tab);
     else normal_pair(w.x, w.y, a, b, tab);
   }
-  gr[q][c] = a;
-  gi[q][c] = b;
+  gr[q][r][c] = a;
+  gi[q][r][c] = b;
   __syncthreads();
   T ar = T(0), ai = T(0);
   if (live) {
-    const int fx = fq(ix, N), fy = fq(iy, N);
-    const T* F = (self ? Sfull + (size_t)((ix == M2) + (iy == M2)) * h * h : S + (size_t)sidx[fx * fx + fy * fy] * h * h) +
-                 (size_t)q * h;
+    const T* F = fac + c * fs + q * h;
 #pragma unroll
     for (int m = 0; m < HMAX; ++m) {
       if (m < h) {
         const T f = F[m];
-        ar += f * gr[m][c];
-        ai += f * gi[m][c];
+        ar += f * gr[m][r][c];
+        ai += f * gi[m][r][c];
       }
     }
   }
   const T vi = self ? T(0) : (flip ? -ai : ai);
-  const size_t at = ((size_t)q * N + ix) * (unpacked ? M2 + 1 : M2) + iy;
-  if ((int64_t)blockIdx.x * C >= pairs) {  // no pair in this workgroup (uniform)
+  const int W = unpacked ? M2 + 1 : M2;
+  const size_t at = ((size_t)q * N + ix) * W + iy;
+  if (blockIdx.x > 0 || unpacked) {  // uniform: no packed pair in this workgroup
     if (live) buf[at] = {ar, vi};
     return;
   }
-  // column 0 packs A = (ix, 0) (even c) and B = (ix, N/2) (odd c), neighbours in this
-  // workgroup (pairs start at column 0 and C is even): A + i B
   __syncthreads();  // every thread has read the normals: gr, gi take the results
-  gr[q][c] = ar;
-  gi[q][c] = vi;
+  gr[q][r][c] = ar;
+  gi[q][r][c] = vi;
   __syncthreads();
   if (!live) return;
-  if (!pair) buf[at] = {ar, vi};
-  else if ((c & 1) == 0) buf[((size_t)q * N + ix) * M2] = {ar - gi[q][c + 1], vi + gr[q][c + 1]};
+  if (c >= 2) buf[at] = {ar, vi};
+  else if (c == 0) buf[((size_t)q * N + ix) * W] = {ar - gi[q][r][1], vi + gr[q][r][1]};
 }
 
 // ------------------------------------------------------------------ layer gather
@@ -364,11 +380,11 @@ template <typename T, int HMAX>
 hipError_t run_hybrid_h(const SlabColumnsArgs& a, int unpacked, hipStream_t s) {
   const T* S = (const T*)a.table;
   const T* Sfull = S + (size_t)a.rows * a.h * a.h;
-  constexpr int C = 256 / HMAX;
+  using Sh = HybridShape<T, HMAX>;
   const int M2 = a.N / 2;
-  const int64_t ncols = (unpacked ? 0 : 2 * (int64_t)a.N) + (int64_t)a.N * (unpacked ? M2 + 1 : M2 - 1);
-  hipLaunchKernelGGL((k_hybrid_columns<T, HMAX>), dim3((unsigned)((ncols + C - 1) / C)), dim3(256), 0, s,
-                     (cpx<T>*)a.buf, a.N, a.h, a.sidx, S, Sfull, a.k0, a.k1, a.bm_tab, unpacked);
+  const dim3 grid((unsigned)((M2 + 1 + Sh::CB - 1) / Sh::CB), (unsigned)(M2 + 1));
+  hipLaunchKernelGGL((k_hybrid_columns<T, HMAX>), grid, dim3(Sh::NT), 0, s, (cpx<T>*)a.buf, a.N, a.h, a.sidx, S,
+                     Sfull, a.k0, a.k1, a.bm_tab, unpacked);
   return hipGetLastError();
 }
 

@@ -6,10 +6,13 @@ C_l on that cap, ``spectrum.synthetic_job_spectrum``; the power-law table with
 ``--spectrum powerlaw``; autotuned tile shapes unless given), with its seed: one
 warm-up realisation, then ``--reps`` launches of each kernel of the hot path through
 cmbx_time_passes, and a device-to-device copy of exactly 512 MiB (torch) whose counter
-readings calibrate the HBM byte counters. Usage:
+readings calibrate the HBM byte counters. With ``--slab``: instead, the benchmark's
+flat-box section (the 2-D method and the 3-D method on the flat N = 512, M = 32 box of a
+10-degree cap, h = 14 layers, nside-64 pixels), ``--reps`` maps of each. Usage:
 
     rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2507_15703_amd.profile_run
     rocprofv3 --pmc FETCH_SIZE -d OUT -- python -m paper_2507_15703_amd.profile_run --reps 1
+    rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2507_15703_amd.profile_run --slab
 """
 import argparse
 import json
@@ -30,11 +33,16 @@ def main():
     ap.add_argument("--plans", default=None, help="FFT stage plans of x, y, z as 'a,b,c' (with given tiles)")
     ap.add_argument("--tile-y", type=int, default=None)
     ap.add_argument("--spectrum", default="lp", choices=["lp", "powerlaw"])
+    ap.add_argument("--slab", action="store_true", help="the flat-box methods instead")
     args = ap.parse_args()
 
     import torch
 
     from paper_2507_15703_amd import cmbx, spectrum, workloads
+    if args.slab:
+        import bench
+        print(json.dumps(bench.slab_section(torch, cmbx, reps=args.reps)), flush=True)
+        return
 
     N = args.N
     job = [j for j in workloads.ensemble_jobs() if j["N"] == 512][0]
