@@ -642,27 +642,35 @@ __device__ __forceinline__ T stencil_sum(const T* __restrict__ field, int N, con
   int iz[K];
 #pragma unroll
   for (int c = 0; c < K; ++c) iz[c] = wrap(i0[2] + c, N);
-  T acc = 0;
+  // every tap is loaded before any is summed, so that the K x K line loads are in flight
+  // together rather than one round trip after another
+  T q[K][K][K];
 #pragma unroll
   for (int a = 0; a < K; ++a) {
     const int ix = wrap(i0[0] + a, N);
-    T accb = 0;
 #pragma unroll
     for (int bb = 0; bb < K; ++bb) {
       const int iy = wrap(i0[1] + bb, N);
       const T* line = field + ((size_t)ix * N + iy) * N;
-      T q[K];
       if constexpr (CONTIGUOUS) {
         const typename Taps<T, K>::vec v = *reinterpret_cast<const typename Taps<T, K>::vec*>(line + i0[2]);
 #pragma unroll
-        for (int c = 0; c < K; ++c) q[c] = v[c];
+        for (int c = 0; c < K; ++c) q[a][bb][c] = v[c];
       } else {
 #pragma unroll
-        for (int c = 0; c < K; ++c) q[c] = line[iz[c]];
+        for (int c = 0; c < K; ++c) q[a][bb][c] = line[iz[c]];
       }
+    }
+  }
+  T acc = 0;
+#pragma unroll
+  for (int a = 0; a < K; ++a) {
+    T accb = 0;
+#pragma unroll
+    for (int bb = 0; bb < K; ++bb) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < K; ++c) s += w[2][c] * q[c];
+      for (int c = 0; c < K; ++c) s += w[2][c] * q[a][bb][c];
       accb += w[1][bb] * s;
     }
     acc += w[0][a] * accb;

@@ -312,26 +312,33 @@ __global__ __launch_bounds__(256) void k_slab_gather(const T* __restrict__ field
     return;
   }
   const bool contiguous = i0[1] >= 0 && i0[1] + K <= N;
-  T acc = T(0);
+  // every tap is loaded before any is summed: the K x K row loads are in flight together
+  T q[K][K][K];
 #pragma unroll
   for (int c = 0; c < K; ++c) {
     const int iz = periodic ? wrapn(i0[2] + c, nz) : i0[2] + c;
-    T accz = T(0);
 #pragma unroll
     for (int a = 0; a < K; ++a) {
       const T* row = field + ((size_t)iz * N + wrapn(i0[0] + a, N)) * N;
-      T q[K];
       if (contiguous) {
         const typename SlabTaps<T, K>::vec v = *reinterpret_cast<const typename SlabTaps<T, K>::vec*>(row + i0[1]);
 #pragma unroll
-        for (int b = 0; b < K; ++b) q[b] = v[b];
+        for (int b = 0; b < K; ++b) q[c][a][b] = v[b];
       } else {
 #pragma unroll
-        for (int b = 0; b < K; ++b) q[b] = row[wrapn(i0[1] + b, N)];
+        for (int b = 0; b < K; ++b) q[c][a][b] = row[wrapn(i0[1] + b, N)];
       }
+    }
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    T accz = T(0);
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
       T s = T(0);
 #pragma unroll
-      for (int b = 0; b < K; ++b) s += w[1][b] * q[b];
+      for (int b = 0; b < K; ++b) s += w[1][b] * q[c][a][b];
       accz += w[0][a] * s;
     }
     acc += w[2][c] * accz;
@@ -342,8 +349,11 @@ __global__ __launch_bounds__(256) void k_slab_gather(const T* __restrict__ field
 // ------------------------------------------------------------------ dispatch
 template <typename T, int MZ>
 constexpr int flat_cols() {
-  // columns per workgroup: 16 (FP32) / 8 (FP64) while the tile stays within 64 KB
+  // columns per workgroup: from 16 (FP32) / 8 (FP64), doubled up to 256 while the tile holds
+  // fewer than 2048 modes (shallow boxes: four waves share the staged tables), halved while
+  // the tile exceeds 64 KB
   int c = sizeof(T) == 4 ? 16 : 8;
+  while (c < 256 && c * MZ < 2048) c *= 2;
   while (c > 1 && c * MZ * (int)sizeof(cpx<T>) > 65536) c /= 2;
   return c;
 }
