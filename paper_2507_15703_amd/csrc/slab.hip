@@ -166,19 +166,21 @@ __global__ __launch_bounds__(256) void k_flat_modes_debug(cpx<T>* __restrict__ o
 // and (-ix) are conjugate, the smaller ix drawn. Sums over m in order, in T.
 //
 // One thread per (column, layer). Workgroup = the rows ix = g and N - g (one row for g = 0
-// and N/2) and CB consecutive columns of the order iy = 0, N/2, 1, 2, ..., N/2 - 1. The
-// two rows share |k_x| and so every column's factor: the CB factors are first copied into
-// LDS (a group of 2 HMAX threads per factor, contiguous reads) and read only there. Thread
-// (q, r, c) then draws the normal pair of layer q of column c in row r into LDS and forms
-// row q of the factor times the column's pair vector. With `unpacked` every (ix, iy) is
-// written to its place; otherwise (ix, 0) and (ix, N/2), the first two of the first
-// block, write their packed sum A + i B to column 0.
+// and N/2) and a block of columns: CB consecutive iy < N/2 (128-byte aligned rows of the
+// packed layers), or, in the last block, the pair iy = 0 and N/2 whose packed sum A + i B
+// is column 0 (column 0 is then written by the pair block only; with `unpacked` every
+// (ix, iy) is written to its own place). The two rows share |k_x| and so every column's
+// factor: each group of 2 HMAX threads loads one factor into registers, the loads stay in
+// flight while the normal pairs are drawn, and the factors are then stored to LDS and read
+// only there. Thread (q, r, c) draws the normal pair of layer q of column c in row r and
+// forms row q of the factor times the column's pair vector.
 template <typename T, int HMAX>
 struct HybridShape {
   static constexpr int NT = 512;
   static constexpr int CB = NT / (2 * HMAX);  // columns per workgroup
   static constexpr int FS = HMAX * HMAX + 1;  // largest LDS stride of a factor
-  static_assert(CB >= 2, "the pairs of column 0 share a workgroup");
+  static constexpr int PER = HMAX / 2;        // factor elements per thread
+  static_assert(CB >= 2, "the packed pair shares a workgroup");
 };
 
 template <typename T, int HMAX>
@@ -192,36 +194,56 @@ __global__ __launch_bounds__(512) void k_hybrid_columns(cpx<T>* __restrict__ buf
   __shared__ T fac[CB * Sh::FS];
   __shared__ T gr[HMAX][2][CB], gi[HMAX][2][CB];
   const int tid = threadIdx.x;
-  const float* tab = stage_tab<T>(tabl, bmg, tid, NT);
   const int M2 = N / 2;
   const int g = blockIdx.y;
   const int hh = h * h, fs = hh | 1;  // odd stride: the CB factors start in different banks
-  {
-    const int cc = tid / (2 * HMAX), li = tid % (2 * HMAX);
-    const int j = blockIdx.x * CB + cc;
-    if (j <= M2) {
-      const int iy = j == 0 ? 0 : (j == 1 ? M2 : j - 1);
-      // self-conjugate columns: iy and ix = g both 0 or N/2
-      const bool self = (iy == 0 || iy == M2) && (g == 0 || g == M2);
-      const T* src = self ? Sfull + (size_t)((g == M2) + (iy == M2)) * hh : S + (size_t)sidx[g * g + iy * iy] * hh;
-      for (int e = li; e < hh; e += 2 * HMAX) fac[cc * fs + e] = src[e];
+  const bool pairblk = (int)blockIdx.x == (M2 + CB - 1) / CB;
+  // column iy of block position p; false if the position holds none
+  auto column = [&](int p, int& iy) {
+    if (pairblk) {
+      iy = p == 0 ? 0 : M2;
+      return p < 2;
     }
+    iy = (int)blockIdx.x * CB + p;
+    return iy < M2;
+  };
+  // the tables first: a wait for one of their loads would also wait for the factors'
+  const float* tab = stage_tab<T>(tabl, bmg, tid, NT);
+  const int fc = tid / (2 * HMAX), li = tid % (2 * HMAX);
+  int fiy;
+  const bool fload = column(fc, fiy);
+  // self-conjugate columns: iy and ix = g both 0 or N/2 (without a column: any factor,
+  // loaded and not stored); indices clamped into the factor, so no load waits on a branch
+  const bool fself = (fiy == 0 || fiy == M2) && (g == 0 || g == M2);
+  const T* src = !fload ? S
+                 : fself ? Sfull + (size_t)((g == M2) + (fiy == M2)) * hh
+                         : S + (size_t)sidx[g * g + fiy * fiy] * hh;
+  T fv[Sh::PER];
+#pragma unroll
+  for (int k = 0; k < Sh::PER; ++k) {
+    const int e = li + 2 * HMAX * k;
+    fv[k] = src[e < hh ? e : hh - 1];
   }
   const int c = tid % CB, r = (tid / CB) & 1, q = tid / (2 * CB);
-  const int j = blockIdx.x * CB + c;
-  const int iy = j == 0 ? 0 : (j == 1 ? M2 : j - 1);
+  int iy;
+  const bool col = column(c, iy);
   const int ix = r ? N - g : g;
-  const bool live = j <= M2 && (r == 0 || (g > 0 && g < M2)) && q < h;
+  const bool live = col && (r == 0 || (g > 0 && g < M2)) && q < h;
   const bool rowc = iy == 0 || iy == M2;
   const int px = ix == 0 ? 0 : N - ix;
   const bool self = rowc && ix == px;
   const bool flip = rowc && ix > px;
-  __syncthreads();  // the staged tables
+  lds_barrier();  // the staged tables (the factor loads stay in flight)
   T a = T(0), b = T(0);
   if (live) {
     const uint4 w = philox4x32_10(make_uint4((uint32_t)(q >> 1), (uint32_t)iy, (uint32_t)(flip ? px : ix), 1u), k0, k1);
     if (q & 1) normal_pair(w.z, w.w, a, b, tab);
     else normal_pair(w.x, w.y, a, b, tab);
+  }
+  if (fload) {
+#pragma unroll
+    for (int k = 0; k < Sh::PER; ++k)
+      if (li + 2 * HMAX * k < hh) fac[fc * fs + li + 2 * HMAX * k] = fv[k];
   }
   gr[q][r][c] = a;
   gi[q][r][c] = b;
@@ -241,17 +263,19 @@ __global__ __launch_bounds__(512) void k_hybrid_columns(cpx<T>* __restrict__ buf
   const T vi = self ? T(0) : (flip ? -ai : ai);
   const int W = unpacked ? M2 + 1 : M2;
   const size_t at = ((size_t)q * N + ix) * W + iy;
-  if (blockIdx.x > 0 || unpacked) {  // uniform: no packed pair in this workgroup
-    if (live) buf[at] = {ar, vi};
+  if (!pairblk) {  // uniform; packed column 0 comes from the pair block
+    if (live && (unpacked || iy != 0)) buf[at] = {ar, vi};
+    return;
+  }
+  if (unpacked) {  // uniform: (ix, 0) was written by the first block
+    if (live && c == 1) buf[at] = {ar, vi};
     return;
   }
   __syncthreads();  // every thread has read the normals: gr, gi take the results
   gr[q][r][c] = ar;
   gi[q][r][c] = vi;
   __syncthreads();
-  if (!live) return;
-  if (c >= 2) buf[at] = {ar, vi};
-  else if (c == 0) buf[((size_t)q * N + ix) * W] = {ar - gi[q][r][1], vi + gr[q][r][1]};
+  if (live && c == 0) buf[((size_t)q * N + ix) * W] = {ar - gi[q][r][1], vi + gr[q][r][1]};
 }
 
 // ------------------------------------------------------------------ layer gather
@@ -392,7 +416,7 @@ hipError_t run_hybrid_h(const SlabColumnsArgs& a, int unpacked, hipStream_t s) {
   const T* Sfull = S + (size_t)a.rows * a.h * a.h;
   using Sh = HybridShape<T, HMAX>;
   const int M2 = a.N / 2;
-  const dim3 grid((unsigned)((M2 + 1 + Sh::CB - 1) / Sh::CB), (unsigned)(M2 + 1));
+  const dim3 grid((unsigned)((M2 + Sh::CB - 1) / Sh::CB + 1), (unsigned)(M2 + 1));  // + the pair block
   hipLaunchKernelGGL((k_hybrid_columns<T, HMAX>), grid, dim3(Sh::NT), 0, s, (cpx<T>*)a.buf, a.N, a.h, a.sidx, S,
                      Sfull, a.k0, a.k1, a.bm_tab, unpacked);
   return hipGetLastError();
