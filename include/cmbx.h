@@ -266,13 +266,15 @@ int cmbx_debug_gather(cmbx_plan* plan, const void* field, double r, const double
 
 /*
  * Time each kernel of the hot path for realisation `seed` of the plan (its first batch
- * slot): every kernel is launched `reps` times in a row on the plan's stream between two
- * HIP events, and ms[i] receives the average duration in milliseconds of kernel i:
- * ms[0] pass x (noise + x transform), ms[1] pass y, ms[2] pass z (complex-to-real),
+ * slot): every kernel is launched once untimed and then `reps` times in a row on the
+ * plan's stream between two HIP events (the first timed launch is queued while the
+ * untimed one runs), and ms[i] receives the average duration in milliseconds of kernel
+ * i: ms[0] pass x (noise + x transform), ms[1] pass y, ms[2] pass z (complex-to-real),
  * ms[3] gather into out[0 .. n_pix). The passes run as in cmbx_simulate_patch: if the
- * plan prunes, the map footprint is made first (not timed). Synchronises the plan's
- * stream; the workspace and out hold one realisation afterwards. Errors: as
- * cmbx_simulate_patch, CMBX_EINVAL for reps < 1 or ms == NULL.
+ * plan prunes, the map footprint is made first (not timed). The y and z passes work in
+ * place, so their repeated launches touch the same memory as one launch but leave no
+ * realisation behind: simulate again before using the workspace or out. Synchronises the
+ * plan's stream. Errors: as cmbx_simulate_patch, CMBX_EINVAL for reps < 1 or ms == NULL.
  */
 int cmbx_time_passes(cmbx_plan* plan, uint64_t seed, double r, const double* dirs, int64_t n_pix,
                      void* out, int reps, double* ms);

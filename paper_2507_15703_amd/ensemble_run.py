@@ -1,6 +1,6 @@
 """Throughput of the mixed-size ensemble, batched against unbatched, on one GPU.
 
-    python -m paper_2507_15703_amd.ensemble_run [--steps 10] [--warmup 2] [--dtype f32]
+    python -m paper_2507_15703_amd.ensemble_run [--steps 10] [--warmup 2] [--dtype f32] [--fixed-dirs]
 
 The ensemble workload: 16 x 128^3 + 8 x 256^3 + 4 x 384^3 + 4 x 512^3 boxes, each with
 its own seed, r = 0.45 L, a cap of half-angle drawn in [10, 40] deg and a spectrum
@@ -23,12 +23,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 
-def build(torch, cmbx, workloads, dtype, kind="lp"):
+def build(torch, cmbx, workloads, dtype, kind="lp", fixed_dirs=False):
     from paper_2507_15703_amd import spectrum
     jobs = []
     for j in workloads.ensemble_jobs():
         N, L = j["N"], 1.0
         plan = cmbx.Plan(N, L, dtype, batch=1, interp="tricubic")
+        if fixed_dirs:
+            plan.set_fixed_dirs(True)
         if kind == "lp":
             k, p = spectrum.synthetic_job_spectrum(N, L, j["r_over_L"] * L, j["theta_deg"], j["amp"])
         else:
@@ -48,13 +50,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--spectrum", default="lp", choices=["lp", "powerlaw"])
+    ap.add_argument("--fixed-dirs", action="store_true",
+                    help="every plan keeps its directions (one footprint per plan, as in bench.py)")
     args = ap.parse_args()
 
     import torch
 
     from paper_2507_15703_amd import cmbx, workloads
 
-    jobs = build(torch, cmbx, workloads, args.dtype, args.spectrum)
+    jobs = build(torch, cmbx, workloads, args.dtype, args.spectrum, args.fixed_dirs)
     ens = cmbx.Ensemble([{k: j[k] for k in ("plan", "seed", "r", "dirs", "out")} for j in jobs], mode="auto")
 
     def batched():
@@ -82,7 +86,7 @@ def main():
     n = len(jobs) * args.steps
     sizes = sorted({j["N"] for j in jobs})
     print(json.dumps({"workload": "16x128^3 + 8x256^3 + 4x384^3 + 4x512^3, caps U[10,40] deg, tricubic",
-                      "spectrum": args.spectrum, "dtype": args.dtype, "maps_per_step": len(jobs), "steps": args.steps,
+                      "spectrum": args.spectrum, "dtype": args.dtype, "fixed_dirs": args.fixed_dirs, "maps_per_step": len(jobs), "steps": args.steps,
                       "batched_maps_per_s": round(n / t_b, 1), "plain_maps_per_s": round(n / t_p, 1),
                       "batched_over_plain": round(t_p / t_b, 3), "ms_per_step_batched": round(t_b / args.steps * 1e3, 3),
                       "groups": dict(zip(sizes, ens.modes)), "lanes": ens.lanes,

@@ -8,11 +8,15 @@ warm-up realisation, then ``--reps`` launches of each kernel of the hot path thr
 cmbx_time_passes, and a device-to-device copy of exactly 512 MiB (torch) whose counter
 readings calibrate the HBM byte counters. With ``--slab``: instead, the benchmark's
 flat-box section (the 2-D method and the 3-D method on the flat N = 512, M = 32 box of a
-10-degree cap, h = 14 layers, nside-64 pixels), ``--reps`` maps of each. Usage:
+10-degree cap, h = 14 layers, nside-64 pixels), ``--reps`` maps of each. With
+``--ensemble``: the benchmark's four 512^3 boxes as its batched path runs them (chained on
+two lanes, directions fixed), ``--reps`` launches after two warm-up launches, for the
+time kernels of the two lanes share the chip (``trace_overlap``). Usage:
 
     rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2507_15703_amd.profile_run
     rocprofv3 --pmc FETCH_SIZE -d OUT -- python -m paper_2507_15703_amd.profile_run --reps 1
     rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2507_15703_amd.profile_run --slab
+    rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2507_15703_amd.profile_run --ensemble
 """
 import argparse
 import json
@@ -34,6 +38,7 @@ def main():
     ap.add_argument("--tile-y", type=int, default=None)
     ap.add_argument("--spectrum", default="lp", choices=["lp", "powerlaw"])
     ap.add_argument("--slab", action="store_true", help="the flat-box methods instead")
+    ap.add_argument("--ensemble", action="store_true", help="the benchmark's batched path instead")
     args = ap.parse_args()
 
     import torch
@@ -42,6 +47,26 @@ def main():
     if args.slab:
         import bench
         print(json.dumps(bench.slab_section(torch, cmbx, reps=args.reps)), flush=True)
+        return
+    if args.ensemble:
+        import bench
+        jobs = bench.build_jobs(torch, cmbx, workloads, 4)
+        ens = cmbx.Ensemble([dict(plan=j["plan"], seed=j["seed"], r=j["r"], dirs=j["dirs"], out=j["out"]) for j in jobs],
+                            mode="chained", lanes=2)
+        for _ in range(2):
+            ens.launch()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(args.reps):
+            ens.launch()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.reps
+        print(json.dumps({"boxes": len(jobs), "lanes": ens.lanes, "ms_per_launch": round(ms, 4),
+                          "maps_per_s": round(len(jobs) / ms * 1e3, 1)}), flush=True)
+        ens.close()
         return
 
     N = args.N
