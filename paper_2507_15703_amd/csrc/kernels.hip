@@ -618,14 +618,19 @@ __device__ __forceinline__ void stencil_origin(int N, double scale, double3 obs,
                                                double frac[3]) {
 #pragma clang fp contract(off)
   const double o[3] = {obs.x, obs.y, obs.z};
+  // the three components loaded together, before the branches below
+  const double n[3] = {dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    double p = (r * dirs[3 * i + d] + o[d]) * scale;
+    double p = (r * n[d] + o[d]) * scale;
     // any finite position is reduced modulo N; non-finite input samples node 0
     if (!(p > -1.0e9 && p < 1.0e9)) p = 0.0;
     const double fl = floor(p);
-    int base = (int)fl % N;
-    base = base < 0 ? base + N : base;
+    int base = (int)fl;
+    if ((unsigned)base >= (unsigned)N) {  // positions in the box need no reduction
+      base %= N;
+      base = base < 0 ? base + N : base;
+    }
     i0[d] = base - (K == 4 ? 1 : 0);
     frac[d] = p - fl;
   }
@@ -639,26 +644,32 @@ struct Taps {
 
 template <typename T, int K, bool CONTIGUOUS>
 __device__ __forceinline__ T stencil_sum(const T* __restrict__ field, int N, const int i0[3], const T (*w)[4]) {
-  int iz[K];
+  // element offsets in 32 bits (N^3 <= 2^30 for the largest compiled box, N = 1024): the
+  // line (a, b) starts at xo[a] + yo[b]
+  const uint32_t n = (uint32_t)N;
+  uint32_t xo[K], yo[K], zo[K];
 #pragma unroll
-  for (int c = 0; c < K; ++c) iz[c] = wrap(i0[2] + c, N);
+  for (int a = 0; a < K; ++a) xo[a] = (uint32_t)wrap(i0[0] + a, N) * (n * n);
+#pragma unroll
+  for (int b = 0; b < K; ++b) yo[b] = (uint32_t)wrap(i0[1] + b, N) * n;
+#pragma unroll
+  for (int c = 0; c < K; ++c) zo[c] = (uint32_t)wrap(i0[2] + c, N);
   // every tap is loaded before any is summed, so that the K x K line loads are in flight
   // together rather than one round trip after another
   T q[K][K][K];
 #pragma unroll
   for (int a = 0; a < K; ++a) {
-    const int ix = wrap(i0[0] + a, N);
 #pragma unroll
     for (int bb = 0; bb < K; ++bb) {
-      const int iy = wrap(i0[1] + bb, N);
-      const T* line = field + ((size_t)ix * N + iy) * N;
+      const uint32_t line = xo[a] + yo[bb];
       if constexpr (CONTIGUOUS) {
-        const typename Taps<T, K>::vec v = *reinterpret_cast<const typename Taps<T, K>::vec*>(line + i0[2]);
+        const typename Taps<T, K>::vec v =
+            *reinterpret_cast<const typename Taps<T, K>::vec*>(field + (line + (uint32_t)i0[2]));
 #pragma unroll
         for (int c = 0; c < K; ++c) q[a][bb][c] = v[c];
       } else {
 #pragma unroll
-        for (int c = 0; c < K; ++c) q[a][bb][c] = line[iz[c]];
+        for (int c = 0; c < K; ++c) q[a][bb][c] = field[line + zo[c]];
       }
     }
   }
