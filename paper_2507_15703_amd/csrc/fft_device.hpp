@@ -256,12 +256,45 @@ struct LdsIO {
   }
 };
 
+// LDS-resident lines (the line layout, not SEQFAST) with the elements of each aligned block
+// of 32 permuted within it: element n of line q at q L + (n ^ ((n >> 3) & 3) ^
+// (((n >> 5) & 7) << 2)) for lengths that are powers of two (a bijection on every aligned
+// block of 32), q L + n otherwise. A stage writes its outputs R positions apart (4j + r,
+// then 32 (j / 4) + j % 4 + 4 r, ...): in the natural layout 8 to 16 lanes of a wave then
+// share a bank, here two (the least a 64-lane write of 8 bytes each takes); the reads,
+// over consecutive j, stay at two. For 3 * 2^k the permutation helps none of the accesses
+// and is not used.
+template <typename T, int L, int NSEQ, bool LB = false>
+struct LdsXorLines {
+  static constexpr bool SW = (L & (L - 1)) == 0;
+  static constexpr int perm(int n) { return SW ? n ^ ((n >> 3) & 3) ^ (((n >> 5) & 7) << 2) : n; }
+  static constexpr bool bijective() {
+    bool seen[L] = {};
+    for (int n = 0; n < L; ++n) {
+      const int m = perm(n);
+      if (m < 0 || m >= L || seen[m]) return false;
+      seen[m] = true;
+    }
+    return true;
+  }
+  static_assert(bijective(), "the line permutation must map [0, L) onto itself");
+  __device__ static __forceinline__ int sw(int n) { return perm(n); }
+  __device__ static __forceinline__ int index(int q, int n) { return q * L + sw(n); }
+  cpx<T>* p;
+  __device__ __forceinline__ cpx<T> operator()(int q, int n) const { return p[index(q, n)]; }
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const { p[index(q, n)] = v; }
+  __device__ __forceinline__ void done() const {
+    if constexpr (LB) lds_barrier();
+    else __syncthreads();
+  }
+};
+
 // Run all stages of a length-L transform with stage plan P: stage 0 reads from `first`,
 // the last stage writes to `last`, stages in between go through the LDS sequences `lds`
-// (laid out as LdsIO<T, L, NSEQ, SEQFAST, P>; LB: their barriers are lds_barrier). `tid`
-// is the thread's index in the workgroup.
+// (laid out as Mid, by default LdsIO<T, L, NSEQ, SEQFAST, P>; LB: their barriers are
+// lds_barrier). `tid` is the thread's index in the workgroup.
 template <typename T, int L, int NSEQ, int NT, bool SEQFAST, int TWMUL, int S, class First, class Last, int P = 0,
-          bool LB = false>
+          bool LB = false, class Mid = LdsIO<T, L, NSEQ, SEQFAST, P, LB>>
 __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* lds, First& first, Last& last,
                                         int tid) {
   constexpr int NST = stage_count(L, P);
@@ -269,7 +302,7 @@ __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* l
   if constexpr (S < NST) {
     constexpr int R = stage_radix(L, S, P);
     constexpr int NS = stage_stride(L, S, P);
-    LdsIO<T, L, NSEQ, SEQFAST, P, LB> mid{lds};
+    Mid mid{lds};
     if constexpr (S == 0 && NST == 1) {
       fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, first, last, tid);
     } else if constexpr (S == 0) {
@@ -279,7 +312,7 @@ __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* l
     } else {
       fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, mid, tid);
     }
-    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1, First, Last, P, LB>(tw, lds, first, last, tid);
+    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1, First, Last, P, LB, Mid>(tw, lds, first, last, tid);
   }
 }
 

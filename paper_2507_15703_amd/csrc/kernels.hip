@@ -537,8 +537,8 @@ __device__ __forceinline__ bool z_stream_step(cpx<T>* cur, cpx<T>* nxt, const cp
   }
   HalfToComplexMasked<T, M, LINES, P> first{cur, tw, m_hi};
   KeptLinesIO<T, M, LINES> last{buf + (size_t)w.blk * LINES * M, keep, nullptr, zmask};
-  fft_run<T, M, LINES, NT, false, 2, 0, HalfToComplexMasked<T, M, LINES, P>, KeptLinesIO<T, M, LINES>, P, true>(
-      tw, cur, first, last, threadIdx.x);
+  fft_run<T, M, LINES, NT, false, 2, 0, HalfToComplexMasked<T, M, LINES, P>, KeptLinesIO<T, M, LINES>, P, true,
+          LdsXorLines<T, M, LINES, true>>(tw, cur, first, last, threadIdx.x);
   w = {en, w.blk1, blk2, fn};
   return more;
 }
