@@ -183,6 +183,58 @@ constexpr bool plan_ok(int L, int P = 0, int i = 0, int prod = 1) {
 // (column tiles, where the sequences are the contiguous dimension); otherwise consecutive
 // j within one sequence (line tiles). src(seq, n) / dst(seq, n, v) access element n of a
 // sequence. tw is the table of NTW-th roots exp(2 pi i m / NTW), NTW = L * TWMUL.
+template <int L, int NSEQ, int NT, int R>
+struct StageSlots {
+  static constexpr int J = L / R;
+  static constexpr int SLOTS = J * NSEQ;
+  static constexpr int PER = (SLOTS + NT - 1) / NT;
+  static constexpr bool FULL = (SLOTS % NT) == 0;
+};
+
+// The inputs of this thread's butterflies of a radix-R stage, v[q][r] = input r of slot
+// tid + q NT (the slot mapping of fft_stage).
+template <typename T, int L, int NSEQ, int NT, int R, bool SEQFAST, class Src>
+__device__ __forceinline__ void stage_inputs(Src& src, cpx<T> (&v)[StageSlots<L, NSEQ, NT, R>::PER][R], int tid) {
+  using SS = StageSlots<L, NSEQ, NT, R>;
+#pragma unroll
+  for (int q = 0; q < SS::PER; ++q) {
+    const int s = tid + q * NT;
+    if (SS::FULL || s < SS::SLOTS) {
+      const int seq = SEQFAST ? s % NSEQ : s / SS::J;
+      const int j = SEQFAST ? s / NSEQ : s % SS::J;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src(seq, j + r * SS::J);
+    }
+  }
+}
+
+// Twiddles, butterflies and outputs of a radix-R stage (stride NS) on inputs in registers.
+template <typename T, int L, int NSEQ, int NT, int R, int NS, bool SEQFAST, int TWMUL, class Dst>
+__device__ __forceinline__ void stage_outputs(const cpx<T>* __restrict__ tw,
+                                              cpx<T> (&v)[StageSlots<L, NSEQ, NT, R>::PER][R], Dst& dst, int tid) {
+  using SS = StageSlots<L, NSEQ, NT, R>;
+#pragma unroll
+  for (int q = 0; q < SS::PER; ++q) {
+    const int s = tid + q * NT;
+    if (SS::FULL || s < SS::SLOTS) {
+      const int seq = SEQFAST ? s % NSEQ : s / SS::J;
+      const int j = SEQFAST ? s / NSEQ : s % SS::J;
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * (L / (NS * R)) * TWMUL]);
+      }
+      Dft<T, R>::run(v[q]);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst(seq, base + r * NS, v[q][r]);
+    }
+  }
+  dst.done();
+}
+
+// (fft_stage keeps its own copy of the two halves: written through the helpers above, the
+// noise + x pass took a few more VALU instructions for its addresses)
 template <typename T, int L, int NSEQ, int NT, int R, int NS, bool SEQFAST, int TWMUL, class Src, class Dst>
 __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ tw, Src& src, Dst& dst, int tid) {
   constexpr int J = L / R;
@@ -313,6 +365,27 @@ __device__ __forceinline__ void fft_run(const cpx<T>* __restrict__ tw, cpx<T>* l
       fft_stage<T, L, NSEQ, NT, R, NS, SEQFAST, TWMUL>(tw, mid, mid, tid);
     }
     fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, S + 1, First, Last, P, LB, Mid>(tw, lds, first, last, tid);
+  }
+}
+
+// fft_run with the first stage's inputs already in registers (v, as stage_inputs loads
+// them for stage plan P): callers that load the next transform's inputs while this one
+// runs.
+template <typename T, int L, int NSEQ, int NT, bool SEQFAST, int TWMUL, class Last, int P = 0, bool LB = false,
+          class Mid = LdsIO<T, L, NSEQ, SEQFAST, P, LB>>
+__device__ __forceinline__ void fft_run_from_regs(const cpx<T>* __restrict__ tw, cpx<T>* lds,
+                                                  cpx<T> (&v)[StageSlots<L, NSEQ, NT, stage_radix(L, 0, P)>::PER]
+                                                            [stage_radix(L, 0, P)],
+                                                  Last& last, int tid) {
+  constexpr int NST = stage_count(L, P);
+  constexpr int R = stage_radix(L, 0, P);
+  static_assert(plan_ok(L, P), "unsupported transform length");
+  if constexpr (NST == 1) {
+    stage_outputs<T, L, NSEQ, NT, R, 1, SEQFAST, TWMUL>(tw, v, last, tid);
+  } else {
+    Mid mid{lds};
+    stage_outputs<T, L, NSEQ, NT, R, 1, SEQFAST, TWMUL>(tw, v, mid, tid);
+    fft_run<T, L, NSEQ, NT, SEQFAST, TWMUL, 1, Mid, Last, P, LB, Mid>(tw, lds, mid, last, tid);
   }
 }
 

@@ -422,6 +422,81 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __re
   }
 }
 
+// The y pass over a map footprint's list with the next pair's loads in flight: a resident
+// grid walks the (listed plane, tile within the support) pairs as k_pass_y does, and each
+// workgroup issues the first stage's loads of its next pair into registers before it
+// transforms the current one, whose inputs it loaded one turn earlier. Barriers inside
+// the walk wait for LDS only (a full barrier would also wait for those loads). Same
+// arithmetic and outputs as k_pass_y.
+template <typename T, int SHIFT>
+struct KeptRowsColLB {
+  KeptRowsColIO<T, SHIFT> io;
+  __device__ __forceinline__ void operator()(int q, int n, cpx<T> v) const { io(q, n, v); }
+  // the next pair's row flags overwrite `keep`: every wave past its last use
+  __device__ __forceinline__ void done() const { lds_barrier(); }
+};
+
+template <typename T, int N, int TZ, int P>
+struct YWalk {
+  static constexpr int NT = XYShape<T, N, TZ>::NT;
+  static constexpr int R0 = stage_radix(N, 0, P);
+  using Regs = cpx<T>[StageSlots<N, TZ, NT, R0>::PER][R0];
+};
+
+template <typename T, int N, int TZ, int P>
+__device__ __forceinline__ void y_walk_load(cpx<T>* __restrict__ buf, const uint32_t* plist, int tiles, int m_hi,
+                                            int e, typename YWalk<T, N, TZ, P>::Regs& v, int tid) {
+  constexpr int M = N / 2;
+  const int zt = e % tiles, ix = (int)plist[e / tiles];
+  SupportColIO<T, N> src{{buf + (size_t)ix * N * M + zt * TZ, (size_t)M}, zt * TZ, m_hi};
+  stage_inputs<T, N, TZ, YWalk<T, N, TZ, P>::NT, YWalk<T, N, TZ, P>::R0, true>(src, v, tid);
+}
+
+// One pair on `cur` (loaded by the previous turn) while the next pair loads into `nxt`;
+// false when the walk is over.
+template <typename T, int N, int TZ, int P>
+__device__ __forceinline__ bool y_walk_step(cpx<T>* smem, uint8_t* rows, cpx<T>* __restrict__ buf,
+                                            const uint8_t* __restrict__ fp, const uint32_t* plist, int tiles,
+                                            int count, int m_hi, int& e, typename YWalk<T, N, TZ, P>::Regs& cur,
+                                            typename YWalk<T, N, TZ, P>::Regs& nxt) {
+  constexpr int M = N / 2, NT = YWalk<T, N, TZ, P>::NT;
+  constexpr int NB = footprint_blocks(N);
+  const int tid = opaque_tid();
+  const int en = e + (int)gridDim.x;
+  if (en < count) y_walk_load<T, N, TZ, P>(buf, plist, tiles, m_hi, en, nxt, tid);
+  const int zt = e % tiles, ix = (int)plist[e / tiles];
+  for (int i = tid; i < NB; i += NT) rows[i] = fp[N + ix * NB + i];
+  lds_barrier();  // the row flags (and the twiddles) in every wave; the tile is free
+  KeptRowsColLB<T, 3> last{{{buf + (size_t)ix * N * M + zt * TZ, (size_t)M}, rows}};
+  fft_run_from_regs<T, N, TZ, NT, true, 1, KeptRowsColLB<T, 3>, P, true>(smem + N * TZ, smem, cur, last, tid);
+  e = en;
+  return en < count;
+}
+
+template <typename T, int N, int TZ, int P = 0>
+__global__ __launch_bounds__((XYShape<T, N, TZ>::NT), 4) void k_pass_y_walk(cpx<T>* __restrict__ buf,
+                                                                      const cpx<T>* __restrict__ twg, int m_hi,
+                                                                      const uint8_t* __restrict__ fp) {
+  constexpr int NT = XYShape<T, N, TZ>::NT;
+  constexpr int T_ = N / 2 / TZ;
+  __shared__ cpx<T> smem[N * TZ + N];
+  __shared__ uint8_t rows[footprint_blocks(N)];
+  const uint32_t* hdr = reinterpret_cast<const uint32_t*>(fp + footprint_list_offset(N));
+  const uint32_t* plist = hdr + kFootprintHeader + N * N;
+  int tiles = 0;
+  while (tiles < T_ && tiles * TZ * tiles * TZ <= m_hi) ++tiles;
+  const int count = (int)hdr[2] * tiles;
+  int e = blockIdx.x;
+  if (e >= count) return;
+  for (int i = threadIdx.x; i < N; i += NT) smem[N * TZ + i] = twg[i];
+  typename YWalk<T, N, TZ, P>::Regs a, b;
+  y_walk_load<T, N, TZ, P>(buf, plist, tiles, m_hi, e, a, threadIdx.x);
+  // two pairs per turn, so that each names its register sets statically
+  while (y_walk_step<T, N, TZ, P>(smem, rows, buf, fp, plist, tiles, count, m_hi, e, a, b) &&
+         y_walk_step<T, N, TZ, P>(smem, rows, buf, fp, plist, tiles, count, m_hi, e, b, a)) {
+  }
+}
+
 // Without a footprint one workgroup per block of LINES lines. With one, a grid of as many
 // workgroups as the device holds at once walks the footprint's list of blocks that hold
 // a read line (if the list was made for another block size, every block, each checked
@@ -965,6 +1040,17 @@ int resident_grid(K kernel, int threads) {
 template <typename T, int N, int TZ, int P = 0>
 hipError_t run_y(const FieldArgs& a, hipStream_t s) {
   constexpr int NWG = N / 2 / TZ * N;
+  if constexpr (P == 1) {
+    // stage plan 1 walks the list with the next pair's loads in flight (k_pass_y_walk), on
+    // as many workgroups as are resident; with stage plan 0 (which it would have to spill
+    // at N = 256 and 512) the autotuner compares it against k_pass_y's plain walk
+    if (a.fp) {
+      static const int resident = resident_grid(k_pass_y_walk<T, N, TZ, P>, XYShape<T, N, TZ>::NT);
+      hipLaunchKernelGGL((k_pass_y_walk<T, N, TZ, P>), dim3(resident), dim3(XYShape<T, N, TZ>::NT), 0, s,
+                         (cpx<T>*)a.buf, (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
+      return hipGetLastError();
+    }
+  }
   const dim3 grid = a.fp ? dim3(NWG > kZGrid ? kZGrid : NWG) : dim3(N / 2 / TZ, N);
   hipLaunchKernelGGL((k_pass_y<T, N, TZ, P>), grid, dim3(XYShape<T, N, TZ>::NT), 0, s, (cpx<T>*)a.buf,
                      (const cpx<T>*)a.tw, a.m_hi, (const uint8_t*)a.fp);
