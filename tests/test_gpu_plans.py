@@ -94,3 +94,28 @@ def test_autotune_records_plans(cmbx, tmp_path):
     again = p.autotune(reps=2, cache_path=cache)
     assert again["cached"] and again["plans"] == t["plans"]
     p.close()
+
+
+def test_prefetching_y_walk_over_several_turns(cmbx):
+    """Stage plan 1 of pass y walks the footprint's (plane, tile) list on the resident grid,
+    each workgroup loading its next pair while it transforms the current one. At 256^3 with
+    a 60-degree cap the list (about 200 planes x 8 tiles) is longer than the grid (about
+    1024 workgroups), so workgroups take more than one turn: the map still matches the
+    oracle, and the plain walk (plan 0) to the same bar."""
+    N = 256
+    k, pk = workloads.powerlaw_cutoff_table(N, 1.0, kc_modes=N // 4)
+    dirs_np = workloads.cap_directions(60.0, 48, 128)
+    dirs = torch.tensor(dirs_np, device="cuda")
+    mref = ogather.gather(ofield.field(onoise.halfgrid(N, 1.0, 21, k, pk)), 1.0, 0.45, dirs_np, "tricubic")
+    p = cmbx.Plan(N, 1.0, "f32", interp="tricubic")
+    p.spectrum_table(k, pk)
+    planes = int(np.count_nonzero(p.debug_footprint(0.45, dirs)[0]))
+    assert planes * (N // 2 // 16) > 1024, planes
+    maps = {}
+    for yplan in (1, 0):
+        p.set_tiles(0, 0, plans=(0, yplan, 0))
+        assert p.shapes()[3][1] == yplan
+        maps[yplan] = p.simulate_patch(21, 0.45, dirs).cpu().numpy()[0]
+        assert _rel(maps[yplan], mref) <= TOL["f32"], yplan
+    assert _rel(maps[1], maps[0]) <= TOL["f32"]
+    p.close()
