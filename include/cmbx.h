@@ -358,7 +358,18 @@ typedef struct cmbx_slab cmbx_slab;
  * compiled), CMBX_ENOMEM, CMBX_EHIP. */
 int cmbx_slab_create(int method, int N, int M, int h, double dp, int dtype, int batch, cmbx_slab** out);
 int cmbx_slab_destroy(cmbx_slab* slab);
-/* CMBX_OPT_INTERP and CMBX_OPT_STREAM as for plans; CMBX_EINVAL otherwise. */
+/* CMBX_OPT_INTERP and CMBX_OPT_STREAM as for plans, and CMBX_SLAB_OPT_DIRECT: how a map's
+ * values are taken from the layers. After the transform along x, each (layer, x) line holds
+ * its half spectrum along y, and the value at row y is that line's inverse DFT at y; with
+ * CMBX_SLAB_DIRECT_ALWAYS every stencil row is summed directly from it (N/2 terms, the
+ * plan's twiddles) instead of running the complex-to-real pass over every line and then
+ * the gather; CMBX_SLAB_DIRECT_NEVER always runs the pass; CMBX_SLAB_DIRECT_AUTO (default)
+ * sums directly while n_pix K^2 N/2 <= 2 nz N^2 (K = 4 tricubic, 2 trilinear). The maps
+ * agree to rounding. CMBX_EINVAL for other keys or values. */
+#define CMBX_SLAB_OPT_DIRECT    12
+#define CMBX_SLAB_DIRECT_AUTO   0
+#define CMBX_SLAB_DIRECT_NEVER  1
+#define CMBX_SLAB_DIRECT_ALWAYS 2
 int cmbx_slab_set(cmbx_slab* slab, int key, int64_t value);
 /* Observer position o in box coordinates (the length unit of dp and r); CMBX_EINVAL if not
  * finite. Sec. II D 2 centres the h layers on the cap: o_z = (h - 1) dp / 2 - r (1 + z_min) / 2. */
@@ -374,7 +385,8 @@ int cmbx_slab_cap_observer(const cmbx_slab* slab, double r, double z_min, double
 int cmbx_slab_spectrum(cmbx_slab* slab, const double* k, const double* P_inf, int64_t n);
 /* Maps of the batch (realisation b uses seed + b) at the pixels: dirs device FP64
  * [n_pix][3], out device [batch][n_pix] of the plan precision; asynchronous on the
- * slab's stream; the layers of the last realisation stay in the workspace. Errors:
+ * slab's stream; the layers of the last realisation stay in the workspace (transformed
+ * along x only, complex [nz][N][N/2], when the map was summed directly). Errors:
  * CMBX_ESTATE (no spectrum), CMBX_EINVAL (r <= 0 or not finite, n_pix, NULL), CMBX_EHIP. */
 int cmbx_slab_simulate(cmbx_slab* slab, uint64_t seed, double r, const double* dirs, int64_t n_pix, void* out);
 /* Tests: the layers of realisation `seed`, real [nz][N][N] (device, plan precision); the

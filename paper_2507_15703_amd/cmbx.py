@@ -23,6 +23,8 @@ SLAB_FLAT, SLAB_HYBRID = 1, 2
 ENS_ONE_LANE, ENS_TWO_LANES, ENS_MAX_LANES = 0x100, 0x200, 4
 OPT_INTERP, OPT_STREAM, OPT_TILE_XY, OPT_LINES_Z, OPT_TILE_X, OPT_TILE_Y, OPT_PRUNE, OPT_FIXED_DIRS = 1, 2, 3, 4, 5, 6, 7, 8
 OPT_PLAN_X, OPT_PLAN_Y, OPT_PLAN_Z = 9, 10, 11
+SLAB_OPT_DIRECT = 12
+_DIRECT = {"auto": 0, "never": 1, "always": 2}
 
 _DTYPES = {"f32": F32, "float32": F32, F32: F32, "f64": F64, "float64": F64, F64: F64}
 _INTERPS = {"trilinear": TRILINEAR, "tricubic": TRICUBIC, TRILINEAR: TRILINEAR, TRICUBIC: TRICUBIC}
@@ -668,6 +670,13 @@ class Slab:
     def set_interp(self, interp):
         self.interp = _INTERPS[interp]
         _check(lib().cmbx_slab_set(self.handle, OPT_INTERP, self.interp))
+
+    def set_direct(self, mode):
+        """How maps take their values from the layers: "always" sums each stencil row
+        directly from its line's half spectrum after the transform along x, "never" runs
+        the complex-to-real pass and the gather, "auto" (default) sums directly for few
+        pixels (CMBX_SLAB_OPT_DIRECT)."""
+        _check(lib().cmbx_slab_set(self.handle, SLAB_OPT_DIRECT, _DIRECT[mode]))
 
     def set_observer(self, position):
         x, y, z = (float(v) for v in position)

@@ -370,6 +370,132 @@ __global__ __launch_bounds__(256) void k_slab_gather(const T* __restrict__ field
   out[i] = acc;
 }
 
+// ------------------------------------------------------------------ direct gather
+// The gather for few pixels without the layers' last transform: after the transform
+// along x, line (z, x) of a layer holds the half spectrum along y, X_0 .. X_{N/2-1}
+// (X_0 = a + i b packs the real X_0 = a and X_{N/2} = b), and the layer's value at y is its
+// inverse DFT a + (-1)^y b + 2 sum_{k=1}^{N/2-1} (Re X_k cos(2 pi k y / N) - Im X_k sin(2 pi
+// k y / N)) -- what the complex-to-real pass computes for every y, evaluated here only at
+// the stencil's K rows (an output-pruned transform; the twiddles are the plan's N roots).
+// Workgroup = one pixel, K waves; wave a takes the stencil's line x = i0x + a at each of the
+// K layers: lane l takes the terms k = l, l + 64, ... (all its loads, line values and
+// twiddles, issued before the first product), weights its K x K partial row sums by the y
+// and z weights, and the wave's lanes are summed by shuffles; the waves' K sums are then
+// weighted along x. The same weighted sum as k_slab_gather, in another order.
+template <typename T, int K, int TMAX>
+__global__ __launch_bounds__(64 * K) void k_slab_direct(const cpx<T>* __restrict__ layers, const cpx<T>* __restrict__ tw,
+                                                         int N, int nz, int periodic, double scale, double3 obs, double r,
+                                                         const double* __restrict__ dirs, int64_t npix, T* __restrict__ out) {
+#pragma clang fp contract(off)
+  // TMAX: terms per lane, 64 TMAX >= N / 2
+  const int64_t i = blockIdx.x;
+  if (i >= npix) return;
+  __shared__ T part[K];  // the y- and z-weighted sum of the stencil's line x = i0x + a
+  const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
+  const double o[3] = {obs.x, obs.y, obs.z};
+  const double n[3] = {dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
+  int i0[3];
+  T w[3][4];
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double p = (r * n[d] + o[d]) * scale;
+    if (!(p > -1.0e9 && p < 1.0e9)) p = 0.0;
+    const double fl = floor(p);
+    const int m = d < 2 ? N : nz;
+    if (d < 2 || periodic) {
+      int base = (int)fl % m;
+      base = base < 0 ? base + m : base;
+      i0[d] = base - (K == 4 ? 1 : 0);
+    } else {
+      i0[d] = (int)fl - (K == 4 ? 1 : 0);
+      inside = i0[d] >= 0 && i0[d] + K <= nz;
+    }
+    keys_or_linear<T>((T)(p - fl), w[d], K == 4);
+  }
+  if (!inside) {  // uniform over the workgroup
+    if (threadIdx.x == 0) out[i] = __builtin_nan("");
+    return;
+  }
+  const int M = N / 2;
+  const int x = wrapn(i0[0] + a, N);
+  int y[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) y[b] = wrapn(i0[1] + b, N);
+  const cpx<T>* line[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const int z = periodic ? wrapn(i0[2] + c, nz) : i0[2] + c;
+    line[c] = layers + ((size_t)z * N + x) * M;
+  }
+  // every load first: the lane's terms of the K lines and their twiddles w^(k y_b)
+  cpx<T> X[TMAX][K], e[TMAX][K];
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    const int k = lane + 64 * t;
+    if (k < M) {
+#pragma unroll
+      for (int c = 0; c < K; ++c) X[t][c] = line[c][k];
+#pragma unroll
+      for (int b = 0; b < K; ++b) e[t][b] = tw[(k * y[b]) % N];
+    }
+  }
+  T q = T(0);
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    T sc = T(0);
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+      T acc = T(0);
+#pragma unroll
+      for (int t = 0; t < TMAX; ++t) {
+        const int k = lane + 64 * t;
+        if (k < M && k > 0) acc += X[t][c].x * e[t][b].x - X[t][c].y * e[t][b].y;
+      }
+      sc += w[1][b] * acc;
+    }
+    q += w[2][c] * sc;
+  }
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+  if (lane == 0) {
+    // the terms k = 0 and N/2, packed in column 0: a + (-1)^y b
+    T q0 = T(0);
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const cpx<T> X0 = line[c][0];
+      T sc = T(0);
+#pragma unroll
+      for (int b = 0; b < K; ++b) sc += w[1][b] * (X0.x + ((y[b] & 1) ? -X0.y : X0.y));
+      q0 += w[2][c] * sc;
+    }
+    part[a] = q0 + T(2) * q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T acc = T(0);
+#pragma unroll
+    for (int aa = 0; aa < K; ++aa) acc += w[0][aa] * part[aa];
+    out[i] = acc;
+  }
+}
+
+template <typename T, int K>
+hipError_t run_slab_direct_k(const SlabGatherArgs& a, const void* tw, hipStream_t s) {
+  const int M = a.N / 2;
+  auto k = M <= 64 ? k_slab_direct<T, K, 1> : M <= 128 ? k_slab_direct<T, K, 2> : M <= 256 ? k_slab_direct<T, K, 4>
+                                                                                             : k_slab_direct<T, K, 8>;
+  hipLaunchKernelGGL(k, dim3((unsigned)a.n_pix), dim3(64 * K), 0, s, (const cpx<T>*)a.field, (const cpx<T>*)tw, a.N,
+                     a.nz, a.periodic_z, a.scale, make_double3(a.obs[0], a.obs[1], a.obs[2]), a.r, a.dirs, a.n_pix,
+                     (T*)a.out);
+  return hipGetLastError();
+}
+
+hipError_t run_slab_direct(const SlabGatherArgs& a, const void* tw, hipStream_t s) {
+  const bool cubic = a.interp == 2;
+  if (a.dtype == 1) return cubic ? run_slab_direct_k<float, 4>(a, tw, s) : run_slab_direct_k<float, 2>(a, tw, s);
+  return cubic ? run_slab_direct_k<double, 4>(a, tw, s) : run_slab_direct_k<double, 2>(a, tw, s);
+}
+
 // ------------------------------------------------------------------ dispatch
 template <typename T, int MZ>
 constexpr int flat_cols() {
@@ -472,6 +598,10 @@ hipError_t launch_slab_gather(const SlabGatherArgs& a, hipStream_t s) {
                        a.dirs, a.n_pix, (double*)a.out);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_slab_direct(const SlabGatherArgs& a, const void* tw, hipStream_t s) {
+  return run_slab_direct(a, tw, s);
 }
 
 }  // namespace cmbx

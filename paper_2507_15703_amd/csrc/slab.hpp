@@ -48,5 +48,10 @@ struct SlabGatherArgs {
   void* out;
 };
 hipError_t launch_slab_gather(const SlabGatherArgs& a, hipStream_t s);
+// The same map from the layers after the transform along x only (complex [nz][N][N/2],
+// packed column 0), each stencil row's value evaluated directly from its line's half
+// spectrum with the N roots tw: for maps of few pixels, in place of the complex-to-real
+// pass and the gather.
+hipError_t launch_slab_direct(const SlabGatherArgs& a, const void* tw, hipStream_t s);
 
 }  // namespace cmbx

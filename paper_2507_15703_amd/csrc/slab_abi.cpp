@@ -22,6 +22,7 @@ struct cmbx_slab {
   double dp = 0;
   int dtype = 0, batch = 0, device = 0;
   int interp = CMBX_TRILINEAR;
+  int direct = CMBX_SLAB_DIRECT_AUTO;
   double obs[3] = {0, 0, 0};
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
@@ -185,18 +186,29 @@ int noise_table(const cmbx_slab* p, const float** bm) {
   return CMBX_OK;
 }
 
-// The layers of one realisation into buf.
-int enqueue_layers(const cmbx_slab* p, uint64_t seed, void* buf, hipStream_t s) {
+// The layers of one realisation into buf: the columns and the transform along x, then
+// (unless `half`) the complex-to-real transform along y.
+int enqueue_layers(const cmbx_slab* p, uint64_t seed, void* buf, hipStream_t s, bool half = false) {
   const float* bm = nullptr;
   if (int rc = noise_table(p, &bm)) return rc;
   HIP_TRY(cmbx::launch_slab_columns(columns_args(p, seed, buf, bm), s));
   HIP_TRY(cmbx::launch_layers_c2c(p->dtype, p->N, buf, p->tw, p->nz, s));
-  HIP_TRY(cmbx::launch_layers_c2r(p->dtype, p->N, buf, p->tw, p->nz, s));
+  if (!half) HIP_TRY(cmbx::launch_layers_c2r(p->dtype, p->N, buf, p->tw, p->nz, s));
   return CMBX_OK;
 }
 
+// Whether a map of n_pix pixels evaluates its stencils' rows directly from the layers'
+// half spectra: the direct sums take K^2 N/2 terms per pixel, the complex-to-real pass and
+// the gather about nz N^2 operations and two launches' latency; the direct way is taken
+// while its terms stay below 2 nz N^2.
+bool use_direct(const cmbx_slab* p, int64_t n_pix) {
+  if (p->direct != CMBX_SLAB_DIRECT_AUTO) return p->direct == CMBX_SLAB_DIRECT_ALWAYS;
+  const int64_t K = p->interp == CMBX_TRICUBIC ? 4 : 2;
+  return n_pix * K * K * (p->N / 2) <= 2 * (int64_t)p->nz * p->N * p->N;
+}
+
 int enqueue_gather(const cmbx_slab* p, const void* layers, double r, const double* dirs, int64_t n_pix, void* out,
-                   hipStream_t s) {
+                   hipStream_t s, bool direct = false) {
   cmbx::SlabGatherArgs g{};
   g.dtype = p->dtype;
   g.interp = p->interp;
@@ -210,7 +222,8 @@ int enqueue_gather(const cmbx_slab* p, const void* layers, double r, const doubl
   g.dirs = dirs;
   g.n_pix = n_pix;
   g.out = out;
-  HIP_TRY(cmbx::launch_slab_gather(g, s));
+  if (direct) HIP_TRY(cmbx::launch_slab_direct(g, p->tw, s));
+  else HIP_TRY(cmbx::launch_slab_gather(g, s));
   return CMBX_OK;
 }
 
@@ -300,6 +313,11 @@ int cmbx_slab_set(cmbx_slab* p, int key, int64_t value) {
       return ok();
     case CMBX_OPT_STREAM:
       p->stream = value == -1 ? p->own_stream : (hipStream_t)(intptr_t)value;
+      return ok();
+    case CMBX_SLAB_OPT_DIRECT:
+      if (value != CMBX_SLAB_DIRECT_AUTO && value != CMBX_SLAB_DIRECT_NEVER && value != CMBX_SLAB_DIRECT_ALWAYS)
+        return fail(CMBX_EINVAL, "unknown direct-evaluation mode %lld", (long long)value);
+      p->direct = (int)value;
       return ok();
     default:
       return fail(CMBX_EINVAL, "option %d does not apply to slabs", key);
@@ -393,10 +411,12 @@ int cmbx_slab_simulate(cmbx_slab* p, uint64_t seed, double r, const double* dirs
   if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(CMBX_EINVAL, "n_pix = %lld out of range", (long long)n_pix);
   if (!dirs || !out) return fail(CMBX_EINVAL, "dirs and out must be non-NULL device pointers");
   DeviceGuard g(p->device);
+  const bool direct = use_direct(p, n_pix);
   for (int b = 0; b < p->batch; ++b) {
     char* buf = (char*)p->field + (size_t)b * p->layers_bytes();
-    if (int rc = enqueue_layers(p, seed + (uint64_t)b, buf, p->stream)) return rc;
-    if (int rc = enqueue_gather(p, buf, r, dirs, n_pix, (char*)out + (size_t)b * n_pix * p->real_size(), p->stream))
+    if (int rc = enqueue_layers(p, seed + (uint64_t)b, buf, p->stream, direct)) return rc;
+    if (int rc = enqueue_gather(p, buf, r, dirs, n_pix, (char*)out + (size_t)b * n_pix * p->real_size(), p->stream,
+                                direct))
       return rc;
   }
   return ok();

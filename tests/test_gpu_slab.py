@@ -79,14 +79,18 @@ def test_flat_layers(cmbx, N, M, dt, tol):
     s.close()
 
 
+@pytest.mark.parametrize("direct", ["never", "always"])
 @pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f64", 1e-12)])
 @pytest.mark.parametrize("interp", ["trilinear", "tricubic"])
-def test_flat_maps(cmbx, dt, tol, interp):
+def test_flat_maps(cmbx, dt, tol, interp, direct):
     """A 15-degree cap on the unit sphere in a 96 x 96 x 24 box centred on the cap
-    (Sec. II D 1, Fig. 2a), batch of two; z wraps modulo M."""
+    (Sec. II D 1, Fig. 2a), batch of two; z wraps modulo M. The map's rows are taken from
+    the complex-to-real pass ("never") or summed directly from the lines' half spectra
+    ("always")."""
     N, M, dp, r = 96, 24, 0.0064, 1.0
     k, p = _gauss(dp, 2.5)
     s = cmbx.Slab("flat", N, M, dp, dtype=dt, batch=2, interp=interp)
+    s.set_direct(direct)
     s.spectrum(k, p)
     z_min = math.cos(math.radians(15.0))
     obs = s.observer_for_cap(r, z_min)
@@ -141,15 +145,18 @@ def test_hybrid_columns_and_layers(cmbx, dt, tol):
     s.close()
 
 
+@pytest.mark.parametrize("direct", ["never", "always"])
 @pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f64", 1e-11)])
 @pytest.mark.parametrize("interp", ["trilinear", "tricubic"])
-def test_hybrid_maps_on_a_cap(cmbx, dt, tol, interp):
+def test_hybrid_maps_on_a_cap(cmbx, dt, tol, interp, direct):
     """A 10-degree cap of the unit sphere sampled from h = 6 layers of a 64 x 64 x 16 box,
     the layers centred on the cap (Sec. II D 2, Fig. 2b); pixels below the cap, whose
-    stencils leave the layers, are NaN on both sides."""
+    stencils leave the layers, are NaN on both sides; rows from the complex-to-real pass
+    or summed directly."""
     N, M, h, dp, r = 64, 16, 6, 0.011, 1.0
     k, p = _gauss(dp, 6.0)
     s = cmbx.Slab("hybrid", N, M, dp, h=h, dtype=dt, batch=2, interp=interp)
+    s.set_direct(direct)
     s.spectrum(k, p)
     z_min = math.cos(math.radians(10.0))
     obs = s.observer_for_cap(r, z_min)
@@ -205,4 +212,7 @@ def test_slab_errors(cmbx):
     with pytest.raises(cmbx.CmbxError) as e:
         s.simulate(0, 0.3, d)
     assert e.value.code == cmbx.ESTATE
+    with pytest.raises(cmbx.CmbxError) as e:                  # no such evaluation mode
+        cmbx._check(cmbx.lib().cmbx_slab_set(s.handle, cmbx.SLAB_OPT_DIRECT, 3))
+    assert e.value.code == cmbx.EINVAL
     s.close()
