@@ -321,9 +321,11 @@ def main():
     # map reads (the stencils' footprint) moves -- pass x writes the x-lines within the
     # support, rows of the planes read; pass y reads those and writes the columns within
     # the support of the lines read; pass z reads those and writes the z nodes read of the
-    # lines read; the gather reads the directions (24 B) and writes the map (4 B) per pixel
+    # lines read; with the directions fixed the gather reads each pixel's record in the
+    # pixel order (16 B: stencil node and fractions) and its index (4 B) and writes the
+    # map (4 B)
     kbytes = [int(field_bytes * y_rows * planes), int(field_bytes * (y_rows * planes + z_cols * lines)),
-              int(field_bytes * (z_cols + zband) * lines), 28 * j0["n_pix"]]
+              int(field_bytes * (z_cols + zband) * lines), 24 * j0["n_pix"]]
     names = ["pass_x_noise", "pass_y", "pass_z_c2r", "gather_tricubic"]
     kernels = {n: {"ms": round(t, 4), "alg_bytes": b, "GBps": round(b / (t * 1e-3) / 1e9, 1)}
                for n, t, b in zip(names, ms, kbytes)}

@@ -74,9 +74,16 @@ extern "C" {
  * maps of one cap, Sec. IV). A pruning plan then makes the map footprint once per
  * (r, dirs, n_pix, interpolant, z tile, observer) and reuses it in later
  * cmbx_simulate_patch calls, and an ensemble created from it makes its footprints once at
- * creation instead of inside its graph at every launch. Setting the option (again, to 0
- * or 1) drops the kept footprint: do so after writing new directions at the same address.
- * Default 0: the footprint is made from the directions at every call. */
+ * creation instead of inside its graph at every launch. Any plan with the option also
+ * sorts the pixels once per (r, dirs, n_pix, interpolant, observer) by the Morton code of
+ * their stencils' first node and gathers in that order (neighbouring threads read the same
+ * field lines; each pixel's value is the same bit for bit, and out keeps the caller's
+ * order): cmbx_simulate_patch and cmbx_time_passes keep the order in the plan (not made
+ * while the plan's stream is being captured: the gather then reads the directions), an
+ * ensemble makes one per realisation at creation for its chained gathers. Setting the
+ * option (again, to 0 or 1) drops the kept footprint and order: do so after writing new
+ * directions at the same address. Default 0: the footprint is made from the directions at
+ * every call and the gather reads them in the caller's order. */
 #define CMBX_OPT_FIXED_DIRS 8
 /* FFT stage plan of the x, y and z pass: 0 (default) or 1, an alternative factorisation of
  * the transform length into radix stages (e.g. 512 = 16 x 8 x 4 instead of 8 x 8 x 8,
@@ -272,7 +279,8 @@ int cmbx_debug_gather(cmbx_plan* plan, const void* field, double r, const double
  * untimed one runs), and ms[i] receives the average duration in milliseconds of kernel
  * i: ms[0] pass x (noise + x transform), ms[1] pass y, ms[2] pass z (complex-to-real),
  * ms[3] gather into out[0 .. n_pix). The passes run as in cmbx_simulate_patch: if the
- * plan prunes, the map footprint is made first (not timed). The y and z passes work in
+ * plan prunes, the map footprint is made first, and with CMBX_OPT_FIXED_DIRS the pixel
+ * order (neither timed). The y and z passes work in
  * place, so their repeated launches touch the same memory as one launch but leave no
  * realisation behind: simulate again before using the workspace or out. Synchronises the
  * plan's stream. Errors: as cmbx_simulate_patch, CMBX_EINVAL for reps < 1 or ms == NULL.

@@ -17,7 +17,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libcmbx.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["kernels.hip", "slab.hip", "mlp.hip", "healpix.hip", "covariance.hip", "linalg.hip", "abi.cpp", "slab_abi.cpp"]
+SOURCES = ["kernels.hip", "pixel_order.hip", "slab.hip", "mlp.hip", "healpix.hip", "covariance.hip", "linalg.hip", "abi.cpp", "slab_abi.cpp"]
 ARCH = "gfx950"
 
 

@@ -45,15 +45,24 @@ struct cmbx_plan {
   void* fp = nullptr;      // map footprint of the last simulate_patch call
   bool prune = true;       // maps make only the part of the field their stencils read
   bool fixed_dirs = false; // the caller keeps the directions at a given address unchanged
-  // what fp was last made from (reused while fixed_dirs holds and every key is the same)
-  struct {
+  // what fp (or ord) was last made from (reused while fixed_dirs holds and every key is
+  // the same)
+  struct PixKey {
     bool valid = false;
     double r = 0;
     const double* dirs = nullptr;
     int64_t n_pix = 0;
     int lines = 0, interp = 0;
     double obs[3] = {0, 0, 0};
-  } fp_key;
+  };
+  PixKey fp_key;
+  // with fixed directions, the gather's pixel order (made once per key; room for
+  // ord_cap pixels) and the work space it is sorted in
+  void* ord = nullptr;
+  int64_t ord_cap = 0;
+  void* ord_scratch = nullptr;
+  size_t ord_scratch_bytes = 0;
+  PixKey ord_key;
   bool has_spectrum = false;
   size_t real_size() const { return dtype == CMBX_F32 ? 4 : 8; }
   size_t field_bytes() const { return (size_t)N * N * N * real_size(); }
@@ -69,7 +78,8 @@ struct cmbx_ensemble {
   std::vector<hipEvent_t> done;
   hipEvent_t fork = nullptr;
   std::vector<void*> dev;  // rotating workspaces and the schedule
-  std::vector<void*> fps;  // one map footprint per realisation whose plan prunes
+  std::vector<void*> fps;  // one map footprint per realisation whose plan prunes, and one
+                           // pixel order per realisation whose plan fixes the directions
   std::vector<int> modes;  // execution mode chosen per (precision, N) group
   // support bound each plan had when its kernels were captured (they skip what lies beyond)
   std::vector<std::pair<const cmbx_plan*, int>> bounds;
@@ -273,8 +283,9 @@ int check_radius(const cmbx_plan* p, double r) {
 }
 
 int enqueue_gather(const cmbx_plan* p, const void* field, double r, const double* dirs, int64_t n_pix, void* out,
-                   hipStream_t s) {
+                   hipStream_t s, const void* order = nullptr) {
   cmbx::GatherArgs g{};
+  g.order = order;
   g.dtype = p->dtype;
   g.interp = p->interp;
   g.N = p->N;
@@ -307,6 +318,82 @@ int enqueue_footprint(const cmbx_plan* p, void* fp, double r, const double* dirs
   return CMBX_OK;
 }
 
+// The gather's pixel order of (r, dirs) in `order` (pixel_order_bytes), sorted in
+// `scratch` (pixel_order_scratch_bytes bytes).
+int enqueue_pixel_order(const cmbx_plan* p, void* order, void* scratch, size_t scratch_bytes, double r,
+                        const double* dirs, int64_t n_pix, hipStream_t s) {
+  cmbx::PixelOrderArgs a{};
+  a.dtype = p->dtype;
+  a.interp = p->interp;
+  a.N = p->N;
+  a.scale = (double)p->N / p->L;
+  for (int d = 0; d < 3; ++d) a.obs[d] = p->obs[d];
+  a.r = r;
+  a.dirs = dirs;
+  a.n_pix = n_pix;
+  a.order = order;
+  a.scratch = scratch;
+  a.scratch_bytes = scratch_bytes;
+  HIP_TRY(cmbx::launch_pixel_order(a, s));
+  return CMBX_OK;
+}
+
+cmbx_plan::PixKey pix_key(const cmbx_plan* p, double r, const double* dirs, int64_t n_pix, int lines) {
+  cmbx_plan::PixKey k;
+  k.valid = true;
+  k.r = r;
+  k.dirs = dirs;
+  k.n_pix = n_pix;
+  k.lines = lines;
+  k.interp = p->interp;
+  for (int d = 0; d < 3; ++d) k.obs[d] = p->obs[d];
+  return k;
+}
+
+bool same_key(const cmbx_plan::PixKey& a, const cmbx_plan::PixKey& b) {
+  return a.valid && b.valid && a.r == b.r && a.dirs == b.dirs && a.n_pix == b.n_pix && a.lines == b.lines &&
+         a.interp == b.interp && a.obs[0] == b.obs[0] && a.obs[1] == b.obs[1] && a.obs[2] == b.obs[2];
+}
+
+// With fixed directions: the plan's pixel order of (r, dirs), made on stream s if the key
+// changed, and returned (NULL without fixed directions, or when s is being captured and
+// the order would have to be made: the gather then reads the directions).
+int plan_pixel_order(cmbx_plan* p, double r, const double* dirs, int64_t n_pix, hipStream_t s, const void** out) {
+  *out = nullptr;
+  if (!p->fixed_dirs) return CMBX_OK;
+  const cmbx_plan::PixKey k = pix_key(p, r, dirs, n_pix, 0);
+  if (!same_key(p->ord_key, k)) {
+    p->ord_key.valid = false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return CMBX_OK;
+    size_t sb = 0;
+    HIP_TRY(cmbx::pixel_order_scratch_bytes(p->N, n_pix, &sb));
+    if (n_pix > p->ord_cap) {
+      if (p->ord) HIP_TRY(hipFree(p->ord));
+      p->ord = nullptr;
+      p->ord_cap = 0;
+      const hipError_t e = hipMalloc(&p->ord, cmbx::pixel_order_bytes(p->dtype, n_pix));
+      if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "pixel order: %s",
+                                       hipGetErrorString(e));
+      p->ord_cap = n_pix;
+    }
+    if (sb > p->ord_scratch_bytes) {
+      if (p->ord_scratch) HIP_TRY(hipFree(p->ord_scratch));
+      p->ord_scratch = nullptr;
+      p->ord_scratch_bytes = 0;
+      const hipError_t e = hipMalloc(&p->ord_scratch, sb);
+      if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "pixel order: %s",
+                                       hipGetErrorString(e));
+      p->ord_scratch_bytes = sb;
+    }
+    if (int rc = enqueue_pixel_order(p, p->ord, p->ord_scratch, p->ord_scratch_bytes, r, dirs, n_pix, s)) return rc;
+    p->ord_key = k;
+  }
+  *out = p->ord;
+  return CMBX_OK;
+}
+
 int check_patch_args(const cmbx_plan* p, double r, const double* dirs, int64_t n_pix, const void* out) {
   if (!p->has_spectrum) return fail(CMBX_ESTATE, "no spectrum set: call cmbx_spectrum_table first");
   if (int rc = check_radius(p, r)) return rc;
@@ -333,11 +420,13 @@ int enqueue_patch(cmbx_plan* p, uint64_t seed, double r, const double* dirs, int
       k = {p->fixed_dirs, r, dirs, n_pix, lines, p->interp, {p->obs[0], p->obs[1], p->obs[2]}};
     }
   }
+  const void* order = nullptr;
+  if (int rc = plan_pixel_order(p, r, dirs, n_pix, s, &order)) return rc;
   for (int b = 0; b < p->batch; ++b) {
     char* buf = (char*)p->field + (size_t)b * p->field_bytes();
     int rc = enqueue_field(p, seed + (uint64_t)b, buf, s, p->prune ? p->fp : nullptr);
     if (rc) return rc;
-    rc = enqueue_gather(p, buf, r, dirs, n_pix, (char*)out + (size_t)b * n_pix * p->real_size(), s);
+    rc = enqueue_gather(p, buf, r, dirs, n_pix, (char*)out + (size_t)b * n_pix * p->real_size(), s, order);
     if (rc) return rc;
   }
   return CMBX_OK;
@@ -407,6 +496,8 @@ int cmbx_plan_destroy(cmbx_plan* p) {
   if (p->tw) (void)hipFree(p->tw);
   if (p->wtab) (void)hipFree(p->wtab);
   if (p->fp) (void)hipFree(p->fp);
+  if (p->ord) (void)hipFree(p->ord);
+  if (p->ord_scratch) (void)hipFree(p->ord_scratch);
   if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
   delete p;
   return ok();
@@ -450,6 +541,7 @@ int cmbx_plan_set(cmbx_plan* p, int key, int64_t value) {
       if (value != 0 && value != 1) return fail(CMBX_EINVAL, "fixed_dirs = %lld must be 0 or 1", (long long)value);
       p->fixed_dirs = value == 1;
       p->fp_key.valid = false;  // setting it (again) makes the next call rebuild the footprint
+      p->ord_key.valid = false;  // and the pixel order
       return ok();
     case CMBX_OPT_STREAM:
       p->stream = value == -1 ? p->own_stream : (hipStream_t)(intptr_t)value;
@@ -685,6 +777,7 @@ struct Item {
   int lane = 0;  // chained mode: the graph (and stream) the item runs in
   void* fp = nullptr;  // its map footprint if its plan prunes
   bool fixed = false;  // its plan fixes the directions: fp is made at creation, not in the graph
+  void* ord = nullptr; // with fixed directions, the gather's pixel order (made at creation)
 };
 
 // Interleave the roles' workgroups in proportion to their counts (largest-deficit
@@ -723,7 +816,7 @@ int enqueue_group(const Group& gr, int mode, const uint32_t* dsched, hipStream_t
       if (it.fp && !it.fixed)
         if (int rc = enqueue_footprint(it.plan, it.fp, it.r, it.dirs, it.n_pix, s)) return rc;
       if (int rc = enqueue_field(it.plan, it.seed, buf, s, it.fp)) return rc;
-      if (int rc = enqueue_gather(it.plan, buf, it.r, it.dirs, it.n_pix, it.out, s)) return rc;
+      if (int rc = enqueue_gather(it.plan, buf, it.r, it.dirs, it.n_pix, it.out, s, it.ord)) return rc;
     }
     return CMBX_OK;
   }
@@ -763,6 +856,40 @@ int make_fixed_footprints(const std::vector<Group>& groups) {
   (void)hipStreamDestroy(st);
   if (rc != CMBX_OK) return rc;
   if (e != hipSuccess) return fail(CMBX_EHIP, "fixed footprints: %s", hipGetErrorString(e));
+  return CMBX_OK;
+}
+
+// The pixel orders of the items whose plans fix the directions (chained mode's gathers
+// read them), made on a stream of their own in one shared work space and waited for.
+int make_fixed_orders(const std::vector<Group>& groups) {
+  size_t sb = 0;
+  for (const Group& gr : groups)
+    for (const Item& it : gr.items)
+      if (it.ord) {
+        size_t b = 0;
+        HIP_TRY(cmbx::pixel_order_scratch_bytes(it.plan->N, it.n_pix, &b));
+        sb = std::max(sb, b);
+      }
+  if (sb == 0) return CMBX_OK;
+  void* scratch = nullptr;
+  hipError_t e = hipMalloc(&scratch, sb);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "pixel orders: %s", hipGetErrorString(e));
+  hipStream_t st = nullptr;
+  e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  int rc = CMBX_OK;
+  for (const Group& gr : groups)
+    for (const Item& it : gr.items)
+      if (e == hipSuccess && rc == CMBX_OK && it.ord)
+        rc = enqueue_pixel_order(it.plan, it.ord, scratch, sb, it.r, it.dirs, it.n_pix, st);
+  if (st) {
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = es;
+    (void)hipStreamDestroy(st);
+  }
+  (void)hipFree(scratch);
+  if (rc != CMBX_OK) return rc;
+  if (e != hipSuccess) return fail(CMBX_EHIP, "pixel orders: %s", hipGetErrorString(e));
   return CMBX_OK;
 }
 
@@ -992,8 +1119,20 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
       it.fp = f;
       it.fixed = it.plan->fixed_dirs;
     }
-  // fixed footprints are valid before any launch (the timing launches of auto mode included)
+  // with fixed directions, a pixel order per realisation for the chained gathers
+  for (Group& gr : groups)
+    for (Item& it : gr.items) {
+      if (!it.plan->fixed_dirs) continue;
+      void* o = nullptr;
+      const hipError_t e = hipMalloc(&o, cmbx::pixel_order_bytes(it.plan->dtype, it.n_pix));
+      if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? CMBX_ENOMEM : CMBX_EHIP, "ensemble pixel orders");
+      en->fps.push_back(o);
+      it.ord = o;
+    }
+  // fixed footprints and orders are valid before any launch (the timing launches of auto
+  // mode included)
   if (int rc = make_fixed_footprints(groups)) return bail(rc, cmbx::err_msg());
+  if (int rc = make_fixed_orders(groups)) return bail(rc, cmbx::err_msg());
   std::vector<uint32_t> sched;
   if (mode != CMBX_ENS_CHAINED) {
     for (Group& gr : groups) {
@@ -1213,6 +1352,9 @@ int cmbx_time_passes(cmbx_plan* p, uint64_t seed, double r, const double* dirs, 
     if (int rc = enqueue_footprint(p, p->fp, r, dirs, n_pix, p->stream)) return rc;
     a.fp = p->fp;
   }
+  // and the gather in the pixel order if the plan fixes the directions
+  const void* order = nullptr;
+  if (int rc = plan_pixel_order(p, r, dirs, n_pix, p->stream, &order)) return rc;
   // per kernel: one untimed launch, then the timed ones between two events; the first
   // timed launch is queued while the untimed one runs, so the host's submission delay
   // after an event is not counted as kernel time
@@ -1221,7 +1363,7 @@ int cmbx_time_passes(cmbx_plan* p, uint64_t seed, double r, const double* dirs, 
   int rc = CMBX_OK;
   hipError_t e = hipSuccess;
   auto launch = [&](int k) -> int {
-    if (k == 3) return enqueue_gather(p, p->field, r, dirs, n_pix, out, p->stream);
+    if (k == 3) return enqueue_gather(p, p->field, r, dirs, n_pix, out, p->stream, order);
     const hipError_t he = k == 0 ? cmbx::launch_pass_x(a, p->stream)
                           : k == 1 ? cmbx::launch_pass_y(a, p->stream)
                                    : cmbx::launch_pass_z(a, p->stream);

@@ -801,6 +801,156 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ field, int
   gather_pixel<T, K>(field, N, scale, obs, r, dirs, i, out);
 }
 
+// ------------------------------------------------------------------ pixel order
+// A record of the pixel order: the stencil's first node wrapped into the box, packed
+// x << 20 | y << 10 | z (N <= 1024), and the fractions rounded to T as the gather rounds
+// them. With the node wrapped, the z taps are contiguous exactly when z + K <= N (a first
+// node at -1 wraps to N - 1), and the taps wrap to the same nodes.
+template <typename T>
+struct alignas(16) OrderRec {
+  uint32_t node;
+  T f[3];
+};
+static_assert(sizeof(OrderRec<float>) == 16 && sizeof(OrderRec<double>) == 32, "record sizes");
+
+size_t pixel_order_record_bytes(int dtype) {
+  return dtype == kF32 ? sizeof(OrderRec<float>) : sizeof(OrderRec<double>);
+}
+
+size_t pixel_order_bytes(int dtype, int64_t n_pix) {
+  return (size_t)n_pix * (pixel_order_record_bytes(dtype) + sizeof(uint32_t));
+}
+
+__device__ __forceinline__ uint32_t spread3_10(uint32_t v) {
+  uint32_t k = 0;
+  for (int b = 0; b < 10; ++b) k |= ((v >> b) & 1u) << (3 * b);
+  return k;
+}
+
+template <int K>
+__device__ __forceinline__ void wrapped_node(int N, double scale, double3 obs, double r, const double* __restrict__ dirs,
+                                             int64_t i, uint32_t c[3], double frac[3]) {
+  int i0[3];
+  stencil_origin<K>(N, scale, obs, r, dirs, i, i0, frac);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) c[d] = (uint32_t)wrap(i0[d], N);
+}
+
+// Key: the Morton code of the wrapped first node (x in the highest bit of each triple).
+template <int K>
+__global__ __launch_bounds__(256) void k_order_keys(int N, double scale, double3 obs, double r,
+                                                    const double* __restrict__ dirs, int64_t npix,
+                                                    uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  uint32_t c[3];
+  double frac[3];
+  wrapped_node<K>(N, scale, obs, r, dirs, i, c, frac);
+  key[i] = (spread3_10(c[0]) << 2) | (spread3_10(c[1]) << 1) | spread3_10(c[2]);
+  val[i] = (uint32_t)i;
+}
+
+// The records in sorted order.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_order_records(int N, double scale, double3 obs, double r,
+                                                       const double* __restrict__ dirs, int64_t npix,
+                                                       const uint32_t* __restrict__ sorted, OrderRec<T>* __restrict__ rec,
+                                                       uint32_t* __restrict__ pix) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= npix) return;
+  const uint32_t i = sorted[j];
+  uint32_t c[3];
+  double frac[3];
+  wrapped_node<K>(N, scale, obs, r, dirs, i, c, frac);
+  OrderRec<T> o;
+  o.node = (c[0] << 20) | (c[1] << 10) | c[2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) o.f[d] = (T)frac[d];
+  rec[j] = o;
+  pix[j] = i;
+}
+
+// The gather in pixel order: thread j makes pixel pix[j] from record j, with the weights
+// and the tap sum of gather_pixel.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_gather_ordered(const T* __restrict__ field, int N,
+                                                        const OrderRec<T>* __restrict__ rec,
+                                                        const uint32_t* __restrict__ pix, int64_t npix,
+                                                        T* __restrict__ out) {
+  const int nb = gridDim.x;
+  const int per = nb / 8;
+  const int b = blockIdx.x;
+  const int logical = (nb % 8 == 0) ? (b % 8) * per + b / 8 : b;
+  const int64_t j = (int64_t)logical * blockDim.x + threadIdx.x;
+  if (j >= npix) return;
+  const OrderRec<T> o = rec[j];
+  const uint32_t p = pix[j];
+  const int i0[3] = {(int)(o.node >> 20), (int)((o.node >> 10) & 1023u), (int)(o.node & 1023u)};
+  T w[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) weights1d<T>(o.f[d], w[d], K == 4 ? kTricubic : kTrilinear);
+  if (i0[2] + K <= N)
+    out[p] = stencil_sum<T, K, true>(field, N, i0, w);
+  else
+    out[p] = stencil_sum<T, K, false>(field, N, i0, w);
+}
+
+// Bits of the Morton key: 3 per level of the node coordinates in [0, N).
+int order_key_bits(int N) {
+  int bits = 0;
+  while ((1 << (bits / 3)) < N) bits += 3;
+  return bits;
+}
+
+hipError_t pixel_order_scratch_bytes(int N, int64_t n_pix, size_t* bytes) {
+  size_t tmp = 0;
+  const hipError_t e =
+      sort_pairs_u32(nullptr, &tmp, nullptr, nullptr, nullptr, nullptr, n_pix, order_key_bits(N), nullptr);
+  if (e != hipSuccess) return e;
+  const size_t kv = ((size_t)n_pix * 16 + 255) / 256 * 256;
+  *bytes = kv + tmp;
+  return hipSuccess;
+}
+
+hipError_t launch_pixel_order(const PixelOrderArgs& a, hipStream_t s) {
+  if (a.N > 1024 || a.n_pix < 1 || a.n_pix > ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const size_t n = (size_t)a.n_pix;
+  const size_t kv = (n * 16 + 255) / 256 * 256;
+  if (a.scratch_bytes < kv) return hipErrorInvalidValue;
+  uint32_t* k_in = (uint32_t*)a.scratch;
+  uint32_t* k_out = k_in + n;
+  uint32_t* v_in = k_out + n;
+  uint32_t* v_out = v_in + n;
+  void* tmp = (char*)a.scratch + kv;
+  size_t tmp_bytes = a.scratch_bytes - kv;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  const double3 obs = make_double3(a.obs[0], a.obs[1], a.obs[2]);
+  const bool cubic = a.interp == kTricubic;
+  auto kk = cubic ? k_order_keys<4> : k_order_keys<2>;
+  hipLaunchKernelGGL(kk, grid, dim3(256), 0, s, a.N, a.scale, obs, a.r, a.dirs, a.n_pix, k_in, v_in);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int bits = order_key_bits(a.N);
+  size_t need = 0;
+  e = sort_pairs_u32(nullptr, &need, k_in, k_out, v_in, v_out, a.n_pix, bits, s);
+  if (e != hipSuccess) return e;
+  if (need > tmp_bytes) return hipErrorInvalidValue;
+  e = sort_pairs_u32(tmp, &tmp_bytes, k_in, k_out, v_in, v_out, a.n_pix, bits, s);
+  if (e != hipSuccess) return e;
+  char* rec = (char*)a.order;
+  uint32_t* pix = (uint32_t*)(rec + n * pixel_order_record_bytes(a.dtype));
+  if (a.dtype == kF32) {
+    auto k = cubic ? k_order_records<float, 4> : k_order_records<float, 2>;
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, a.N, a.scale, obs, a.r, a.dirs, a.n_pix, v_out,
+                       (OrderRec<float>*)rec, pix);
+  } else {
+    auto k = cubic ? k_order_records<double, 4> : k_order_records<double, 2>;
+    hipLaunchKernelGGL(k, grid, dim3(256), 0, s, a.N, a.scale, obs, a.r, a.dirs, a.n_pix, v_out,
+                       (OrderRec<double>*)rec, pix);
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ map footprint
 // Mark what the K-point stencils of the pixels read: the 8-row block of line (ix, iy)
 // and the 32-node z block (the x-planes are flagged from the row blocks afterwards, by
@@ -1365,6 +1515,21 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
   nb = (nb + 7) / 8 * 8;
   const dim3 grid((unsigned)nb);
   const bool cubic = a.interp == kTricubic;
+  if (a.order) {
+    const size_t n = (size_t)a.n_pix;
+    const char* rec = (const char*)a.order;
+    const uint32_t* pix = (const uint32_t*)(rec + n * pixel_order_record_bytes(a.dtype));
+    if (a.dtype == kF32) {
+      auto k = cubic ? k_gather_ordered<float, 4> : k_gather_ordered<float, 2>;
+      hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const float*)a.field, a.N, (const OrderRec<float>*)rec, pix,
+                         a.n_pix, (float*)a.out);
+    } else {
+      auto k = cubic ? k_gather_ordered<double, 4> : k_gather_ordered<double, 2>;
+      hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const double*)a.field, a.N, (const OrderRec<double>*)rec, pix,
+                         a.n_pix, (double*)a.out);
+    }
+    return hipGetLastError();
+  }
   if (a.dtype == kF32) {
     auto k = cubic ? k_gather<float, 4> : k_gather<float, 2>;
     hipLaunchKernelGGL(k, grid, dim3(256), 0, s, (const float*)a.field, a.N, a.scale, make_double3(a.obs[0], a.obs[1], a.obs[2]), a.r, a.dirs, a.n_pix,

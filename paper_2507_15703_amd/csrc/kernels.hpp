@@ -102,8 +102,34 @@ struct GatherArgs {
   const double* dirs;  // [n_pix][3]
   int64_t n_pix;
   void* out;           // [n_pix]
+  const void* order = nullptr;  // the pixel order of (r, dirs) if made (dirs are then not read)
 };
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
+
+// Pixel order of a map whose directions stay fixed: the pixels sorted by the Morton code
+// of their stencil's first node (wrapped into the box), each with that node and its
+// fractions, so that the threads of a gather wave read the same few field lines. The same
+// integer decisions and fractions as the gather's own (stencil_origin), so a map gathered
+// in this order is bit-identical. Layout: n_pix records of pixel_order_record_bytes(dtype)
+// (packed node x << 20 | y << 10 | z, then the three fractions in the plan's precision),
+// then n_pix uint32 pixel indices.
+size_t pixel_order_record_bytes(int dtype);
+size_t pixel_order_bytes(int dtype, int64_t n_pix);
+// Work space of launch_pixel_order (keys and values to sort and the sort's own storage).
+hipError_t pixel_order_scratch_bytes(int N, int64_t n_pix, size_t* bytes);
+struct PixelOrderArgs {
+  int dtype, interp, N;
+  double scale, obs[3], r;
+  const double* dirs;
+  int64_t n_pix;
+  void* order;    // pixel_order_bytes(dtype, n_pix)
+  void* scratch;  // pixel_order_scratch_bytes(N, n_pix), 256-byte aligned
+  size_t scratch_bytes;
+};
+hipError_t launch_pixel_order(const PixelOrderArgs& a, hipStream_t s);
+// Stable sort of n (key, value) pairs by the low `bits` bits of the keys (pixel_order.hip).
+hipError_t sort_pairs_u32(void* tmp, size_t* tmp_bytes, const uint32_t* keys_in, uint32_t* keys_out,
+                          const uint32_t* vals_in, uint32_t* vals_out, int64_t n, int bits, hipStream_t s);
 
 // HEALPix RING pixel centres of the polar cap: the number of pixels in the rings with
 // z >= z_min (host only), and their unit directions, [count][3] FP64, for resolution n.

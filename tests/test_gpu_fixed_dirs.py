@@ -1,7 +1,8 @@
 """CMBX_OPT_FIXED_DIRS: a pruning plan (and an ensemble made from it) makes the map footprint
 once for directions that stay the same, and the maps are bit-identical to the maps of a plan
 that remakes it at every call; new directions (another tensor, or the option set again
-after overwriting the same tensor) rebuild it."""
+after overwriting the same tensor) rebuild it. With the option the chained gather also runs
+in the pixel order, bit-identical too."""
 import numpy as np
 import pytest
 
@@ -93,3 +94,40 @@ def test_ensemble_with_fixed_directions(cmbx, mode):
     ep.close()
     for j in jobs_f + jobs_p:
         j["plan"].close()
+
+
+@pytest.mark.parametrize("dt,interp,prune", [("f32", "tricubic", True), ("f64", "tricubic", True),
+                                             ("f32", "trilinear", True), ("f64", "trilinear", False)])
+def test_pixel_order_with_wrapping_stencils(cmbx, dt, interp, prune):
+    """With fixed directions the chained gather runs in the pixel order (the pixels sorted by
+    their stencils' first node): bit-identical maps, here with the observer near a corner of
+    the box so that stencils wrap in x and in z (the taps read one by one), several
+    realisations per plan, and one plan without the footprint (order only)."""
+    jobs_f, jobs_p, plans = [], [], []
+    for i, (N, th, obs) in enumerate([(48, 25.0, (0.97, 0.5, 0.58)), (64, 30.0, (0.5, 0.02, 0.56))]):
+        fixed, plain = _pair(cmbx, N, dt, interp)
+        for p in (fixed, plain):
+            p.set_observer(obs)
+            p.set_prune(prune)
+        plans += [fixed, plain]
+        dirs = torch.tensor(workloads.cap_directions(th, 24, 72), device="cuda")
+        for plan, lst in ((fixed, jobs_f), (plain, jobs_p)):
+            for k in range(2):
+                out = torch.empty((1, dirs.shape[0]), dtype=plan.torch_dtype, device="cuda")
+                lst.append(dict(plan=plan, seed=300 + 7 * i + k, r=0.45, dirs=dirs, out=out))
+    ef = cmbx.Ensemble(jobs_f, mode="chained")
+    ep = cmbx.Ensemble(jobs_p, mode="chained")
+    for rep in range(2):
+        for j in jobs_f + jobs_p:
+            j["out"].fill_(float("nan"))
+        ef.launch()
+        ep.launch()
+        torch.cuda.synchronize()
+        for a, b in zip(jobs_f, jobs_p):
+            x, y = a["out"].cpu().numpy(), b["out"].cpu().numpy()
+            assert np.isfinite(x).all()
+            assert np.array_equal(_bits(x), _bits(y)), (dt, interp, prune, rep)
+    ef.close()
+    ep.close()
+    for p in plans:
+        p.close()

@@ -2,8 +2,9 @@
 
 * The benchmark's launch configuration: the four 512^3 FP32 boxes of the mixed-size
   ensemble, each with the programme's spectrum for its cap (Sec. II B), tricubic, maps
-  pruned to their footprint, tiles tuned on each map's pixels, run as one chained
-  ensemble on four lanes; every pixel of every map against the oracle, on two replays.
+  pruned to their footprint, fixed directions, tiles tuned on each map's pixels, run as
+  one chained ensemble on four lanes; every pixel of every map against the oracle, on two
+  replays.
 * 384^3 (radix-3 transform lengths at size), FP32 and FP64, every pixel.
 * The flat-box methods at the benchmark's size (N = 512, M = 32, h = 14): the 2-D (hybrid)
   method and the 3-D method on the flat box, every pixel of a HEALPix cap.
@@ -70,7 +71,8 @@ def _oracle_map(N, seed, k, p, r, dirs, interp):
 
 def test_bench_ensemble_512_every_pixel(cmbx):
     """The 4 x 512^3 FP32 benchmark ensemble (chained, four lanes, LP spectra, pruned,
-    patch-tuned tiles): every pixel of every map within 1e-5 of the FP64 oracle."""
+    patch-tuned tiles, fixed directions: footprints made once and the gathers in pixel
+    order): every pixel of every map within 1e-5 of the FP64 oracle."""
     meta = [j for j in workloads.ensemble_jobs() if j["N"] == 512]
     assert len(meta) == 4
     jobs, dirs_np, tables = [], [], []
@@ -80,6 +82,7 @@ def test_bench_ensemble_512_every_pixel(cmbx):
         tables.append((k, p))
         plan = cmbx.Plan(512, 1.0, "f32", batch=1, interp="tricubic")
         plan.spectrum_table(k, p)
+        plan.set_fixed_dirs(True)
         d_np = workloads.cap_directions(j["theta_deg"], j["n_ring"], j["n_phi"])
         dirs_np.append(d_np)
         dirs = torch.tensor(d_np, device="cuda")
