@@ -198,12 +198,12 @@ __device__ __forceinline__ void stage_inputs(Src& src, cpx<T> (&v)[StageSlots<L,
   using SS = StageSlots<L, NSEQ, NT, R>;
 #pragma unroll
   for (int q = 0; q < SS::PER; ++q) {
-    const int s = tid + q * NT;
-    if (SS::FULL || s < SS::SLOTS) {
-      const int seq = SEQFAST ? s % NSEQ : s / SS::J;
-      const int j = SEQFAST ? s / NSEQ : s % SS::J;
+    const unsigned s = (unsigned)tid + q * NT;
+    if (SS::FULL || s < (unsigned)SS::SLOTS) {
+      const unsigned seq = SEQFAST ? s % NSEQ : s / SS::J;
+      const unsigned j = SEQFAST ? s / NSEQ : s % SS::J;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src(seq, j + r * SS::J);
+      for (int r = 0; r < R; ++r) v[q][r] = src((int)seq, (int)(j + r * SS::J));
     }
   }
 }
@@ -215,19 +215,19 @@ __device__ __forceinline__ void stage_outputs(const cpx<T>* __restrict__ tw,
   using SS = StageSlots<L, NSEQ, NT, R>;
 #pragma unroll
   for (int q = 0; q < SS::PER; ++q) {
-    const int s = tid + q * NT;
-    if (SS::FULL || s < SS::SLOTS) {
-      const int seq = SEQFAST ? s % NSEQ : s / SS::J;
-      const int j = SEQFAST ? s / NSEQ : s % SS::J;
-      const int k = j % NS;
+    const unsigned s = (unsigned)tid + q * NT;
+    if (SS::FULL || s < (unsigned)SS::SLOTS) {
+      const unsigned seq = SEQFAST ? s % NSEQ : s / SS::J;
+      const unsigned j = SEQFAST ? s / NSEQ : s % SS::J;
+      const unsigned k = j % NS;
       if (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * (L / (NS * R)) * TWMUL]);
       }
       Dft<T, R>::run(v[q]);
-      const int base = (j / NS) * NS * R + k;
+      const unsigned base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst(seq, base + r * NS, v[q][r]);
+      for (int r = 0; r < R; ++r) dst((int)seq, (int)(base + r * NS), v[q][r]);
     }
   }
   dst.done();
@@ -242,32 +242,34 @@ __device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ tw, Src& sr
   constexpr int PER = (SLOTS + NT - 1) / NT;
   constexpr bool FULL = (SLOTS % NT) == 0;
   cpx<T> v[PER][R];
+  // slot arithmetic unsigned: the thread index is not known to the compiler to be
+  // non-negative, and signed division by the (power-of-two) constants costs fix-ups
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int s = tid + q * NT;
-    if (FULL || s < SLOTS) {
-      const int seq = SEQFAST ? s % NSEQ : s / J;
-      const int j = SEQFAST ? s / NSEQ : s % J;
+    const unsigned s = (unsigned)tid + q * NT;
+    if (FULL || s < (unsigned)SLOTS) {
+      const unsigned seq = SEQFAST ? s % NSEQ : s / J;
+      const unsigned j = SEQFAST ? s / NSEQ : s % J;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src(seq, j + r * J);
+      for (int r = 0; r < R; ++r) v[q][r] = src((int)seq, (int)(j + r * J));
     }
   }
   src.done();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int s = tid + q * NT;
-    if (FULL || s < SLOTS) {
-      const int seq = SEQFAST ? s % NSEQ : s / J;
-      const int j = SEQFAST ? s / NSEQ : s % J;
-      const int k = j % NS;
+    const unsigned s = (unsigned)tid + q * NT;
+    if (FULL || s < (unsigned)SLOTS) {
+      const unsigned seq = SEQFAST ? s % NSEQ : s / J;
+      const unsigned j = SEQFAST ? s / NSEQ : s % J;
+      const unsigned k = j % NS;
       if (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * (L / (NS * R)) * TWMUL]);
       }
       Dft<T, R>::run(v[q]);
-      const int base = (j / NS) * NS * R + k;
+      const unsigned base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst(seq, base + r * NS, v[q][r]);
+      for (int r = 0; r < R; ++r) dst((int)seq, (int)(base + r * NS), v[q][r]);
     }
   }
   dst.done();

@@ -214,6 +214,15 @@ __device__ __forceinline__ int isqrt_floor(int d) {
   return s;
 }
 
+// floor(sqrt(d)) for 0 <= d < 2^22: the hardware square root is within an ulp of the
+// root (below 2048), so the truncated value is off by at most one either way.
+__device__ __forceinline__ int isqrt_small(int d) {
+  int s = (int)__builtin_amdgcn_sqrtf((float)d);
+  s -= s * s > d ? 1 : 0;
+  s += (s + 1) * (s + 1) <= d ? 1 : 0;
+  return s;
+}
+
 // Tiles of the x pass within the spectrum's support: z tile zt holds modes of nonzero
 // weight only for rows with fy^2 + (zt TZ)^2 <= m_hi, i.e. |fy| <= R(zt): the rows
 // 0 .. R and N - R .. N - 1, min(N, 2R + 1) of them (none if (zt TZ)^2 > m_hi).
@@ -264,28 +273,87 @@ struct SupportColIO {
   __device__ __forceinline__ void done() const { g.done(); }
 };
 
+// Raw buffer resource over `bytes` bytes at p (gfx9 descriptor word 3: 32-bit data
+// format). Loads at an offset at or past `bytes` return zero without a memory access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> buffer_load_cpx(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+  else return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+}
+
+// The same reader as SupportColIO for the column tile at zc0 of one plane, through a
+// buffer resource on the plane: an element beyond the support is read at an offset past
+// the plane (zero, no memory access) instead of under a branch, and the offsets are 32
+// bits. The support test takes the row bound R of the thread's column (|fy| <= R, the
+// floor root of m_hi - zc^2, -1 if that is negative), made once: every call of a thread
+// is for its own column q = tid % TZ (column-fast tiles whose thread count is a multiple
+// of TZ).
+template <typename T, int N>
+struct SupportBufCol {
+  static constexpr int M = N / 2;
+  __amdgpu_buffer_rsrc_t rs;
+  int zc0, R;
+  __device__ __forceinline__ SupportBufCol(const cpx<T>* plane, int zc0_, int m_hi, int q) : zc0(zc0_) {
+    rs = buffer_rsrc(plane, (uint32_t)(N * M * sizeof(cpx<T>)));
+    const int zc = zc0 + q;
+    const int d = m_hi - zc * zc;  // (m_hi may be INT_MAX: no support bound)
+    R = d < 0 ? -1 : d >= M * M ? M : isqrt_small(d);
+  }
+  __device__ __forceinline__ cpx<T> operator()(int q, int n) const {
+    bool in;
+    if constexpr ((N & (N - 1)) == 0) in = (int)((unsigned)(n + R) & (N - 1)) <= 2 * R;
+    else in = n <= R || n >= N - R;
+    const uint32_t off = in ? (uint32_t)(n * M + zc0 + q) * (uint32_t)sizeof(cpx<T>) : 0x80000000u;
+    return buffer_load_cpx<T>(rs, off);
+  }
+  // the tile is read and written in place, so all reads must finish before any write
+  __device__ __forceinline__ void done() const { __syncthreads(); }
+};
+
 // With a map footprint `fp`, x-planes that no stencil reads are skipped, and of the
 // others only the 8-row blocks that some stencil reads are written.
 template <typename T, int N, int TZ, int NT, int P = 0>
 __device__ __forceinline__ void role_y(cpx<T>* smem, int zt, int ix, cpx<T>* __restrict__ buf,
-                                       const cpx<T>* __restrict__ twg, int m_hi, const uint8_t* __restrict__ fp) {
+                                       const cpx<T>* __restrict__ twg, int m_hi, const uint8_t* __restrict__ fp,
+                                       bool load_tw = true) {
   constexpr int M = N / 2;
   constexpr int NB = footprint_blocks(N);
   cpx<T>* tile = smem;
   cpx<T>* tw = smem + N * TZ;
+  const int tid = opaque_tid();
+  // (the thread index is opaque: a loop over it is not reduced to one step by itself)
+  if (load_tw) {
+    if constexpr (N <= NT) {
+      if (tid < N) tw[tid] = twg[tid];
+    } else {
+      for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+    }
+  }
   // columns wholly beyond the support stay zero through pass y; pass z does not read them
   if (zt * TZ * zt * TZ > m_hi) return;
   if (fp && !fp[ix]) return;
-  const int tid = opaque_tid();
   __shared__ uint8_t rows[NB];
-  if (fp)
-    for (int i = tid; i < NB; i += NT) rows[i] = fp[N + ix * NB + i];
-  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  if (fp) {
+    if constexpr (NB <= NT) {
+      if (tid < NB) rows[tid] = fp[N + ix * NB + tid];
+    } else {
+      for (int i = tid; i < NB; i += NT) rows[i] = fp[N + ix * NB + i];
+    }
+  }
   __syncthreads();
   GlobalColIO<T> io{buf + (size_t)ix * N * M + zt * TZ, (size_t)M};
-  SupportColIO<T, N> first{io, zt * TZ, m_hi};
   KeptRowsColIO<T, 3> last{io, fp ? rows : nullptr};
-  fft_run<T, N, TZ, NT, true, 1, 0, SupportColIO<T, N>, KeptRowsColIO<T, 3>, P>(tw, tile, first, last, tid);
+  if constexpr (NT % TZ == 0) {
+    SupportBufCol<T, N> first(buf + (size_t)ix * N * M, zt * TZ, m_hi, (int)((unsigned)tid % TZ));
+    fft_run<T, N, TZ, NT, true, 1, 0, SupportBufCol<T, N>, KeptRowsColIO<T, 3>, P>(tw, tile, first, last, tid);
+  } else {
+    SupportColIO<T, N> first{io, zt * TZ, m_hi};
+    fft_run<T, N, TZ, NT, true, 1, 0, SupportColIO<T, N>, KeptRowsColIO<T, 3>, P>(tw, tile, first, last, tid);
+  }
 }
 
 // ------------------------------------------------------------------ pass 3: z (c2r)
@@ -417,7 +485,8 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_y(cpx<T>* __re
   }
   for (int e = e0; e < count; e += step) {
     const int zt = e % tiles, ix = plist ? (int)plist[e / tiles] : e / tiles;
-    role_y<T, N, TZ, XYShape<T, N, TZ>::NT, P>(smem, zt, ix, buf, twg, m_hi, fp);
+    // the twiddles stay in LDS from one pair to the next (the tile lies below them)
+    role_y<T, N, TZ, XYShape<T, N, TZ>::NT, P>(smem, zt, ix, buf, twg, m_hi, fp, e == e0);
     __syncthreads();  // the tile is reused by the next pair
   }
 }
@@ -448,8 +517,13 @@ __device__ __forceinline__ void y_walk_load(cpx<T>* __restrict__ buf, const uint
                                             int e, typename YWalk<T, N, TZ, P>::Regs& v, int tid) {
   constexpr int M = N / 2;
   const int zt = e % tiles, ix = (int)plist[e / tiles];
-  SupportColIO<T, N> src{{buf + (size_t)ix * N * M + zt * TZ, (size_t)M}, zt * TZ, m_hi};
-  stage_inputs<T, N, TZ, YWalk<T, N, TZ, P>::NT, YWalk<T, N, TZ, P>::R0, true>(src, v, tid);
+  if constexpr (YWalk<T, N, TZ, P>::NT % TZ == 0) {
+    SupportBufCol<T, N> src(buf + (size_t)ix * N * M, zt * TZ, m_hi, (int)((unsigned)tid % TZ));
+    stage_inputs<T, N, TZ, YWalk<T, N, TZ, P>::NT, YWalk<T, N, TZ, P>::R0, true>(src, v, tid);
+  } else {
+    SupportColIO<T, N> src{{buf + (size_t)ix * N * M + zt * TZ, (size_t)M}, zt * TZ, m_hi};
+    stage_inputs<T, N, TZ, YWalk<T, N, TZ, P>::NT, YWalk<T, N, TZ, P>::R0, true>(src, v, tid);
+  }
 }
 
 // One pair on `cur` (loaded by the previous turn) while the next pair loads into `nxt`;

@@ -377,7 +377,8 @@ def test_autotune_on_a_maps_pixels(cmbx):
     t = p.autotune(reps=2, r=0.45, dirs=dirs)
     assert not t["cached"] and t["tile_x"] in cmbx.tile_choices("f32", N, 0)
     assert t["lines_z"] in cmbx.tile_choices("f32", N, 1) and all(m > 0 for m in t["ms"])
-    w.set_tiles(0, t["lines_z"], tile_x=t["tile_x"], tile_y=t["tile_y"])
+    # the same stage plans too: a plan 1 transform rounds differently from plan 0
+    w.set_tiles(0, t["lines_z"], tile_x=t["tile_x"], tile_y=t["tile_y"], plans=t["plans"])
     a = p.simulate_patch(8, 0.45, dirs).cpu().numpy()
     b = w.simulate_patch(8, 0.45, dirs).cpu().numpy()
     assert np.array_equal(_bits(a), _bits(b))
