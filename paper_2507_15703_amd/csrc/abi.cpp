@@ -1250,32 +1250,39 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
         if (got == want && !(m == &all_chained && want == 1)) cands.push_back({*m, want});
       }
     }
-    // four sweeps over every candidate, each keeping its best time: the candidates are a
-    // few percent apart, as much as the clock drifts over a sweep (re-timing only the two
-    // fastest of the first sweep had kept a candidate that lost by 5 % in steady state)
-    std::vector<double> tc(cands.size(), 1e300);
+    // six sweeps over every candidate, in alternating order, each candidate scored by the
+    // median of its six times: the candidates are a few percent apart, as much as the clock
+    // drifts over a sweep, and a best-of-sweeps score favoured the candidates of widest
+    // spread (more lanes: four had timed level with two and then ran 5-7 % slower in steady
+    // state; re-timing only the two fastest of the first sweep had kept a candidate that
+    // lost by 5 %)
+    constexpr int kSweeps = 6;
+    std::vector<std::vector<double>> ts(cands.size());
     auto time_cand = [&](size_t c) -> int {
       set_modes(cands[c].modes, cands[c].lanes);
       clear_lanes(en);
       if (int rc = build_lanes(en, groups, dsched, cands[c].lanes)) return rc;
       const double t = time_ensemble(en);
       if (t < 0) return fail(CMBX_EHIP, "ensemble timing failed");
-      tc[c] = std::min(tc[c], t);
+      ts[c].push_back(t);
       return CMBX_OK;
     };
     size_t best = 0;
     if (cands.size() > 1) {
-      for (int round = 0; round < 4; ++round)
+      for (int round = 0; round < kSweeps; ++round)
         for (size_t c = 0; c < cands.size(); ++c)
           if (int rc = time_cand(round % 2 ? cands.size() - 1 - c : c)) return bail(rc, cmbx::err_msg());
+      std::vector<double> tc(cands.size());
+      for (size_t c = 0; c < cands.size(); ++c) {
+        std::sort(ts[c].begin(), ts[c].end());
+        tc[c] = 0.5 * (ts[c][kSweeps / 2 - 1] + ts[c][kSweeps / 2]);
+      }
       for (size_t c = 1; c < cands.size(); ++c)
         if (tc[c] < tc[best]) best = c;
-      // within 2 % of the fastest (about the spread of one candidate's timings) the fewest
-      // lanes win: at creation four lanes had timed level with two and then ran 5-7 %
-      // slower in steady state
+      // within 1 % of the fastest the fewest lanes win
       const double fastest = tc[best];
       for (size_t c = 0; c < cands.size(); ++c)
-        if (tc[c] <= 1.02 * fastest && cands[c].lanes < cands[best].lanes) best = c;
+        if (tc[c] <= 1.01 * fastest && cands[c].lanes < cands[best].lanes) best = c;
     }
     set_modes(cands[best].modes, cands[best].lanes);
     clear_lanes(en);
