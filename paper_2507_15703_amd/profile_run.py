@@ -3,7 +3,8 @@
 Runs, on one FP32 plan of the benchmark's first 512^3 box (tricubic, r = 0.45 L, its cap
 of 26.9 deg and 687 x 2048 pixels, its spectrum: the programme's solution for the synthetic
 C_l on that cap, ``spectrum.synthetic_job_spectrum``; the power-law table with
-``--spectrum powerlaw``; autotuned tile shapes unless given), with its seed: one
+``--spectrum powerlaw``; autotuned tile shapes unless given; directions fixed, as the
+benchmark runs them), with its seed: one
 warm-up realisation, then ``--reps`` launches of each kernel of the hot path through
 cmbx_time_passes, and a device-to-device copy of exactly 512 MiB (torch) whose counter
 readings calibrate the HBM byte counters. With ``--slab``: instead, the benchmark's
@@ -72,6 +73,7 @@ def main():
     N = args.N
     job = [j for j in workloads.ensemble_jobs() if j["N"] == 512][0]
     plan = cmbx.Plan(N, 1.0, args.dtype, batch=1, interp="tricubic")
+    plan.set_fixed_dirs(True)  # as bench.py: footprint made once, the gather in pixel order
     if args.spectrum == "lp":
         k, p = spectrum.synthetic_job_spectrum(N, 1.0, job["r_over_L"], job["theta_deg"], job["amp"])
     else:
