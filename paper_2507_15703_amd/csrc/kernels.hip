@@ -172,17 +172,26 @@ __device__ __forceinline__ void x_tile(cpx<T>* smem, int zt, int iy, cpx<T>* __r
     }
   }
   // every other pair of columns (2p, 2p + 1) holds two generic modes drawn from one
-  // Philox call
+  // Philox call. The two are neighbours in the column-fast tile (columns are its fastest
+  // index), 16-byte aligned in binary32: one 16-byte store, which also runs the lanes'
+  // stores over consecutive banks (two 8-byte stores met in pairs on a bank)
+  auto store2 = [&](int pr, int ix, cpx<T> a, cpx<T> b) {
+    cpx<T>* p = &tile[Lds::index(2 * pr, ix)];
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
+    } else {
+      p[0] = a;
+      p[1] = b;
+    }
+  };
   auto pair = [&](int pr, int ix, int zc, int m0) {
     if (m0 > m_hi) {  // both modes beyond the spectrum's support: +0, no draw, no load
-      tile[Lds::index(2 * pr, ix)] = {T(0), T(0)};
-      tile[Lds::index(2 * pr + 1, ix)] = {T(0), T(0)};
+      store2(pr, ix, {T(0), T(0)}, {T(0), T(0)});
       return;
     }
     const int m1 = m0 + 2 * zc + 1;
     const uint4 w = philox4x32_10(make_uint4((uint32_t)zc >> 1, (uint32_t)iy, (uint32_t)ix, 0u), k0, k1);
-    tile[Lds::index(2 * pr, ix)] = weighted<T>(wtab[m0], w.x, w.y, tab);
-    tile[Lds::index(2 * pr + 1, ix)] = weighted<T>(wtab[m1], w.z, w.w, tab);
+    store2(pr, ix, weighted<T>(wtab[m0], w.x, w.y, tab), weighted<T>(wtab[m1], w.z, w.w, tab));
   };
   if constexpr (NT % PAIRS == 0) {
     // a thread keeps its pair of columns over the rows it visits
@@ -430,7 +439,7 @@ __global__ __launch_bounds__((XYShape<T, N, TZ>::NT)) void k_pass_x(cpx<T>* __re
                                                                  const uint8_t* __restrict__ fp) {
   constexpr int NT = XYShape<T, N, TZ>::NT;
   constexpr int T_ = N / 2 / TZ;  // z tiles
-  __shared__ cpx<T> smem[XLds<T, N, TZ>::SIZE];
+  __shared__ __align__(16) cpx<T> smem[XLds<T, N, TZ>::SIZE];
   __shared__ uint8_t planes[N];
   __shared__ int start[T_ + 1];   // first listed tile of each z tile
   __shared__ int radius[T_];      // R(zt)
@@ -1149,7 +1158,7 @@ struct PipeShape {
 template <typename T, int N, int TX, int TY, int LZ>
 __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict__ sched, PipeArgs<T> a) {
   constexpr int M = N / 2;
-  __shared__ cpx<T> smem[PipeShape<T, N, TX, TY, LZ>::SMEM];
+  __shared__ __align__(16) cpx<T> smem[PipeShape<T, N, TX, TY, LZ>::SMEM];
   const uint32_t e = sched[blockIdx.x];
   const int role = (int)(e >> 30);
   const int idx = (int)(e & 0x3FFFFFFFu);
