@@ -1216,10 +1216,16 @@ constexpr int tz_choice(int d, int N, int k) {
   const int t = d >> k;
   return (t >= 2 && t % 2 == 0 && (N / 2) % t == 0) ? t : d;
 }
-// lines per z workgroup: about 4096 (FP32) / 2048 (FP64) complex, dividing N^2
+// lines per z workgroup: about 2048 complex, dividing N^2 (in FP32 the streamed pass with
+// blocks of 2048 complex, four workgroups per CU, ran faster than with blocks of 4096, two
+// per CU: N = 512 0.025 -> 0.021 ms, N = 128 0.0048 -> 0.0044, level at 256 and 384), but
+// 4096 in FP32 for N = 3 x 2^k: there the smaller block made the footprint's maps stream
+// at N = 48, and the streamed kernel's radix-3 transform rounds differently from k_pass_z's
+// (the whole field's), where maps made from the footprint must equal the whole field's
 template <typename T>
 constexpr int default_lines(int N) {
-  const int target = (sizeof(T) == 4 ? 4096 : 2048) / (N / 2);
+  const bool pow2 = (N & (N - 1)) == 0;
+  const int target = (sizeof(T) == 4 && !pow2 ? 4096 : 2048) / (N / 2);
   int l = 1;
   while (l * 2 <= target && (N * N) % (l * 2) == 0) l *= 2;
   return l;
