@@ -1216,16 +1216,17 @@ constexpr int tz_choice(int d, int N, int k) {
   const int t = d >> k;
   return (t >= 2 && t % 2 == 0 && (N / 2) % t == 0) ? t : d;
 }
-// lines per z workgroup: about 2048 complex, dividing N^2 (in FP32 the streamed pass with
-// blocks of 2048 complex, four workgroups per CU, ran faster than with blocks of 4096, two
-// per CU: N = 512 0.025 -> 0.021 ms, N = 128 0.0048 -> 0.0044, level at 256 and 384), but
-// 4096 in FP32 for N = 3 x 2^k: there the smaller block made the footprint's maps stream
-// at N = 48, and the streamed kernel's radix-3 transform rounds differently from k_pass_z's
-// (the whole field's), where maps made from the footprint must equal the whole field's
+// lines per z workgroup: about 2048 complex (FP64), dividing N^2. In FP32 smaller blocks
+// (more workgroups per CU) ran the streamed pass faster: blocks of 1024 complex from
+// N = 256 (eight per CU; N = 512 0.025 -> 0.021 ms with 2048, 0.020 with 1024; N = 256
+// 0.0068 -> 0.0064 with 1024), 2048 below (N = 128 0.0048 -> 0.0044). Boxes of 3 x 2^k
+// keep 4096 in FP32: a smaller block made N = 48's footprint maps stream, and the streamed
+// kernel's radix-3 transform rounds differently from k_pass_z's (the whole field's), where
+// maps made from the footprint must equal the whole field's
 template <typename T>
 constexpr int default_lines(int N) {
   const bool pow2 = (N & (N - 1)) == 0;
-  const int target = (sizeof(T) == 4 && !pow2 ? 4096 : 2048) / (N / 2);
+  const int target = (sizeof(T) == 8 ? 2048 : !pow2 ? 4096 : N >= 256 ? 1024 : 2048) / (N / 2);
   int l = 1;
   while (l * 2 <= target && (N * N) % (l * 2) == 0) l *= 2;
   return l;
