@@ -1181,6 +1181,7 @@ int cmbx_ensemble_create(const cmbx_job* jobs, int n_jobs, int mode, cmbx_ensemb
           cnt[3] = (it.n_pix + cmbx::kPipeThreads - 1) / cmbx::kPipeThreads;
           a.field_g = gr.bufs[ig % nbuf];
           a.dirs = it.dirs;
+          a.order = it.ord;
           a.out = it.out;
           a.npix = it.n_pix;
           a.r = it.r;

@@ -953,8 +953,25 @@ __global__ __launch_bounds__(256) void k_order_records(int N, double scale, doub
   pix[j] = i;
 }
 
-// The gather in pixel order: thread j makes pixel pix[j] from record j, with the weights
-// and the tap sum of gather_pixel.
+// Pixel pix[j] from record j, with the weights and the tap sum of gather_pixel.
+template <typename T, int K>
+__device__ __forceinline__ void gather_ordered_pixel(const T* __restrict__ field, int N,
+                                                     const OrderRec<T>* __restrict__ rec,
+                                                     const uint32_t* __restrict__ pix, int64_t j,
+                                                     T* __restrict__ out) {
+  const OrderRec<T> o = rec[j];
+  const uint32_t p = pix[j];
+  const int i0[3] = {(int)(o.node >> 20), (int)((o.node >> 10) & 1023u), (int)(o.node & 1023u)};
+  T w[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) weights1d<T>(o.f[d], w[d], K == 4 ? kTricubic : kTrilinear);
+  if (i0[2] + K <= N)
+    out[p] = stencil_sum<T, K, true>(field, N, i0, w);
+  else
+    out[p] = stencil_sum<T, K, false>(field, N, i0, w);
+}
+
+// The gather in pixel order: thread j makes pixel pix[j] from record j.
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_gather_ordered(const T* __restrict__ field, int N,
                                                         const OrderRec<T>* __restrict__ rec,
@@ -966,16 +983,7 @@ __global__ __launch_bounds__(256) void k_gather_ordered(const T* __restrict__ fi
   const int logical = (nb % 8 == 0) ? (b % 8) * per + b / 8 : b;
   const int64_t j = (int64_t)logical * blockDim.x + threadIdx.x;
   if (j >= npix) return;
-  const OrderRec<T> o = rec[j];
-  const uint32_t p = pix[j];
-  const int i0[3] = {(int)(o.node >> 20), (int)((o.node >> 10) & 1023u), (int)(o.node & 1023u)};
-  T w[3][4];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) weights1d<T>(o.f[d], w[d], K == 4 ? kTricubic : kTrilinear);
-  if (i0[2] + K <= N)
-    out[p] = stencil_sum<T, K, true>(field, N, i0, w);
-  else
-    out[p] = stencil_sum<T, K, false>(field, N, i0, w);
+  gather_ordered_pixel<T, K>(field, N, rec, pix, j, out);
 }
 
 // Bits of the Morton key: 3 per level of the node coordinates in [0, N).
@@ -1138,6 +1146,8 @@ struct PipeArgs {
   cpx<T>* bz;          // pass z buffer
   const T* field_g;    // gather input field
   const double* dirs;  // gather directions
+  const OrderRec<T>* rec;  // with fixed directions, the pixel order (records, indices), else NULL
+  const uint32_t* pix;
   T* out;              // gather output
   int64_t npix;
   double r, scale;
@@ -1188,10 +1198,16 @@ __global__ __launch_bounds__(kPipeNT) void k_pipeline(const uint32_t* __restrict
   } else {
     const int64_t i = (int64_t)idx * kPipeNT + threadIdx.x;
     if (i < a.npix) {
-      if (a.cubic)
+      if (a.rec) {
+        if (a.cubic)
+          gather_ordered_pixel<T, 4>(a.field_g, N, a.rec, a.pix, i, a.out);
+        else
+          gather_ordered_pixel<T, 2>(a.field_g, N, a.rec, a.pix, i, a.out);
+      } else if (a.cubic) {
         gather_pixel<T, 4>(a.field_g, N, a.scale, a.obs, a.r, a.dirs, i, a.out);
-      else
+      } else {
         gather_pixel<T, 2>(a.field_g, N, a.scale, a.obs, a.r, a.dirs, i, a.out);
+      }
     }
   }
 }
@@ -1360,6 +1376,10 @@ hipError_t run_pipe(const PipeLaunch& a, hipStream_t s) {
   p.bz = (cpx<T>*)a.bz;
   p.field_g = (const T*)a.field_g;
   p.dirs = a.dirs;
+  if (a.order) {
+    p.rec = (const OrderRec<T>*)a.order;
+    p.pix = (const uint32_t*)((const char*)a.order + (size_t)a.npix * sizeof(OrderRec<T>));
+  }
   p.out = (T*)a.out;
   p.npix = a.npix;
   p.r = a.r;

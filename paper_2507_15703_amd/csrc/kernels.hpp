@@ -160,6 +160,7 @@ struct PipeLaunch {
   void* bz;
   const void* field_g;
   const double* dirs;
+  const void* order = nullptr;  // the gather item's pixel order (pixel_order_bytes), or NULL
   void* out;
   int64_t npix;
   double r, scale;
