@@ -205,7 +205,8 @@ typedef struct cmbx_job {
  * ensemble with the per-group choice and with every group chained, on each possible
  * number of lanes up to CMBX_ENS_MAX_LANES (each candidate scored by the median of six
  * timings taken in alternating sweeps), and keeps the fastest, or among those within
- * 1 % of it the one with the fewest lanes (so it may report a group chained that was
+ * 1 % of it the one with the fewest lanes, two counting before one where two are possible
+ * (so it may report a group chained that was
  * faster pipelined alone); the explicit modes use one lane. Launches of one ensemble must be
  * ordered (one launch stream, or synchronised).
  * Buffers passed in stay caller-owned and must outlive the ensemble, and so must the
